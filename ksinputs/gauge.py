@@ -1,0 +1,158 @@
+"""Synthetic improved-staggered gauge fields.
+
+Recipe (one reading, since the paper prints no ensemble):
+
+* thin link  U = exp(i s H), H = (G + G^H)/2 minus its trace/3, G with i.i.d. CN(0,1) entries
+  (re and im ~ N(0, 1/2)); the exponential is taken through the Hermitian eigendecomposition
+  and the result is reunitarised (Gram-Schmidt of rows 0 and 1, row 2 = conj(row0 x row1)),
+  so det U = 1;
+* fat link   V = 0.9 U + 0.05 N, N with i.i.d. CN(0,1) entries (not SU(3) times a scalar);
+* Naik link  W_mu(x) = -(1/24) U_mu(x) U_mu(x+mu) U_mu(x+2mu) (unsigned U, periodic wrap);
+* staggered phases eta_0 = 1, eta_1 = (-1)^x, eta_2 = (-1)^(x+y), eta_3 = (-1)^(x+y+z) and the
+  antiperiodic time boundary are folded in: a one-link leaving t = Nt-1 and a three-link
+  starting at t >= Nt-3 cross the boundary once and pick up -1.
+
+Layout of every link array: complex128 [4][V][3][3], lexicographic site index
+i = x + Nx (y + Ny (z + Nz t)), row index before column index.
+
+Random streams: ``SeedSequence(seed).spawn(2)`` gives one stream for the G draws of U and one
+for the N draws of V; each stream is consumed in site order, then mu, then matrix entry
+(row-major), re before im.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+NAIK_COEFF = -1.0 / 24.0
+FAT_DIAG = 0.9
+FAT_NOISE = 0.05
+
+
+def lattice_volume(dims) -> int:
+    return int(np.prod([int(d) for d in dims]))
+
+
+def lattice_coords(dims):
+    """Coordinates (x, y, z, t) of every site, lexicographic order with x fastest."""
+    nx, ny, nz, nt = (int(d) for d in dims)
+    i = np.arange(nx * ny * nz * nt, dtype=np.int64)
+    return i % nx, (i // nx) % ny, (i // (nx * ny)) % nz, i // (nx * ny * nz)
+
+
+def staggered_phase(mu: int, x, y, z, t):
+    """eta_mu(x) as +-1 floats."""
+    if mu == 0:
+        return np.ones_like(x, dtype=np.float64)
+    s = (x, x + y, x + y + z)[mu - 1]
+    return 1.0 - 2.0 * (s & 1)
+
+
+def time_bc_sign(hops: int, t, nt: int):
+    """-1 where a forward hop of `hops` links from time slice t wraps past Nt-1, else +1."""
+    return np.where(t + hops >= nt, -1.0, 1.0)
+
+
+def su3_from_gaussian(g: np.ndarray, scale: float) -> np.ndarray:
+    """SU(3) matrices exp(i*scale*H) from Gaussian draws g[..., 3, 3, 2] (re, im)."""
+    G = (g[..., 0] + 1j * g[..., 1]) * np.sqrt(0.5)
+    H = 0.5 * (G + np.conj(np.swapaxes(G, -1, -2)))
+    tr = np.trace(H, axis1=-2, axis2=-1).real / 3.0
+    H = H - tr[..., None, None] * np.eye(3)
+    w, Q = np.linalg.eigh(H)
+    U = (Q * np.exp(1j * scale * w)[..., None, :]) @ np.conj(np.swapaxes(Q, -1, -2))
+    r0 = U[..., 0, :]
+    r0 = r0 / np.linalg.norm(r0, axis=-1, keepdims=True)
+    r1 = U[..., 1, :]
+    r1 = r1 - np.sum(np.conj(r0) * r1, axis=-1, keepdims=True) * r0
+    r1 = r1 / np.linalg.norm(r1, axis=-1, keepdims=True)
+    r2 = np.conj(np.cross(r0, r1))
+    return np.stack([r0, r1, r2], axis=-2)
+
+
+def random_su3(rng: np.random.Generator, n: int, scale: float) -> np.ndarray:
+    """n random SU(3) matrices drawn with the thin-link recipe."""
+    return su3_from_gaussian(rng.standard_normal((n, 3, 3, 2)), scale)
+
+
+def _chunks(V: int, chunk: int = 1 << 17):
+    for s in range(0, V, chunk):
+        yield s, min(V, s + chunk)
+
+
+def thin_links(dims, scale: float, seed: int) -> np.ndarray:
+    """Unsigned thin links U, complex128 [4][V][3][3]."""
+    V = lattice_volume(dims)
+    rng = np.random.default_rng(np.random.SeedSequence(seed).spawn(2)[0])
+    U = np.empty((4, V, 3, 3), dtype=np.complex128)
+    for s, e in _chunks(V):
+        g = rng.standard_normal((e - s, 4, 3, 3, 2))
+        U[:, s:e] = np.swapaxes(su3_from_gaussian(g, scale), 0, 1)
+    return U
+
+
+def _shift_fwd(A: np.ndarray, dims, mu: int, hops: int) -> np.ndarray:
+    """B[i] = A[i + hops*mu_hat] for a per-site array A[V, ...] (periodic wrap)."""
+    nx, ny, nz, nt = (int(d) for d in dims)
+    shaped = A.reshape((nt, nz, ny, nx) + A.shape[1:])
+    axis = 3 - mu
+    return np.roll(shaped, -hops, axis=axis).reshape(A.shape)
+
+
+def naik_from_thin(U: np.ndarray, dims) -> np.ndarray:
+    """Unsigned W_mu(x) = -(1/24) U_mu(x) U_mu(x+mu) U_mu(x+2mu)."""
+    W = np.empty_like(U)
+    for mu in range(4):
+        W[mu] = NAIK_COEFF * (U[mu] @ _shift_fwd(U[mu], dims, mu, 1) @ _shift_fwd(U[mu], dims, mu, 2))
+    return W
+
+
+def fat_and_naik(U: np.ndarray, dims, seed: int):
+    """Phase-folded fat link V and Naik link W built from the unsigned thin links U."""
+    V = lattice_volume(dims)
+    rng = np.random.default_rng(np.random.SeedSequence(seed).spawn(2)[1])
+    fat = np.empty_like(U)
+    for s, e in _chunks(V):
+        g = rng.standard_normal((e - s, 4, 3, 3, 2))
+        N = (g[..., 0] + 1j * g[..., 1]) * np.sqrt(0.5)
+        fat[:, s:e] = FAT_DIAG * U[:, s:e] + FAT_NOISE * np.swapaxes(N, 0, 1)
+    naik = naik_from_thin(U, dims)
+    fold_phases(fat, naik, dims)
+    return fat, naik
+
+
+def fold_phases(fat: np.ndarray, naik: np.ndarray, dims) -> None:
+    """Multiply eta_mu(x) and the antiperiodic-time sign into V and W in place."""
+    x, y, z, t = lattice_coords(dims)
+    nt = int(dims[3])
+    for mu in range(4):
+        eta = staggered_phase(mu, x, y, z, t)
+        s1 = eta * (time_bc_sign(1, t, nt) if mu == 3 else 1.0)
+        s3 = eta * (time_bc_sign(3, t, nt) if mu == 3 else 1.0)
+        fat[mu] *= s1[:, None, None]
+        naik[mu] *= s3[:, None, None]
+
+
+@dataclass
+class GaugeField:
+    dims: tuple
+    fat: np.ndarray            # complex128 [4][V][3][3], phases and BC folded in
+    naik: np.ndarray           # complex128 [4][V][3][3], phases and BC folded in
+    thin: np.ndarray | None = field(default=None, repr=False)   # unsigned U
+    scale: float = 0.0
+    seed: int = 0
+
+    @property
+    def volume(self) -> int:
+        return lattice_volume(self.dims)
+
+
+def make_gauge(dims, scale: float, seed: int, keep_thin: bool = False) -> GaugeField:
+    """The full synthetic field (U, V, W) for one lattice."""
+    dims = tuple(int(d) for d in dims)
+    if len(dims) != 4 or any(d < 4 or d % 2 for d in dims):
+        raise ValueError("dims must be four even extents >= 4")
+    U = thin_links(dims, scale, seed)
+    fat, naik = fat_and_naik(U, dims, seed)
+    return GaugeField(dims, fat, naik, U if keep_thin else None, scale, seed)
