@@ -1,0 +1,186 @@
+"""Benchmark of the improved-staggered solver on one MI355X.
+
+Workload: the 32^4 lattice (thin-link scale 0.5, gauge seed 1002, source seed 2002, m = 0.01).
+One step is one pass of the hot path over it:
+  1. a timed burst of FP64 Dslash_eo launches (HIP events around every launch, on the stream
+     the library launches on), plus FP32 / FP16 and 12-real bursts;
+  2. the plain FP64 GPU CG solve to true relative residual 1e-10;
+  3. the mixed-precision CG solves (FP32 inner, FP16 inner with 12-real Naik) to the same
+     FP64 true residual.
+`value` is the FP64 Dslash_eo's algorithmic HBM bandwidth (least-data model: 2400 bytes per
+output site) averaged over every launch of the timed steps.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+DIMS = (32, 32, 32, 32)
+MASS = 0.01
+TOL = 1e-10
+BURST = 20
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def model_bytes_per_site(prec: str, recon: int) -> int:
+    real = {"f64": 8, "f32": 4, "f16": 2}[prec]
+    spinor = {"f64": 48, "f32": 24, "f16": 16}[prec]
+    links = (8 * 18 + 8 * 12) * real if recon == 12 else 16 * 18 * real
+    return links + 2 * spinor
+
+
+def cpu_baseline(g, b, budget_s: float = 12.0):
+    """The FP64 oracle timed on the host: Dslash_eo calls over the same 32^4 field."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    vh = g.volume // 2
+    oracle.dslash_eo(g, 0, b)   # warm
+    n, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        oracle.dslash_eo(g, 0, b)
+        n += 1
+    dt = (time.perf_counter() - t0) / n
+    return {"value": model_bytes_per_site("f64", 18) * vh / dt / 1e9, "unit": "GB/s",
+            "cores": threads, "kind": "oracle",
+            "sample": "%d FP64 oracle Dslash_eo calls on the 32^4 field (%.3f s each)" % (n, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the solver has no multi-GPU path (the lattice is "
+              "not domain-decomposed here); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1611_00728_amd as ks
+    from ksinputs import make_gauge, gaussian_source
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    g = make_gauge(DIMS, 0.5, 1002)
+    vh = g.volume // 2
+    b = gaussian_source(vh, 2002)
+    log("inputs generated in %.1f s" % (time.time() - t0))
+    G = ks.Gauge(DIMS, g.fat, g.naik)
+    for p in (ks.F64, ks.F32, ks.F16):
+        for r in (18, 12):
+            G.prepare(p, r)
+    torch.cuda.synchronize()
+    log("gauge loaded, %.2f GB on the device" % (G.device_bytes() / 1e9))
+
+    bd = torch.from_numpy(b).cuda()
+    fields = {}
+    for name, p in (("f64", ks.F64), ("f32", ks.F32), ("f16", ks.F16)):
+        fields[name] = (ks.Field(G, ks.EVEN, p).load(bd), ks.Field(G, ks.ODD, p))
+    stream = torch.cuda.current_stream()
+
+    variants = [("f64", 18), ("f64", 12), ("f32", 18), ("f32", 12), ("f16", 18), ("f16", 12)]
+    times = {v: [] for v in variants}
+
+    def burst(v, record):
+        ein, eout = fields[v[0]]
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(BURST)]
+        for k in range(BURST):
+            evs[k][0].record(stream)
+            ks.dslash_eo(G, eout, ein, v[1])
+            evs[k][1].record(stream)
+        stream.synchronize()
+        if record:
+            times[v].extend(a.elapsed_time(c) * 1e-3 for a, c in evs)
+
+    solves = {"f64": [], "f32": [], "f16_r12": []}
+    solve_cfg = {"f64": dict(inner=ks.F64, recon=18), "f32": dict(inner=ks.F32, recon=18),
+                 "f16_r12": dict(inner=ks.F16, recon=12)}
+
+    def step(record):
+        for v in variants:
+            burst(v, record)
+        for name, kw in solve_cfg.items():
+            xd = torch.zeros_like(bd)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            res = ks.cg_solve(G, MASS, bd, xd, ks.default_params(tol=TOL, **kw))
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            if record:
+                solves[name].append((dt, res.stats))
+
+    for _ in range(args.warmup):
+        step(False)
+    log("warmup done")
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        step(True)
+        log("step %d done" % k)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+
+    dsl = {}
+    for v, ts in times.items():
+        avg = float(np.mean(ts))
+        mb = model_bytes_per_site(*v) * vh
+        dsl["%s_r%d" % v] = {"avg_us": avg * 1e6, "model_GBps": mb / avg / 1e9,
+                             "frac_of_8TBps": mb / avg / 1e9 / HBM_PEAK_GBS,
+                             "gflops": 1146.0 * vh / avg / 1e9}
+    head = dsl["f64_r18"]
+    tts = {}
+    base = float(np.median([d for d, _ in solves["f64"]]))
+    for name, rs in solves.items():
+        med = float(np.median([d for d, _ in rs]))
+        st = rs[-1][1]
+        tts[name] = {"seconds": med, "iters": st["iters"], "reliable_updates": st["reliable_updates"],
+                     "true_rel_resid": st["true_rel_resid"], "speedup_vs_f64": base / med,
+                     "model_GBps": st["model_bytes"] / st["seconds"] / 1e9}
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(g, b)
+    out = {
+        "metric": "Dslash HBM GB/s; CG time-to-1e-10 residual, mixed/learned vs FP64, 32^4",
+        "value": head["model_GBps"],
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "32^4 improved-staggered Dslash_eo + CG, m=0.01, H scale 0.5",
+                   "lattice": list(DIMS), "mass": MASS, "tol": TOL, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": head["model_GBps"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": head["model_GBps"] / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "dslash_kernel<F64,18,false>",
+                     "bytes_per_launch": model_bytes_per_site("f64", 18) * vh},
+        "dslash": dsl,
+        "time_to_solution": tts,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

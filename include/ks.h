@@ -1,0 +1,168 @@
+/*
+ * ks.h -- C ABI of the MI355X (gfx950) improved-staggered solver library, libks.so.
+ *
+ * The library solves the even-odd preconditioned normal equations of the improved-staggered
+ * (HISQ-style) Dirac operator,
+ *
+ *     A_sigma x_e = (sigma - D_eo D_oe) x_e = b_e,   sigma = 4 m^2 for one mass,
+ *
+ * by conjugate gradient, single-mass and multi-mass (the "staggered CG" and "multi-mass CG"
+ * of Sec. 3, benchmarked in double precision in Sec. 4), with
+ *
+ *     (D psi)(x) = sum_mu [ V_mu(x) psi(x+mu) - V_mu(x-mu)^+ psi(x-mu)
+ *                         + W_mu(x) psi(x+3mu) - W_mu(x-3mu)^+ psi(x-3mu) ]
+ *
+ * for the fat one-link V and the Naik three-link W, staggered phases and boundary signs
+ * folded into the links by the caller.  No factor 1/2: the full operator is M = 2m + D.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Lattice: dims = {Nx, Ny, Nz, Nt}, each even and >= 4; V = Nx Ny Nz Nt, Vh = V / 2.
+ * Sites are lexicographic, i = x + Nx (y + Ny (z + Nz t)); parity (x+y+z+t) mod 2 (even = 0).
+ * One-parity ("checkerboard") colour-vector fields are complex128 [Vh][3], interleaved
+ * (re, im), colour fastest; the site i of that parity is row i >> 1.
+ * Links are complex128 [4][V][3][3] (mu, site, row, column).
+ * Pointers named *_dev are device pointers (hipMalloc or torch CUDA tensors); the caller owns
+ * them.  Handles (ks_gauge_t, ks_field_t) are owned by the library and hold device memory in
+ * the library's internal layout; free them with the matching *_free call.
+ * Streams: all device work is queued on the caller's stream.  ks_dslash_eo and ks_apply_A
+ * return without waiting; the solvers wait for their stream before returning.
+ * Errors: every call returns a ks_status_t and never aborts; ks_last_error() gives a message
+ * for the calling thread's last failure.
+ */
+#ifndef KS_H
+#define KS_H
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ks_gauge_s* ks_gauge_t;
+typedef struct ks_field_s* ks_field_t;
+
+typedef enum { KS_F64 = 0, KS_F32 = 1, KS_F16 = 2 } ks_prec_t;
+/* storage of the Naik link W: 18 reals, or the two first rows of W / c (12 reals) with the
+ * real scale c and the third row rebuilt in the kernel (exact only when W = c * SU(3)). */
+typedef enum { KS_RECON_18 = 18, KS_RECON_12 = 12 } ks_recon_t;
+typedef enum { KS_EVEN = 0, KS_ODD = 1 } ks_parity_t;
+
+typedef enum {
+    KS_SUCCESS = 0,
+    KS_ERR_ARG = -1,            /* invalid argument (dims, null pointer, parity, aliasing) */
+    KS_ERR_HIP = -2,            /* a HIP runtime call failed */
+    KS_ERR_NOMEM = -3,          /* device allocation failed */
+    KS_ERR_NOT_SU3 = -4,        /* 12-real storage asked for links that are not c * SU(3) */
+    KS_ERR_NOT_CONVERGED = -5,  /* max_iter reached; x holds the last iterate, stats filled */
+    KS_ERR_BREAKDOWN = -6,      /* <p, A p> <= 0 */
+    KS_ERR_NONFINITE = -7       /* a NaN or Inf appeared in the iteration */
+} ks_status_t;
+
+typedef struct {
+    double tol;           /* target true relative residual |b - A x| / |b| */
+    int max_iter;         /* cap on Krylov steps (all restarts included) */
+    ks_prec_t inner;      /* precision of the inner operator and Krylov vectors */
+    ks_recon_t recon;     /* Naik-link storage of the inner operator */
+    double delta;         /* reliable update when |r_inner| < delta * max |r| since the last */
+    int check_every;      /* Krylov steps between host reads of the device status */
+    int max_restarts;     /* FP64 true-residual checks that may send the loop back */
+} ks_solver_params;
+
+typedef struct {
+    int iters;                 /* Krylov steps taken */
+    int reliable_updates;      /* FP64 recomputations of r = b - A x */
+    int restarts;              /* FP64 checks that failed and continued the loop */
+    int fallback;              /* flexible CG only: 1 when it fell back to plain CG */
+    double true_rel_resid;     /* FP64 |b - A x| / |b| at return, computed on the GPU */
+    double seconds;            /* wall time of the call */
+    double model_bytes;        /* least-data model bytes of the work done */
+    double model_flops;        /* model flops of the work done */
+} ks_solver_stats;
+
+/* Defaults: tol 1e-10, max_iter 100000, FP64 inner, 18-real Naik, delta 0.1, check every 16
+ * steps, 5 restarts. */
+void ks_default_params(ks_solver_params* p);
+
+/* ------------------------------------------------------------------ gauge field */
+
+/* Loads V (fat) and W (naik), complex128 [4][V][3][3] each, host (on_device = 0) or device
+ * (on_device = 1) memory, into a new handle.  The library keeps, for both output parities,
+ * the 16 matrices of every site {V_mu(x), -V_mu(x-mu)^+, W_mu(x), -W_mu(x-3mu)^+} as FP64
+ * site-major planes (the 8-way forward-plus-backward storage of Sec. 3).  Synchronises the
+ * stream before returning; the caller may free its arrays afterwards.
+ * KS_ERR_ARG for bad dims or null pointers, KS_ERR_NOMEM, KS_ERR_HIP. */
+ks_status_t ks_gauge_load(ks_gauge_t* out, const int dims[4], const double* fat,
+                          const double* naik, int on_device, hipStream_t stream);
+
+/* Builds (once) the link store of precision `prec` and Naik storage `recon` from the FP64
+ * store; every later call with that pair reuses it.  FP16 stores each link class scaled by a
+ * power of two so that its largest real lies in [0.5, 1).  12-real storage requires every
+ * stored Naik matrix to be c * eta_mu(x) * bc(x) * SU(3) for one real c, the staggered phases
+ * eta_0 = 1, eta_1 = (-1)^x, eta_2 = (-1)^(x+y), eta_3 = (-1)^(x+y+z), and bc = -1 exactly
+ * on the three-links that cross the antiperiodic time boundary; otherwise KS_ERR_NOT_SU3 and
+ * no store is kept.  Synchronises the stream. */
+ks_status_t ks_gauge_prepare(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon,
+                             hipStream_t stream);
+
+ks_status_t ks_gauge_free(ks_gauge_t g);
+
+/* Device bytes held by the handle (all stores and solver workspaces). */
+size_t ks_gauge_device_bytes(ks_gauge_t g);
+
+/* ------------------------------------------------------------------ fields */
+
+/* A one-parity colour-vector field of the handle's lattice in the library's layout:
+ * FP64 and FP32 as three site-major complex planes, FP16 as one 16-byte record per site
+ * (FP32 scale n, then three binary16 complex numbers of v / n, n = max |real| of the site). */
+ks_status_t ks_field_create(ks_field_t* f, ks_gauge_t g, ks_parity_t parity, ks_prec_t prec);
+ks_status_t ks_field_free(ks_field_t f);
+/* Copies complex128 [Vh][3] (device memory) into / out of the field, rounding to nearest
+ * even into FP32 / FP16.  Asynchronous on `stream`. */
+ks_status_t ks_field_import(ks_field_t f, const double* src_dev, hipStream_t stream);
+ks_status_t ks_field_export(ks_field_t f, double* dst_dev, hipStream_t stream);
+
+/* ------------------------------------------------------------------ operator */
+
+/* out = D_{p,1-p} in, p = parity of `out`; `in` must have the other parity and both fields
+ * the same precision (the link store of that precision and `recon` is built on first use).
+ * KS_ERR_ARG if parities or precisions do not match, if out == in, or if the fields belong
+ * to another lattice.  Asynchronous. */
+ks_status_t ks_dslash_eo(ks_gauge_t g, ks_field_t out, ks_field_t in, ks_recon_t recon,
+                         hipStream_t stream);
+
+/* out_dev = (sigma - D_eo D_oe) in_dev in FP64 on even sites, complex128 [Vh][3] device
+ * arrays (in_dev != out_dev).  Asynchronous. */
+ks_status_t ks_apply_A(ks_gauge_t g, double sigma, const double* in_dev, double* out_dev,
+                       hipStream_t stream);
+
+/* ------------------------------------------------------------------ solvers */
+
+/* Solves (4 m^2 - D_eo D_oe) x = b, b_dev and x_dev complex128 [Vh][3] device arrays.
+ * x_dev holds the initial guess on entry (zero it for x0 = 0) and the solution on return.
+ * With p->inner = KS_F64 this is plain FP64 CG; with KS_F32 / KS_F16 the Krylov vectors and
+ * the inner operator are FP32 / FP16 while x is accumulated in FP64 and r = b - A x is
+ * recomputed in FP64 (reliable update) whenever the inner residual falls below delta times
+ * its maximum since the last update, and before returning.  Reductions are FP64 throughout.
+ * Success means the FP64 true relative residual is <= p->tol. */
+ks_status_t ks_cg_solve(ks_gauge_t g, double mass, const double* b_dev, double* x_dev,
+                        const ks_solver_params* p, ks_solver_stats* st, hipStream_t stream);
+
+/* Solves (sigma_i - D_eo D_oe) x_i = b for nshift (<= 32) shifts in one Krylov space (the
+ * multi-mass CG of Sec. 3 and Sec. 4); sigma (host, length nshift) >= 0, x_dev a host array
+ * of nshift device pointers (complex128 [Vh][3], overwritten; the initial guess is zero),
+ * tol (host, length nshift) the per-shift targets.  The shared iteration runs in p->inner
+ * precision with x_i accumulated in FP64; every shift whose FP64 true residual is then above
+ * its target is refined by ks_cg_solve's method from x_i.  st: nshift entries. */
+ks_status_t ks_multishift_cg_solve(ks_gauge_t g, int nshift, const double* sigma,
+                                   const double* b_dev, double* const* x_dev,
+                                   const double* tol, const ks_solver_params* p,
+                                   ks_solver_stats* st, hipStream_t stream);
+
+/* Message of the calling thread's last failure ("" if none). */
+const char* ks_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KS_H */

@@ -1,0 +1,228 @@
+"""MI355X (gfx950) improved-staggered CG solver: Python binding of libks.so.
+
+This module only marshals arguments for the C ABI of include/ks.h (ctypes); every step of the
+computation runs in the library's HIP kernels.  Device arrays are torch CUDA tensors (their
+data pointers are handed to the library); the default stream is torch's current stream.
+There is no CPU path: if libks.so is missing, or no GPU is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libks.so")
+
+F64, F32, F16 = 0, 1, 2
+RECON_18, RECON_12 = 18, 12
+EVEN, ODD = 0, 1
+PREC = {"f64": F64, "f32": F32, "f16": F16}
+
+STATUS = {0: "success", -1: "invalid argument", -2: "HIP error", -3: "out of device memory",
+          -4: "links not c*SU(3)", -5: "not converged", -6: "breakdown", -7: "non-finite value"}
+
+
+class KSError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s (%d): %s" % (STATUS.get(code, "error"), code, msg))
+        self.code = code
+
+
+class SolverParams(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("inner", C.c_int),
+                ("recon", C.c_int), ("delta", C.c_double), ("check_every", C.c_int),
+                ("max_restarts", C.c_int)]
+
+
+class SolverStats(C.Structure):
+    _fields_ = [("iters", C.c_int), ("reliable_updates", C.c_int), ("restarts", C.c_int),
+                ("fallback", C.c_int), ("true_rel_resid", C.c_double), ("seconds", C.c_double),
+                ("model_bytes", C.c_double), ("model_flops", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+_vp = C.c_void_p
+
+
+def lib():
+    """The loaded libks.so.  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libks.so is not built (run __graft_entry__.build() or "
+                               "python paper_1611_00728_amd/build.py)")
+        L = C.CDLL(LIB_PATH)
+        L.ks_default_params.argtypes = [C.POINTER(SolverParams)]
+        L.ks_default_params.restype = None
+        L.ks_last_error.restype = C.c_char_p
+        L.ks_gauge_load.argtypes = [C.POINTER(_vp), C.POINTER(C.c_int), _vp, _vp, C.c_int, _vp]
+        L.ks_gauge_prepare.argtypes = [_vp, C.c_int, C.c_int, _vp]
+        L.ks_gauge_free.argtypes = [_vp]
+        L.ks_gauge_device_bytes.argtypes = [_vp]
+        L.ks_gauge_device_bytes.restype = C.c_size_t
+        L.ks_field_create.argtypes = [C.POINTER(_vp), _vp, C.c_int, C.c_int]
+        L.ks_field_free.argtypes = [_vp]
+        L.ks_field_import.argtypes = [_vp, _vp, _vp]
+        L.ks_field_export.argtypes = [_vp, _vp, _vp]
+        L.ks_dslash_eo.argtypes = [_vp, _vp, _vp, C.c_int, _vp]
+        L.ks_apply_A.argtypes = [_vp, C.c_double, _vp, _vp, _vp]
+        L.ks_cg_solve.argtypes = [_vp, C.c_double, _vp, _vp, C.POINTER(SolverParams),
+                                  C.POINTER(SolverStats), _vp]
+        L.ks_multishift_cg_solve.argtypes = [_vp, C.c_int, C.POINTER(C.c_double), _vp,
+                                             C.POINTER(_vp), C.POINTER(C.c_double),
+                                             C.POINTER(SolverParams), C.POINTER(SolverStats), _vp]
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise KSError(rc, lib().ks_last_error().decode())
+
+
+def _stream(stream):
+    if stream is not None:
+        return _vp(int(stream))
+    import torch
+    return _vp(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_ptr(t, what="tensor"):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.complex128
+            and t.is_contiguous()):
+        raise ValueError("%s must be a contiguous complex128 CUDA tensor" % what)
+    return _vp(t.data_ptr())
+
+
+def default_params(**kw) -> SolverParams:
+    p = SolverParams()
+    lib().ks_default_params(C.byref(p))
+    for k, v in kw.items():
+        if k == "inner" and isinstance(v, str):
+            v = PREC[v]
+        setattr(p, k, v)
+    return p
+
+
+class Gauge:
+    """A gauge field loaded into the library (ks_gauge_load)."""
+
+    def __init__(self, dims, fat, naik, stream=None):
+        import numpy as np
+        import torch
+        self.dims = tuple(int(d) for d in dims)
+        self.volume = int(np.prod(self.dims))
+        self.vh = self.volume // 2
+        d = (C.c_int * 4)(*self.dims)
+        h = _vp()
+        if isinstance(fat, torch.Tensor):
+            args = (_dev_ptr(fat, "fat"), _dev_ptr(naik, "naik"), 1)
+        else:
+            self._host = (np.ascontiguousarray(fat, dtype=np.complex128),
+                          np.ascontiguousarray(naik, dtype=np.complex128))
+            args = (_vp(self._host[0].ctypes.data), _vp(self._host[1].ctypes.data), 0)
+        _check(lib().ks_gauge_load(C.byref(h), d, args[0], args[1], args[2], _stream(stream)))
+        self._host = None
+        self.handle = h
+
+    def prepare(self, prec=F64, recon=RECON_18, stream=None):
+        _check(lib().ks_gauge_prepare(self.handle, prec, recon, _stream(stream)))
+
+    def device_bytes(self) -> int:
+        return int(lib().ks_gauge_device_bytes(self.handle))
+
+    def free(self):
+        if self.handle:
+            _check(lib().ks_gauge_free(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Field:
+    """A one-parity colour-vector field in the library's layout (ks_field_create)."""
+
+    def __init__(self, gauge: Gauge, parity: int, prec: int = F64):
+        h = _vp()
+        _check(lib().ks_field_create(C.byref(h), gauge.handle, parity, prec))
+        self.handle = h
+        self.gauge = gauge
+        self.parity = parity
+        self.prec = prec
+
+    def load(self, t, stream=None):
+        _check(lib().ks_field_import(self.handle, _dev_ptr(t), _stream(stream)))
+        return self
+
+    def store(self, t, stream=None):
+        _check(lib().ks_field_export(self.handle, _dev_ptr(t), _stream(stream)))
+        return t
+
+    def free(self):
+        if self.handle:
+            _check(lib().ks_field_free(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def dslash_eo(gauge: Gauge, out: Field, inp: Field, recon: int = RECON_18, stream=None):
+    _check(lib().ks_dslash_eo(gauge.handle, out.handle, inp.handle, recon, _stream(stream)))
+
+
+def apply_A(gauge: Gauge, sigma: float, x, out, stream=None):
+    _check(lib().ks_apply_A(gauge.handle, float(sigma), _dev_ptr(x, "x"), _dev_ptr(out, "out"),
+                            _stream(stream)))
+    return out
+
+
+@dataclass
+class SolveResult:
+    status: int
+    stats: dict
+
+    @property
+    def ok(self):
+        return self.status == 0
+
+
+def cg_solve(gauge: Gauge, mass: float, b, x, params: SolverParams | None = None,
+             stream=None, raise_on_error: bool = True) -> SolveResult:
+    """(4 m^2 - D_eo D_oe) x = b; x holds the initial guess and receives the solution."""
+    p = params if params is not None else default_params()
+    st = SolverStats()
+    rc = lib().ks_cg_solve(gauge.handle, float(mass), _dev_ptr(b, "b"), _dev_ptr(x, "x"),
+                           C.byref(p), C.byref(st), _stream(stream))
+    if rc != 0 and raise_on_error:
+        _check(rc)
+    return SolveResult(rc, st.as_dict())
+
+
+def multishift_cg_solve(gauge: Gauge, sigmas, b, xs, tols, params: SolverParams | None = None,
+                        stream=None, raise_on_error: bool = True):
+    """(sigma_i - D_eo D_oe) x_i = b for every shift; returns (status, [stats])."""
+    n = len(sigmas)
+    p = params if params is not None else default_params()
+    sig = (C.c_double * n)(*[float(s) for s in sigmas])
+    tl = (C.c_double * n)(*([float(tols)] * n if isinstance(tols, (int, float)) else
+                            [float(t) for t in tols]))
+    ptrs = (_vp * n)(*[_dev_ptr(x, "x[%d]" % i).value for i, x in enumerate(xs)])
+    st = (SolverStats * n)()
+    rc = lib().ks_multishift_cg_solve(gauge.handle, n, sig, _dev_ptr(b, "b"), ptrs, tl,
+                                      C.byref(p), st, _stream(stream))
+    if rc != 0 and raise_on_error:
+        _check(rc)
+    return rc, [s.as_dict() for s in st]

@@ -1,0 +1,313 @@
+// C ABI of libks (declared in include/ks.h): argument checks, handle management, error
+// reporting.  Every entry point catches the library's internal failures and returns a code.
+#include <cstdarg>
+#include <cstring>
+#include <vector>
+
+#include "ks_common.h"
+#include "ks_solvers.h"
+
+namespace ks {
+
+namespace {
+thread_local char g_err[512] = "";
+}
+
+const char* error_text() { return g_err; }
+
+void set_error(const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+void* device_alloc(size_t bytes)
+{
+    void* p = nullptr;
+    const hipError_t e = hipMalloc(&p, bytes ? bytes : 1);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+        throw Failure{KS_ERR_NOMEM};
+    }
+    return p;
+}
+
+void device_free(void* p)
+{
+    if (p) (void)hipFree(p);
+}
+
+Geom make_geom(const int dims[4])
+{
+    Geom g;
+    long v = 1;
+    for (int mu = 0; mu < 4; ++mu) {
+        g.n[mu] = dims[mu];
+        g.stride[mu] = (int)v;
+        v *= dims[mu];
+    }
+    g.V = (int)v;
+    g.Vh = (int)(v / 2);
+    return g;
+}
+
+size_t field_bytes(const Geom& g, ks_prec_t prec)
+{
+    return (size_t)g.Vh * (prec == KS_F64 ? 48 : prec == KS_F32 ? 24 : 16);
+}
+
+}  // namespace ks
+
+using namespace ks;
+
+#define KS_API_BEGIN try {
+#define KS_API_END                                                                      \
+    }                                                                                   \
+    catch (const Failure& f) {                                                          \
+        return f.code;                                                                  \
+    }                                                                                   \
+    catch (...) {                                                                       \
+        set_error("unexpected C++ exception");                                          \
+        return KS_ERR_HIP;                                                              \
+    }
+
+static bool prec_ok(int p) { return p == KS_F64 || p == KS_F32 || p == KS_F16; }
+static bool recon_ok(int r) { return r == KS_RECON_18 || r == KS_RECON_12; }
+
+extern "C" {
+
+void ks_default_params(ks_solver_params* p)
+{
+    if (!p) return;
+    p->tol = 1e-10;
+    p->max_iter = 100000;
+    p->inner = KS_F64;
+    p->recon = KS_RECON_18;
+    p->delta = 0.1;
+    p->check_every = 16;
+    p->max_restarts = 5;
+}
+
+const char* ks_last_error(void) { return error_text(); }
+
+ks_status_t ks_gauge_load(ks_gauge_t* out, const int dims[4], const double* fat,
+                          const double* naik, int on_device, hipStream_t stream)
+{
+    KS_API_BEGIN
+    KS_REQUIRE(out && dims && fat && naik, KS_ERR_ARG, "ks_gauge_load: null argument");
+    *out = nullptr;
+    long v = 1;
+    for (int mu = 0; mu < 4; ++mu) {
+        KS_REQUIRE(dims[mu] >= 4 && dims[mu] % 2 == 0, KS_ERR_ARG,
+                   "ks_gauge_load: extent %d of direction %d must be even and >= 4", dims[mu], mu);
+        v *= dims[mu];
+    }
+    KS_REQUIRE(v <= (1L << 29), KS_ERR_ARG, "ks_gauge_load: volume %ld too large", v);
+    ks_gauge_s* g = new ks_gauge_s();
+    g->geom = make_geom(dims);
+    const size_t bytes = (size_t)4 * v * 9 * 16;
+    double* tmp_fat = nullptr;
+    double* tmp_naik = nullptr;
+    try {
+        const double* df = fat;
+        const double* dn = naik;
+        if (!on_device) {
+            tmp_fat = static_cast<double*>(device_alloc(bytes));
+            tmp_naik = static_cast<double*>(device_alloc(bytes));
+            KS_HIP(hipMemcpyAsync(tmp_fat, fat, bytes, hipMemcpyHostToDevice, stream));
+            KS_HIP(hipMemcpyAsync(tmp_naik, naik, bytes, hipMemcpyHostToDevice, stream));
+            df = tmp_fat;
+            dn = tmp_naik;
+        }
+        gauge_build_f64(g, df, dn, stream);
+    } catch (...) {
+        device_free(tmp_fat);
+        device_free(tmp_naik);
+        gauge_release(g);
+        delete g;
+        throw;
+    }
+    device_free(tmp_fat);
+    device_free(tmp_naik);
+    *out = g;
+    return KS_SUCCESS;
+    KS_API_END
+}
+
+ks_status_t ks_gauge_prepare(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, hipStream_t stream)
+{
+    KS_API_BEGIN
+    KS_REQUIRE(g, KS_ERR_ARG, "ks_gauge_prepare: null handle");
+    KS_REQUIRE(prec_ok(prec) && recon_ok(recon), KS_ERR_ARG, "ks_gauge_prepare: bad precision/recon");
+    gauge_prepare(g, prec, recon, stream);
+    return KS_SUCCESS;
+    KS_API_END
+}
+
+ks_status_t ks_gauge_free(ks_gauge_t g)
+{
+    KS_API_BEGIN
+    if (!g) return KS_SUCCESS;
+    (void)hipDeviceSynchronize();
+    workspace_free(g->ws);
+    g->ws = nullptr;
+    gauge_release(g);
+    delete g;
+    return KS_SUCCESS;
+    KS_API_END
+}
+
+size_t ks_gauge_device_bytes(ks_gauge_t g)
+{
+    if (!g) return 0;
+    size_t b = 0;
+    for (int p = 0; p < 3; ++p)
+        for (int r = 0; r < 2; ++r) b += g->store[p][r].bytes;
+    if (g->ws) b += g->ws->bytes;
+    return b;
+}
+
+ks_status_t ks_field_create(ks_field_t* f, ks_gauge_t g, ks_parity_t parity, ks_prec_t prec)
+{
+    KS_API_BEGIN
+    KS_REQUIRE(f && g, KS_ERR_ARG, "ks_field_create: null argument");
+    KS_REQUIRE(parity == KS_EVEN || parity == KS_ODD, KS_ERR_ARG, "ks_field_create: bad parity");
+    KS_REQUIRE(prec_ok(prec), KS_ERR_ARG, "ks_field_create: bad precision");
+    *f = nullptr;
+    ks_field_s* h = new ks_field_s();
+    h->g = g;
+    h->parity = parity;
+    h->prec = prec;
+    h->bytes = field_bytes(g->geom, prec);
+    try {
+        h->data = device_alloc(h->bytes);
+    } catch (...) {
+        delete h;
+        throw;
+    }
+    *f = h;
+    return KS_SUCCESS;
+    KS_API_END
+}
+
+ks_status_t ks_field_free(ks_field_t f)
+{
+    KS_API_BEGIN
+    if (!f) return KS_SUCCESS;
+    device_free(f->data);
+    delete f;
+    return KS_SUCCESS;
+    KS_API_END
+}
+
+ks_status_t ks_field_import(ks_field_t f, const double* src_dev, hipStream_t stream)
+{
+    KS_API_BEGIN
+    KS_REQUIRE(f && src_dev, KS_ERR_ARG, "ks_field_import: null argument");
+    import_field(f->g->geom, f->prec, src_dev, f->data, stream);
+    return KS_SUCCESS;
+    KS_API_END
+}
+
+ks_status_t ks_field_export(ks_field_t f, double* dst_dev, hipStream_t stream)
+{
+    KS_API_BEGIN
+    KS_REQUIRE(f && dst_dev, KS_ERR_ARG, "ks_field_export: null argument");
+    export_field(f->g->geom, f->prec, f->data, dst_dev, stream);
+    return KS_SUCCESS;
+    KS_API_END
+}
+
+ks_status_t ks_dslash_eo(ks_gauge_t g, ks_field_t out, ks_field_t in, ks_recon_t recon,
+                         hipStream_t stream)
+{
+    KS_API_BEGIN
+    KS_REQUIRE(g && out && in, KS_ERR_ARG, "ks_dslash_eo: null argument");
+    KS_REQUIRE(out != in && out->data != in->data, KS_ERR_ARG, "ks_dslash_eo: out aliases in");
+    KS_REQUIRE(out->g == g && in->g == g, KS_ERR_ARG, "ks_dslash_eo: field of another lattice");
+    KS_REQUIRE(out->parity != in->parity, KS_ERR_ARG, "ks_dslash_eo: parities must differ");
+    KS_REQUIRE(out->prec == in->prec, KS_ERR_ARG, "ks_dslash_eo: precisions differ");
+    KS_REQUIRE(recon_ok(recon), KS_ERR_ARG, "ks_dslash_eo: bad recon");
+    DslashArgs a;
+    a.out_parity = out->parity;
+    a.in = in->data;
+    a.out = out->data;
+    dslash(g, out->prec, recon, a, stream);
+    return KS_SUCCESS;
+    KS_API_END
+}
+
+ks_status_t ks_apply_A(ks_gauge_t g, double sigma, const double* in_dev, double* out_dev,
+                       hipStream_t stream)
+{
+    KS_API_BEGIN
+    KS_REQUIRE(g && in_dev && out_dev, KS_ERR_ARG, "ks_apply_A: null argument");
+    KS_REQUIRE(in_dev != out_dev, KS_ERR_ARG, "ks_apply_A: out aliases in");
+    Workspace& w = workspace(g);
+    import_field(g->geom, KS_F64, in_dev, w.b64, stream);
+    apply_A64(g, sigma, static_cast<const double*>(w.b64), static_cast<double*>(w.ax64), stream,
+              nullptr);
+    export_field(g->geom, KS_F64, w.ax64, out_dev, stream);
+    return KS_SUCCESS;
+    KS_API_END
+}
+
+static void check_params(const ks_solver_params* p)
+{
+    KS_REQUIRE(p, KS_ERR_ARG, "solver: null params");
+    KS_REQUIRE(p->tol > 0 && p->max_iter >= 1, KS_ERR_ARG, "solver: tol must be > 0, max_iter >= 1");
+    KS_REQUIRE(prec_ok(p->inner) && recon_ok(p->recon), KS_ERR_ARG, "solver: bad inner precision/recon");
+    KS_REQUIRE(p->delta >= 0 && p->delta < 1, KS_ERR_ARG, "solver: delta must be in [0, 1)");
+}
+
+ks_status_t ks_cg_solve(ks_gauge_t g, double mass, const double* b_dev, double* x_dev,
+                        const ks_solver_params* p, ks_solver_stats* st, hipStream_t stream)
+{
+    KS_API_BEGIN
+    KS_REQUIRE(g && b_dev && x_dev, KS_ERR_ARG, "ks_cg_solve: null argument");
+    KS_REQUIRE(b_dev != x_dev, KS_ERR_ARG, "ks_cg_solve: x aliases b");
+    check_params(p);
+    Workspace& w = workspace(g);
+    import_field(g->geom, KS_F64, b_dev, w.b64, stream);
+    import_field(g->geom, KS_F64, x_dev, w.x64, stream);
+    ks_solver_stats local;
+    const ks_status_t rc = cg_core(g, 4.0 * mass * mass, static_cast<const double*>(w.b64),
+                                   static_cast<double*>(w.x64), *p, local, stream);
+    export_field(g->geom, KS_F64, w.x64, x_dev, stream);
+    KS_HIP(hipStreamSynchronize(stream));
+    if (st) *st = local;
+    return rc;
+    KS_API_END
+}
+
+ks_status_t ks_multishift_cg_solve(ks_gauge_t g, int nshift, const double* sigma,
+                                   const double* b_dev, double* const* x_dev, const double* tol,
+                                   const ks_solver_params* p, ks_solver_stats* st,
+                                   hipStream_t stream)
+{
+    KS_API_BEGIN
+    KS_REQUIRE(g && sigma && b_dev && x_dev && tol && st, KS_ERR_ARG,
+               "ks_multishift_cg_solve: null argument");
+    KS_REQUIRE(nshift >= 1 && nshift <= 32, KS_ERR_ARG, "ks_multishift_cg_solve: nshift in [1, 32]");
+    check_params(p);
+    for (int i = 0; i < nshift; ++i)
+        KS_REQUIRE(x_dev[i] && x_dev[i] != b_dev, KS_ERR_ARG, "ks_multishift_cg_solve: bad x[%d]", i);
+    Workspace& w = workspace(g);
+    import_field(g->geom, KS_F64, b_dev, w.b64, stream);
+    // solutions are kept in the library's FP64 planes, then exported into the caller's arrays
+    std::vector<double*> xs(nshift);
+    std::vector<void*>& keep = w.ms_x;
+    while ((int)keep.size() < nshift) keep.push_back(device_alloc(field_bytes(g->geom, KS_F64)));
+    for (int i = 0; i < nshift; ++i) xs[i] = static_cast<double*>(keep[i]);
+    const ks_status_t rc = multishift_core(g, nshift, sigma, static_cast<const double*>(w.b64),
+                                           xs.data(), tol, *p, st, stream);
+    for (int i = 0; i < nshift; ++i) export_field(g->geom, KS_F64, xs[i], x_dev[i], stream);
+    KS_HIP(hipStreamSynchronize(stream));
+    return rc;
+    KS_API_END
+}
+
+}  // extern "C"

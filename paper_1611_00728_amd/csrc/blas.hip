@@ -1,0 +1,375 @@
+// Deterministic FP64 reductions, field import/export and the fused BLAS-1 steps of CG.
+#include "ks_device.h"
+#include "ks_blas.h"
+
+namespace ks {
+
+namespace {
+
+constexpr int kFinish = 1024;
+
+// Fixed-order sum: thread t adds partials t, t + 1024, ... in order, then a fixed tree.
+__global__ __launch_bounds__(kFinish) void reduce_sum_kernel(const double* __restrict__ in, int n,
+                                                             double* __restrict__ out)
+{
+    double s = 0.0;
+    for (int k = threadIdx.x; k < n; k += kFinish) s += in[k];
+    s = block_sum<kFinish>(s);
+    if (threadIdx.x == 0) *out = s;
+}
+
+__global__ __launch_bounds__(kFinish) void reduce_max_kernel(const double* __restrict__ in, int n,
+                                                             double* __restrict__ out)
+{
+    double s = 0.0;
+    for (int k = threadIdx.x; k < n; k += kFinish) s = fmax(s, in[k]);
+    s = block_max<kFinish>(s);
+    if (threadIdx.x == 0) *out = s;
+}
+
+template <int P>
+__global__ __launch_bounds__(kBlock) void import_kernel(int vh, const double2* __restrict__ src,
+                                                        void* __restrict__ dst)
+{
+    using R = typename St<P>::R;
+    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= vh) return;
+    cx<R> v[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double2 t = src[3 * (size_t)h + k];
+        v[k] = {(R)t.x, (R)t.y};
+    }
+    Spinor<P>::store(dst, vh, h, v);
+}
+
+template <int P>
+__global__ __launch_bounds__(kBlock) void export_kernel(int vh, const void* __restrict__ src,
+                                                        double2* __restrict__ dst)
+{
+    using R = typename St<P>::R;
+    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= vh) return;
+    cx<R> v[3];
+    Spinor<P>::load(src, vh, h, v);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) dst[3 * (size_t)h + k] = make_double2((double)v[k].r, (double)v[k].i);
+}
+
+// out = in, converting storage precision
+template <int PI, int PO>
+__global__ __launch_bounds__(kBlock) void convert_kernel(int vh, const void* __restrict__ in,
+                                                         void* __restrict__ out,
+                                                         const int* __restrict__ gate)
+{
+    if (gate && *gate) return;
+    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= vh) return;
+    cx<typename St<PI>::R> v[3];
+    Spinor<PI>::load(in, vh, h, v);
+    cx<typename St<PO>::R> w[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) w[k] = {(typename St<PO>::R)v[k].r, (typename St<PO>::R)v[k].i};
+    Spinor<PO>::store(out, vh, h, w);
+}
+
+// partial sums of |v|^2 (FP64 field)
+__global__ __launch_bounds__(kBlock) void norm2_kernel(int vh, const double2* __restrict__ v,
+                                                       double* __restrict__ partials)
+{
+    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    double s = 0.0;
+    if (h < vh) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double2 t = v[k * vh + h];
+            s += t.x * t.x + t.y * t.y;
+        }
+    }
+    s = block_sum<kBlock>(s);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// r = b - Ax (FP64 planes), partial sums of |r|^2
+__global__ __launch_bounds__(kBlock) void sub_norm_kernel(int vh, const double2* __restrict__ b,
+                                                          const double2* __restrict__ ax,
+                                                          double2* __restrict__ r,
+                                                          double* __restrict__ partials)
+{
+    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    double s = 0.0;
+    if (h < vh) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double2 u = b[k * vh + h], w = ax[k * vh + h];
+            const double2 t = make_double2(u.x - w.x, u.y - w.y);
+            r[k * vh + h] = t;
+            s += t.x * t.x + t.y * t.y;
+        }
+    }
+    s = block_sum<kBlock>(s);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// x (FP64) += alpha p; r -= alpha q (precision P); partial sums of |r|^2 as stored
+template <int P>
+__global__ __launch_bounds__(kBlock) void update_xr_kernel(int vh, double2* __restrict__ x,
+                                                           const void* __restrict__ p,
+                                                           const void* __restrict__ q,
+                                                           void* __restrict__ r,
+                                                           const CGState* __restrict__ st,
+                                                           double* __restrict__ partials)
+{
+    using R = typename St<P>::R;
+    if (st->gate) return;
+    const double alpha = st->alpha;
+    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    double s = 0.0;
+    if (h < vh) {
+        cx<R> pv[3], qv[3], rv[3];
+        Spinor<P>::load(p, vh, h, pv);
+        Spinor<P>::load(q, vh, h, qv);
+        Spinor<P>::load(r, vh, h, rv);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            double2 t = x[k * vh + h];
+            t.x = fma(alpha, (double)pv[k].r, t.x);
+            t.y = fma(alpha, (double)pv[k].i, t.y);
+            x[k * vh + h] = t;
+        }
+        const R a = (R)alpha;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            rv[k].r = fma(-a, qv[k].r, rv[k].r);
+            rv[k].i = fma(-a, qv[k].i, rv[k].i);
+        }
+        Spinor<P>::store(r, vh, h, rv);
+        Spinor<P>::round(rv);
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            s += (double)rv[k].r * (double)rv[k].r + (double)rv[k].i * (double)rv[k].i;
+    }
+    s = block_sum<kBlock>(s);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// p = r + beta p
+template <int P>
+__global__ __launch_bounds__(kBlock) void xpay_kernel(int vh, const void* __restrict__ r,
+                                                      void* __restrict__ p,
+                                                      const CGState* __restrict__ st)
+{
+    using R = typename St<P>::R;
+    if (st->gate) return;
+    const R beta = (R)st->beta;
+    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= vh) return;
+    cx<R> rv[3], pv[3];
+    Spinor<P>::load(r, vh, h, rv);
+    Spinor<P>::load(p, vh, h, pv);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        pv[k].r = fma(beta, pv[k].r, rv[k].r);
+        pv[k].i = fma(beta, pv[k].i, rv[k].i);
+    }
+    Spinor<P>::store(p, vh, h, pv);
+}
+
+// ---------------------------------------------------------------- CG scalar steps
+
+__device__ __forceinline__ double finish_sum(const double* in, int n)
+{
+    double s = 0.0;
+    for (int k = threadIdx.x; k < n; k += kFinish) s += in[k];
+    return block_sum<kFinish>(s);
+}
+
+__global__ __launch_bounds__(kFinish) void cg_alpha_kernel(const double* __restrict__ part, int n,
+                                                           CGState* __restrict__ st)
+{
+    if (st->gate) return;
+    const double pap = finish_sum(part, n);
+    if (threadIdx.x != 0) return;
+    st->pAp = pap;
+    if (!isfinite(pap)) {
+        st->status = KS_ERR_NONFINITE;
+        st->gate = 1;
+    } else if (!(pap > 0.0)) {
+        st->status = KS_ERR_BREAKDOWN;
+        st->gate = 1;
+    } else {
+        st->alpha = st->rho / pap;
+    }
+}
+
+__global__ __launch_bounds__(kFinish) void cg_beta_kernel(const double* __restrict__ part, int n,
+                                                          CGState* __restrict__ st)
+{
+    if (st->gate) return;
+    const double rho_new = finish_sum(part, n);
+    if (threadIdx.x != 0) return;
+    st->iter += 1;
+    st->rho_new = rho_new;
+    if (!isfinite(rho_new)) {
+        st->status = KS_ERR_NONFINITE;
+        st->gate = 1;
+        return;
+    }
+    const double rn = sqrt(rho_new);
+    if (rho_new <= st->stop2 || rn < st->delta * st->maxr) {
+        // FP64 recomputation of r = b - A x decides (reliable update or final check)
+        st->ru_pending = 1;
+        st->gate = 1;
+        return;
+    }
+    st->beta = rho_new / st->rho;
+    st->rho = rho_new;
+    st->maxr = fmax(st->maxr, rn);
+    if (st->iter >= st->max_iter) st->gate = 1;
+}
+
+// After r = b - A x in FP64: either converged, or continue with beta = |r|^2 / rho.
+__global__ __launch_bounds__(kFinish) void cg_reliable_kernel(const double* __restrict__ part, int n,
+                                                              CGState* __restrict__ st, int initial)
+{
+    const double r2 = finish_sum(part, n);
+    if (threadIdx.x != 0) return;
+    st->true_r2 = r2;
+    st->ru_pending = 0;
+    if (!isfinite(r2)) {
+        st->status = KS_ERR_NONFINITE;
+        st->gate = 1;
+        return;
+    }
+    if (r2 <= st->stop2) {
+        st->done = 1;
+        st->gate = 1;
+        return;
+    }
+    st->beta = initial ? 0.0 : r2 / st->rho;
+    st->rho = r2;
+    st->maxr = sqrt(r2);
+    st->gate = (st->iter >= st->max_iter) ? 1 : 0;
+}
+
+__global__ void finish_to_kernel(const double* __restrict__ part, int n, double* __restrict__ out)
+{
+    const double s = finish_sum(part, n);
+    if (threadIdx.x == 0) *out = s;
+}
+
+}  // namespace
+
+void reduce_sum(const double* partials, int n, double* out, hipStream_t s)
+{
+    reduce_sum_kernel<<<1, kFinish, 0, s>>>(partials, n, out);
+    KS_HIP(hipGetLastError());
+}
+
+void reduce_max(const double* partials, int n, double* out, hipStream_t s)
+{
+    reduce_max_kernel<<<1, kFinish, 0, s>>>(partials, n, out);
+    KS_HIP(hipGetLastError());
+}
+
+void import_field(const Geom& g, ks_prec_t prec, const double* src, void* dst, hipStream_t s)
+{
+    const int nb = blocks_for(g.Vh);
+    const double2* sp = reinterpret_cast<const double2*>(src);
+    if (prec == KS_F64) import_kernel<KS_F64><<<nb, kBlock, 0, s>>>(g.Vh, sp, dst);
+    else if (prec == KS_F32) import_kernel<KS_F32><<<nb, kBlock, 0, s>>>(g.Vh, sp, dst);
+    else import_kernel<KS_F16><<<nb, kBlock, 0, s>>>(g.Vh, sp, dst);
+    KS_HIP(hipGetLastError());
+}
+
+void export_field(const Geom& g, ks_prec_t prec, const void* src, double* dst, hipStream_t s)
+{
+    const int nb = blocks_for(g.Vh);
+    double2* dp = reinterpret_cast<double2*>(dst);
+    if (prec == KS_F64) export_kernel<KS_F64><<<nb, kBlock, 0, s>>>(g.Vh, src, dp);
+    else if (prec == KS_F32) export_kernel<KS_F32><<<nb, kBlock, 0, s>>>(g.Vh, src, dp);
+    else export_kernel<KS_F16><<<nb, kBlock, 0, s>>>(g.Vh, src, dp);
+    KS_HIP(hipGetLastError());
+}
+
+void convert_field(int vh, ks_prec_t pin, const void* in, ks_prec_t pout, void* out,
+                   const int* gate, hipStream_t s)
+{
+    const int nb = blocks_for(vh);
+#define KS_CONV(A, B)                                                                   \
+    if (pin == A && pout == B) {                                                        \
+        convert_kernel<A, B><<<nb, kBlock, 0, s>>>(vh, in, out, gate);                  \
+        KS_HIP(hipGetLastError());                                                      \
+        return;                                                                         \
+    }
+    KS_CONV(KS_F64, KS_F64)
+    KS_CONV(KS_F64, KS_F32)
+    KS_CONV(KS_F64, KS_F16)
+    KS_CONV(KS_F32, KS_F32)
+    KS_CONV(KS_F32, KS_F64)
+    KS_CONV(KS_F16, KS_F16)
+    KS_CONV(KS_F16, KS_F64)
+#undef KS_CONV
+    KS_REQUIRE(false, KS_ERR_ARG, "unsupported conversion %d -> %d", (int)pin, (int)pout);
+}
+
+void norm2_partials(int vh, const double* v, double* partials, hipStream_t s)
+{
+    norm2_kernel<<<blocks_for(vh), kBlock, 0, s>>>(vh, reinterpret_cast<const double2*>(v), partials);
+    KS_HIP(hipGetLastError());
+}
+
+void sub_norm_partials(int vh, const double* b, const double* ax, double* r, double* partials,
+                       hipStream_t s)
+{
+    sub_norm_kernel<<<blocks_for(vh), kBlock, 0, s>>>(
+        vh, reinterpret_cast<const double2*>(b), reinterpret_cast<const double2*>(ax),
+        reinterpret_cast<double2*>(r), partials);
+    KS_HIP(hipGetLastError());
+}
+
+void update_xr(int vh, ks_prec_t prec, double* x, const void* p, const void* q, void* r,
+               const CGState* st, double* partials, hipStream_t s)
+{
+    const int nb = blocks_for(vh);
+    double2* xp = reinterpret_cast<double2*>(x);
+    if (prec == KS_F64) update_xr_kernel<KS_F64><<<nb, kBlock, 0, s>>>(vh, xp, p, q, r, st, partials);
+    else if (prec == KS_F32) update_xr_kernel<KS_F32><<<nb, kBlock, 0, s>>>(vh, xp, p, q, r, st, partials);
+    else update_xr_kernel<KS_F16><<<nb, kBlock, 0, s>>>(vh, xp, p, q, r, st, partials);
+    KS_HIP(hipGetLastError());
+}
+
+void xpay(int vh, ks_prec_t prec, const void* r, void* p, const CGState* st, hipStream_t s)
+{
+    const int nb = blocks_for(vh);
+    if (prec == KS_F64) xpay_kernel<KS_F64><<<nb, kBlock, 0, s>>>(vh, r, p, st);
+    else if (prec == KS_F32) xpay_kernel<KS_F32><<<nb, kBlock, 0, s>>>(vh, r, p, st);
+    else xpay_kernel<KS_F16><<<nb, kBlock, 0, s>>>(vh, r, p, st);
+    KS_HIP(hipGetLastError());
+}
+
+void cg_alpha(const double* part, int n, CGState* st, hipStream_t s)
+{
+    cg_alpha_kernel<<<1, kFinish, 0, s>>>(part, n, st);
+    KS_HIP(hipGetLastError());
+}
+
+void cg_beta(const double* part, int n, CGState* st, hipStream_t s)
+{
+    cg_beta_kernel<<<1, kFinish, 0, s>>>(part, n, st);
+    KS_HIP(hipGetLastError());
+}
+
+void cg_reliable(const double* part, int n, CGState* st, int initial, hipStream_t s)
+{
+    cg_reliable_kernel<<<1, kFinish, 0, s>>>(part, n, st, initial);
+    KS_HIP(hipGetLastError());
+}
+
+void finish_to(const double* part, int n, double* out, hipStream_t s)
+{
+    finish_to_kernel<<<1, kFinish, 0, s>>>(part, n, out);
+    KS_HIP(hipGetLastError());
+}
+
+}  // namespace ks

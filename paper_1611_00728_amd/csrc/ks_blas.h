@@ -1,0 +1,40 @@
+// Scalar state and vector steps of the CG solvers.
+#pragma once
+
+#include "ks_common.h"
+
+namespace ks {
+
+// Device-resident scalars of one CG solve.  Kernels of one iteration skip their work while
+// `gate` is nonzero: after convergence, after an error, or while a reliable update is due.
+struct CGState {
+    double rho;        // |r|^2 of the inner residual
+    double rho_new;
+    double alpha, beta;
+    double pAp;
+    double maxr;       // max |r| since the last reliable update
+    double stop2;      // (tol |b|)^2
+    double delta;      // reliable-update threshold (0 = only the final check)
+    double true_r2;    // |b - A x|^2 of the last FP64 recomputation
+    int iter;
+    int max_iter;
+    int gate;
+    int ru_pending;
+    int done;
+    int status;
+};
+
+void convert_field(int vh, ks_prec_t pin, const void* in, ks_prec_t pout, void* out,
+                   const int* gate, hipStream_t s);
+void norm2_partials(int vh, const double* v, double* partials, hipStream_t s);
+void sub_norm_partials(int vh, const double* b, const double* ax, double* r, double* partials,
+                       hipStream_t s);
+void update_xr(int vh, ks_prec_t prec, double* x, const void* p, const void* q, void* r,
+               const CGState* st, double* partials, hipStream_t s);
+void xpay(int vh, ks_prec_t prec, const void* r, void* p, const CGState* st, hipStream_t s);
+void cg_alpha(const double* part, int n, CGState* st, hipStream_t s);
+void cg_beta(const double* part, int n, CGState* st, hipStream_t s);
+void cg_reliable(const double* part, int n, CGState* st, int initial, hipStream_t s);
+void finish_to(const double* part, int n, double* out, hipStream_t s);
+
+}  // namespace ks

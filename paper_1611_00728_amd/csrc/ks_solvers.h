@@ -1,0 +1,58 @@
+// Solver workspaces and internal solver entry points.
+#pragma once
+
+#include <vector>
+
+#include "ks_blas.h"
+
+namespace ks {
+
+// Per-gauge-handle solver buffers, allocated on first use and kept until ks_gauge_free.
+struct Workspace {
+    size_t bytes = 0;
+    int npart = 0;
+    double* partials = nullptr;   // per-block partial sums
+    double* scal = nullptr;       // device scalars (after the partials)
+    double* host_scal = nullptr;  // pinned
+    CGState* st = nullptr;
+    CGState* st_host = nullptr;   // pinned
+    // FP64 planes [3][Vh] (t64 has the odd parity)
+    double* b64 = nullptr;
+    double* x64 = nullptr;
+    double* r64 = nullptr;
+    double* t64 = nullptr;
+    double* ax64 = nullptr;
+    // inner-precision vectors per precision (ts odd)
+    void* rs[3] = {nullptr, nullptr, nullptr};
+    void* ps[3] = {nullptr, nullptr, nullptr};
+    void* qs[3] = {nullptr, nullptr, nullptr};
+    void* ts[3] = {nullptr, nullptr, nullptr};
+    // multi-shift
+    std::vector<void*> ms_x;      // FP64 solutions
+    std::vector<void*> ms_p;      // shifted directions, inner precision
+    int ms_prec = -1;
+    void* ms_r = nullptr;
+    void* ms_pb = nullptr;
+    void* ms_q = nullptr;
+    void* ms_t = nullptr;
+    void* ms_st = nullptr;
+    void* ms_st_host = nullptr;
+};
+
+Workspace& workspace(ks_gauge_t g);
+void workspace_free(Workspace* w);
+
+double dslash_model_bytes(ks_prec_t p, ks_recon_t r);
+double cg_iter_model_bytes(ks_prec_t p, ks_recon_t r);
+double norm2_host(ks_gauge_t g, const double* v, hipStream_t s);
+void apply_A64(ks_gauge_t g, double sigma, const double* x, double* ax, hipStream_t s,
+               const int* gate);
+double true_resid2(ks_gauge_t g, double sigma, const double* b, const double* x, hipStream_t s);
+
+ks_status_t cg_core(ks_gauge_t g, double sigma, const double* b, double* x,
+                    const ks_solver_params& prm, ks_solver_stats& stats, hipStream_t s);
+ks_status_t multishift_core(ks_gauge_t g, int nshift, const double* sigma, const double* b,
+                            double* const* x, const double* tol, const ks_solver_params& prm,
+                            ks_solver_stats* stats, hipStream_t s);
+
+}  // namespace ks

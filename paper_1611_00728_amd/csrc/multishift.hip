@@ -1,0 +1,356 @@
+// Multi-mass (multi-shift) CG: (sigma_i - D_eo D_oe) x_i = b for all shifts in one Krylov
+// space (the multi-mass CG of Sec. 3 and Sec. 4), then FP64-checked per-shift refinement.
+//
+// Base system A_0 = sigma_0 - D_eo D_oe with sigma_0 = min sigma_i; delta_i = sigma_i - sigma_0.
+// Per step, with the base CG's alpha, beta:
+//   zeta_i' = zeta_i zeta_i^- alpha^- / (alpha beta^- (zeta_i^- - zeta_i)
+//                                        + zeta_i^- alpha^- (1 + delta_i alpha))
+//   alpha_i = alpha zeta_i' / zeta_i,  beta_i = beta (zeta_i' / zeta_i)^2,
+//   x_i += alpha_i p_i,  p_i = zeta_i' r + beta_i p_i  (one fused kernel for all shifts),
+// which keeps r_i = zeta_i r.  Shift i freezes once zeta_i^2 |r|^2 <= (tol_i |b|)^2.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "ks_device.h"
+#include "ks_solvers.h"
+
+namespace ks {
+
+namespace {
+
+constexpr int kMaxShift = 32;
+constexpr int kFinish = 1024;
+
+struct MSState {
+    double rho, alpha, alpha_prev, beta, beta_prev, pAp;
+    int iter, max_iter, gate, stop_next, status, nactive, nshift, pad;
+    double delta[kMaxShift], stop2[kMaxShift];
+    double zeta[kMaxShift], zeta_prev[kMaxShift];
+    double alpha_i[kMaxShift], beta_i[kMaxShift];
+    int active[kMaxShift], upd[kMaxShift];
+};
+
+struct ShiftPtrs {
+    double2* x[kMaxShift];
+    void* p[kMaxShift];
+};
+
+__device__ __forceinline__ double finish_sum(const double* in, int n)
+{
+    double s = 0.0;
+    for (int k = threadIdx.x; k < n; k += kFinish) s += in[k];
+    return block_sum<kFinish>(s);
+}
+
+__global__ __launch_bounds__(kFinish) void ms_alpha_kernel(const double* __restrict__ part, int n,
+                                                           MSState* __restrict__ st)
+{
+    if (st->gate) return;
+    if (st->stop_next) {
+        if (threadIdx.x == 0) st->gate = 1;
+        return;
+    }
+    const double pap = finish_sum(part, n);
+    if (threadIdx.x != 0) return;
+    st->pAp = pap;
+    if (!isfinite(pap) || !(pap > 0.0)) {
+        st->status = isfinite(pap) ? KS_ERR_BREAKDOWN : KS_ERR_NONFINITE;
+        st->gate = 1;
+        return;
+    }
+    const double a = st->rho / pap;
+    st->alpha = a;
+    for (int i = 0; i < st->nshift; ++i) {
+        st->upd[i] = st->active[i];
+        if (!st->active[i]) continue;
+        const double z = st->zeta[i], zp = st->zeta_prev[i];
+        const double zn = z * zp * st->alpha_prev /
+                          (a * st->beta_prev * (zp - z) + zp * st->alpha_prev * (1.0 + st->delta[i] * a));
+        st->alpha_i[i] = a * zn / z;
+        st->beta_i[i] = zn;   // holds zeta' until the beta step
+    }
+}
+
+// r -= alpha q; partial sums of |r|^2 as stored
+template <int P>
+__global__ __launch_bounds__(kBlock) void ms_r_kernel(int vh, const void* __restrict__ q,
+                                                      void* __restrict__ r,
+                                                      const MSState* __restrict__ st,
+                                                      double* __restrict__ partials)
+{
+    using R = typename St<P>::R;
+    if (st->gate) return;
+    const R a = (R)st->alpha;
+    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    double s = 0.0;
+    if (h < vh) {
+        cx<R> qv[3], rv[3];
+        Spinor<P>::load(q, vh, h, qv);
+        Spinor<P>::load(r, vh, h, rv);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            rv[k].r = fma(-a, qv[k].r, rv[k].r);
+            rv[k].i = fma(-a, qv[k].i, rv[k].i);
+        }
+        Spinor<P>::store(r, vh, h, rv);
+        Spinor<P>::round(rv);
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            s += (double)rv[k].r * (double)rv[k].r + (double)rv[k].i * (double)rv[k].i;
+    }
+    s = block_sum<kBlock>(s);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kFinish) void ms_beta_kernel(const double* __restrict__ part, int n,
+                                                          MSState* __restrict__ st)
+{
+    if (st->gate) return;
+    const double rn = finish_sum(part, n);
+    if (threadIdx.x != 0) return;
+    if (!isfinite(rn)) {
+        st->status = KS_ERR_NONFINITE;
+        st->gate = 1;
+        return;
+    }
+    const double b = rn / st->rho;
+    st->beta = b;
+    st->iter += 1;
+    for (int i = 0; i < st->nshift; ++i) {
+        if (!st->upd[i]) continue;
+        const double zn = st->beta_i[i];
+        const double ratio = zn / st->zeta[i];
+        st->beta_i[i] = b * ratio * ratio;
+        st->zeta_prev[i] = st->zeta[i];
+        st->zeta[i] = zn;
+        if (zn * zn * rn <= st->stop2[i]) {
+            st->active[i] = 0;
+            st->nactive -= 1;
+        }
+    }
+    st->alpha_prev = st->alpha;
+    st->beta_prev = b;
+    st->rho = rn;
+    if (st->nactive == 0 || st->iter >= st->max_iter) st->stop_next = 1;
+}
+
+// x_i += alpha_i p_i; p_i = zeta_i r + beta_i p_i for every shift updated this step, and the
+// base direction p = r + beta p.  r is read once per site for all shifts.
+template <int P>
+__global__ __launch_bounds__(kBlock) void ms_update_kernel(int vh, const void* __restrict__ r,
+                                                           void* __restrict__ pb, ShiftPtrs sp,
+                                                           const MSState* __restrict__ st)
+{
+    using R = typename St<P>::R;
+    if (st->gate) return;
+    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= vh) return;
+    cx<R> rv[3], pv[3];
+    Spinor<P>::load(r, vh, h, rv);
+    const int ns = st->nshift;
+    for (int i = 0; i < ns; ++i) {
+        if (!st->upd[i]) continue;
+        const double ai = st->alpha_i[i];
+        const R bi = (R)st->beta_i[i], zi = (R)st->zeta[i];
+        Spinor<P>::load(sp.p[i], vh, h, pv);
+        double2* x = sp.x[i];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            double2 t = x[k * vh + h];
+            t.x = fma(ai, (double)pv[k].r, t.x);
+            t.y = fma(ai, (double)pv[k].i, t.y);
+            x[k * vh + h] = t;
+            pv[k].r = fma(bi, pv[k].r, zi * rv[k].r);
+            pv[k].i = fma(bi, pv[k].i, zi * rv[k].i);
+        }
+        Spinor<P>::store(sp.p[i], vh, h, pv);
+    }
+    const R b = (R)st->beta;
+    Spinor<P>::load(pb, vh, h, pv);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        pv[k].r = fma(b, pv[k].r, rv[k].r);
+        pv[k].i = fma(b, pv[k].i, rv[k].i);
+    }
+    Spinor<P>::store(pb, vh, h, pv);
+}
+
+template <int P>
+void launch_r(int vh, const void* q, void* r, const MSState* st, double* part, hipStream_t s)
+{
+    ms_r_kernel<P><<<blocks_for(vh), kBlock, 0, s>>>(vh, q, r, st, part);
+}
+
+template <int P>
+void launch_upd(int vh, const void* r, void* pb, const ShiftPtrs& sp, const MSState* st,
+                hipStream_t s)
+{
+    ms_update_kernel<P><<<blocks_for(vh), kBlock, 0, s>>>(vh, r, pb, sp, st);
+}
+
+}  // namespace
+
+double multishift_iter_model_bytes(ks_prec_t p, ks_recon_t r, int nactive)
+{
+    const double sb = p == KS_F64 ? 48 : p == KS_F32 ? 24 : 16;
+    // A-apply (two hopping terms + xpay read), r update (q, r read, r write), fused update
+    // (r, p read, p write; per shift p_i read/write and x_i read/write in FP64)
+    return 2 * dslash_model_bytes(p, r) + sb + 3 * sb + 3 * sb + nactive * (2 * sb + 96);
+}
+
+ks_status_t multishift_core(ks_gauge_t g, int nshift, const double* sigma, const double* b,
+                            double* const* x, const double* tol, const ks_solver_params& prm,
+                            ks_solver_stats* stats, hipStream_t s)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    KS_REQUIRE(nshift >= 1 && nshift <= kMaxShift, KS_ERR_ARG, "nshift must be in [1, %d]",
+               kMaxShift);
+    for (int i = 0; i < nshift; ++i) {
+        KS_REQUIRE(sigma[i] >= 0 && std::isfinite(sigma[i]), KS_ERR_ARG, "shift %d is negative", i);
+        KS_REQUIRE(tol[i] > 0, KS_ERR_ARG, "tolerance of shift %d must be positive", i);
+        KS_REQUIRE(x[i] != nullptr, KS_ERR_ARG, "solution pointer %d is null", i);
+    }
+    Workspace& w = workspace(g);
+    const Geom& G = g->geom;
+    const int vh = G.Vh;
+    const ks_prec_t P = prm.inner;
+    const ks_recon_t RC = prm.recon;
+    gauge_prepare(g, P, RC, s);
+    const size_t fb = field_bytes(G, P);
+    if (w.ms_prec != (int)P) {
+        for (void* v : w.ms_p) device_free(v);
+        w.ms_p.clear();
+        device_free(w.ms_r);
+        device_free(w.ms_pb);
+        device_free(w.ms_q);
+        device_free(w.ms_t);
+        w.ms_r = device_alloc(fb);
+        w.ms_pb = device_alloc(fb);
+        w.ms_q = device_alloc(fb);
+        w.ms_t = device_alloc(fb);
+        w.ms_prec = (int)P;
+    }
+    while ((int)w.ms_p.size() < nshift) w.ms_p.push_back(device_alloc(fb));
+    if (!w.ms_st) {
+        w.ms_st = device_alloc(sizeof(MSState));
+        KS_HIP(hipHostMalloc(&w.ms_st_host, sizeof(MSState)));
+    }
+    MSState* st = static_cast<MSState*>(w.ms_st);
+    MSState* hs = static_cast<MSState*>(w.ms_st_host);
+
+    double s0 = sigma[0];
+    for (int i = 1; i < nshift; ++i) s0 = std::min(s0, sigma[i]);
+
+    // r = p = p_i = b in the inner precision, x_i = 0
+    convert_field(vh, KS_F64, b, P, w.ms_r, nullptr, s);
+    convert_field(vh, KS_F64, b, P, w.ms_pb, nullptr, s);
+    ShiftPtrs sp{};
+    for (int i = 0; i < nshift; ++i) {
+        convert_field(vh, KS_F64, b, P, w.ms_p[i], nullptr, s);
+        KS_HIP(hipMemsetAsync(x[i], 0, field_bytes(G, KS_F64), s));
+        sp.x[i] = reinterpret_cast<double2*>(x[i]);
+        sp.p[i] = w.ms_p[i];
+    }
+    const double b2 = norm2_host(g, b, s);
+    convert_field(vh, P, w.ms_r, KS_F64, w.r64, nullptr, s);
+    const double r2 = norm2_host(g, static_cast<const double*>(w.r64), s);
+
+    std::memset(hs, 0, sizeof(MSState));
+    hs->rho = r2;
+    hs->alpha_prev = 1.0;
+    hs->beta_prev = 0.0;
+    hs->max_iter = prm.max_iter;
+    hs->nshift = nshift;
+    hs->nactive = nshift;
+    for (int i = 0; i < nshift; ++i) {
+        hs->delta[i] = sigma[i] - s0;
+        hs->stop2[i] = tol[i] * tol[i] * b2;
+        hs->zeta[i] = hs->zeta_prev[i] = 1.0;
+        hs->active[i] = 1;
+    }
+    if (b2 == 0.0) {
+        hs->gate = 1;
+        hs->nactive = 0;
+    }
+    KS_HIP(hipMemcpyAsync(st, hs, sizeof(MSState), hipMemcpyHostToDevice, s));
+
+    const int chunk = std::max(1, prm.check_every);
+    ks_status_t result = KS_SUCCESS;
+    auto iteration = [&]() {
+        DslashArgs a1;
+        a1.out_parity = 1;
+        a1.in = w.ms_pb;
+        a1.out = w.ms_t;
+        a1.gate = &st->gate;
+        dslash(g, P, RC, a1, s);
+        DslashArgs a2;
+        a2.out_parity = 0;
+        a2.in = w.ms_t;
+        a2.out = w.ms_q;
+        a2.x = w.ms_pb;
+        a2.a = s0;
+        a2.dot_partials = w.partials;
+        a2.gate = &st->gate;
+        dslash(g, P, RC, a2, s);
+        ms_alpha_kernel<<<1, kFinish, 0, s>>>(w.partials, w.npart, st);
+        if (P == KS_F64) launch_r<KS_F64>(vh, w.ms_q, w.ms_r, st, w.partials, s);
+        else if (P == KS_F32) launch_r<KS_F32>(vh, w.ms_q, w.ms_r, st, w.partials, s);
+        else launch_r<KS_F16>(vh, w.ms_q, w.ms_r, st, w.partials, s);
+        ms_beta_kernel<<<1, kFinish, 0, s>>>(w.partials, w.npart, st);
+        if (P == KS_F64) launch_upd<KS_F64>(vh, w.ms_r, w.ms_pb, sp, st, s);
+        else if (P == KS_F32) launch_upd<KS_F32>(vh, w.ms_r, w.ms_pb, sp, st, s);
+        else launch_upd<KS_F16>(vh, w.ms_r, w.ms_pb, sp, st, s);
+        KS_HIP(hipGetLastError());
+    };
+    double model_bytes = 0.0;
+    int last_iter = 0;
+    for (;;) {
+        KS_HIP(hipMemcpyAsync(hs, st, sizeof(MSState), hipMemcpyDeviceToHost, s));
+        KS_HIP(hipStreamSynchronize(s));
+        model_bytes += (hs->iter - last_iter) * multishift_iter_model_bytes(P, RC, hs->nactive) * vh;
+        last_iter = hs->iter;
+        if (hs->status != 0) {
+            result = static_cast<ks_status_t>(hs->status);
+            set_error("multi-shift CG: %s at step %d",
+                      result == KS_ERR_BREAKDOWN ? "breakdown" : "non-finite value", hs->iter);
+            break;
+        }
+        if (hs->gate || hs->stop_next) break;
+        for (int k = 0; k < chunk; ++k) iteration();
+    }
+    const int ms_iters = hs->iter;
+
+    // FP64 verdict per shift; refine the ones above target from x_i
+    for (int i = 0; i < nshift; ++i) {
+        ks_solver_stats& o = stats[i];
+        o = ks_solver_stats();
+        o.iters = ms_iters;
+        o.model_bytes = model_bytes / nshift;
+        if (result != KS_SUCCESS) continue;
+        const double tr2 = true_resid2(g, sigma[i], b, x[i], s);
+        o.true_rel_resid = b2 > 0 ? std::sqrt(tr2 / b2) : 0.0;
+        if (b2 > 0 && tr2 > tol[i] * tol[i] * b2) {
+            ks_solver_params q = prm;
+            q.tol = tol[i];
+            ks_solver_stats rs;
+            const ks_status_t rc = cg_core(g, sigma[i], b, x[i], q, rs, s);
+            o.iters += rs.iters;
+            o.reliable_updates = rs.reliable_updates;
+            o.restarts = rs.restarts + 1;
+            o.true_rel_resid = rs.true_rel_resid;
+            o.model_bytes += rs.model_bytes;
+            o.seconds = rs.seconds;
+            if (rc != KS_SUCCESS && result == KS_SUCCESS) result = rc;
+        }
+    }
+    const double total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int i = 0; i < nshift; ++i) {
+        stats[i].seconds = total;
+        stats[i].model_flops = (double)stats[i].iters * (2 * 1146.0 + 100) * vh;
+    }
+    return result;
+}
+
+}  // namespace ks

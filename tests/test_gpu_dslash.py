@@ -1,0 +1,176 @@
+"""GPU parity of the gauge load, the Dslash and the normal operator against the FP64 oracle,
+through the C ABI.
+
+Tolerances (relative L2 over the output):
+* FP64: 1e-12 (the two sides differ only in summation order; expect ~1e-15).
+* FP32: against the oracle applied to FP32-rounded links and input, 1e-6 (48 products of
+  binary32 numbers summed in binary32: about sqrt(48) * 2^-24 per component); against plain
+  FP64 5e-6.
+* FP16 with per-site FP32 norm: against the oracle on the FP16-rounded links and input,
+  2e-3 (the output is rounded to binary16 relative to its site maximum, unit roundoff 2^-11,
+  plus FP32 sums); against plain FP64 5e-3.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from ksinputs import make_gauge, gaussian_source, GaugeField
+from conftest import rel_l2
+from gpu_util import dev, host, zeros_dev, announce
+
+pytestmark = pytest.mark.gpu
+
+DIMS = [(4, 4, 4, 4), (6, 4, 8, 4), (8, 8, 8, 8), (8, 6, 10, 12), (12, 12, 12, 12),
+        (16, 16, 16, 16)]
+
+
+@pytest.fixture(scope="module")
+def ks():
+    import torch
+    import paper_1611_00728_amd as ks
+    assert torch.cuda.is_available()
+    return ks
+
+
+_cache = {}
+
+
+def loaded(ks, dims, scale=0.5, seed=3):
+    key = (dims, scale, seed)
+    if key not in _cache:
+        g = make_gauge(dims, scale, seed)
+        _cache[key] = (g, ks.Gauge(dims, g.fat, g.naik))
+    return _cache[key]
+
+
+def run_dslash(ks, G, vh, out_par, psi, prec, recon):
+    inp = ks.Field(G, 1 - out_par, prec).load(dev(psi))
+    out = ks.Field(G, out_par, prec)
+    ks.dslash_eo(G, out, inp, recon)
+    res = zeros_dev((vh, 3))
+    out.store(res)
+    import torch
+    torch.cuda.synchronize()
+    return host(res)
+
+
+@pytest.mark.parametrize("dims", DIMS)
+@pytest.mark.parametrize("recon", [18, 12])
+def test_dslash_f64(ks, dims, recon):
+    announce("dslash f64", dims, recon)
+    g, G = loaded(ks, dims)
+    vh = g.volume // 2
+    for out_par in (0, 1):
+        psi = gaussian_source(vh, 100 + out_par)
+        got = run_dslash(ks, G, vh, out_par, psi, ks.F64, recon)
+        ref = oracle.dslash_eo(g, out_par, psi)
+        assert rel_l2(got, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 4, 8, 4), (12, 12, 12, 12)])
+@pytest.mark.parametrize("recon", [18, 12])
+def test_dslash_f32(ks, dims, recon):
+    announce("dslash f32", dims, recon)
+    g, G = loaded(ks, dims)
+    vh = g.volume // 2
+    q = GaugeField(g.dims, oracle.quantise_f32(g.fat), oracle.quantise_f32(g.naik))
+    for out_par in (0, 1):
+        psi = gaussian_source(vh, 200 + out_par)
+        got = run_dslash(ks, G, vh, out_par, psi, ks.F32, recon)
+        ref = oracle.dslash_eo(g, out_par, psi)
+        if recon == 18:
+            refq = oracle.dslash_eo(q, out_par, oracle.quantise_f32(psi))
+            assert rel_l2(got, refq) <= 1e-6
+        assert rel_l2(got, ref) <= 5e-6
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 4, 8, 4), (12, 12, 12, 12)])
+@pytest.mark.parametrize("recon", [18, 12])
+def test_dslash_f16(ks, dims, recon):
+    announce("dslash f16", dims, recon)
+    g, G = loaded(ks, dims)
+    vh = g.volume // 2
+    q = GaugeField(g.dims, oracle.quantise_f16_links(g.fat), oracle.quantise_f16_links(g.naik))
+    for out_par in (0, 1):
+        psi = gaussian_source(vh, 300 + out_par) * np.geomspace(1e-3, 10, vh)[:, None]
+        got = run_dslash(ks, G, vh, out_par, psi, ks.F16, recon)
+        ref = oracle.dslash_eo(g, out_par, psi)
+        if recon == 18:
+            refq = oracle.dslash_eo(q, out_par, oracle.quantise_f16_sites(psi))
+            assert rel_l2(got, refq) <= 2e-3
+        assert rel_l2(got, ref) <= 5e-3
+
+
+def test_field_roundtrip_exact(ks):
+    """FP64 import/export is the identity; FP32 and FP16 reproduce the oracle's rounding."""
+    announce("field roundtrip")
+    g, G = loaded(ks, (6, 4, 8, 4))
+    vh = g.volume // 2
+    v = gaussian_source(vh, 9) * np.geomspace(1e-4, 1e2, vh)[:, None]
+    import torch
+    for prec, ref, tol in ((ks.F64, v, 0.0), (ks.F32, oracle.quantise_f32(v), 0.0),
+                           (ks.F16, oracle.quantise_f16_sites(v), 2.0 ** -11)):
+        f = ks.Field(G, 0, prec).load(dev(v))
+        out = zeros_dev((vh, 3))
+        f.store(out)
+        torch.cuda.synchronize()
+        got = host(out)
+        if tol == 0.0:
+            assert np.array_equal(got, ref)
+        else:
+            n = np.max(np.abs(np.stack([v.real, v.imag], -1).reshape(vh, 6)), axis=1)
+            assert np.all(np.abs(got - ref) <= 2 * tol * n[:, None])
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (8, 6, 10, 12), (16, 16, 16, 16)])
+def test_apply_A_f64(ks, dims):
+    announce("apply_A f64", dims)
+    g, G = loaded(ks, dims)
+    vh = g.volume // 2
+    x = gaussian_source(vh, 400)
+    out = zeros_dev((vh, 3))
+    for sigma in (4 * 0.1 ** 2, 0.0, 1.7):
+        ks.apply_A(G, sigma, dev(x), out)
+        import torch
+        torch.cuda.synchronize()
+        assert rel_l2(host(out), oracle.apply_A(g, sigma, x)) <= 1e-12
+
+
+def test_recon12_rejects_non_su3(ks):
+    """12-real storage of a Naik field that is not c * phase * SU(3) is refused."""
+    announce("recon12 reject")
+    g = make_gauge((4, 4, 4, 4), 0.5, 5)
+    G = ks.Gauge(g.dims, g.fat, g.fat)   # fat links are not SU(3) times a scalar
+    with pytest.raises(ks.KSError) as e:
+        G.prepare(ks.F64, 12)
+    assert e.value.code == -4
+    # the 18-real path still works on it
+    G.prepare(ks.F64, 18)
+
+
+def test_dslash_argument_errors(ks):
+    announce("dslash argument errors")
+    g, G = loaded(ks, (4, 4, 4, 4))
+    a = ks.Field(G, 0, ks.F64)
+    b = ks.Field(G, 0, ks.F64)
+    c = ks.Field(G, 1, ks.F32)
+    for out, inp in ((a, b), (a, a), (a, c)):
+        with pytest.raises(ks.KSError) as e:
+            ks.dslash_eo(G, out, inp)
+        assert e.value.code == -1
+
+
+def test_dslash_full_size_32(ks):
+    """32^4 (the benchmark lattice), FP64 and FP32, both parities, every site."""
+    announce("dslash 32^4")
+    dims = (32, 32, 32, 32)
+    g, G = loaded(ks, dims, 0.5, 1002)
+    vh = g.volume // 2
+    psi = gaussian_source(vh, 2002)
+    for out_par in (0, 1):
+        ref = oracle.dslash_eo(g, out_par, psi)
+        assert rel_l2(run_dslash(ks, G, vh, out_par, psi, ks.F64, 18), ref) <= 1e-12
+        assert rel_l2(run_dslash(ks, G, vh, out_par, psi, ks.F64, 12), ref) <= 1e-12
+        assert rel_l2(run_dslash(ks, G, vh, out_par, psi, ks.F32, 18), ref) <= 5e-6
+        assert rel_l2(run_dslash(ks, G, vh, out_par, psi, ks.F16, 12), ref) <= 5e-3
+    _cache.pop((dims, 0.5, 1002))

@@ -1,0 +1,156 @@
+"""GPU CG and multi-shift CG through the C ABI, judged by the FP64 oracle on the CPU:
+
+* the true relative residual |b - A x| / |b| of the returned x, recomputed by the oracle's
+  operator, must be <= the requested tolerance;
+* the solution must agree with the oracle's own CG solution within 2 tol kappa, kappa taken
+  from the oracle's Lanczos estimate (a solution with residual <= tol is within tol kappa of
+  the exact one, for both sides).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from ksinputs import make_gauge, gaussian_source, SEEDS
+from conftest import rel_l2
+from gpu_util import dev, host, zeros_dev, announce
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ks():
+    import torch
+    import paper_1611_00728_amd as ks
+    assert torch.cuda.is_available()
+    return ks
+
+
+@pytest.fixture(scope="module")
+def cfg1(ks):
+    """8^4, s = 0.3, m = 0.1: the small plain-FP64 workload."""
+    g = make_gauge((8, 8, 8, 8), 0.3, SEEDS["gauge"](1))
+    b = gaussian_source(g.volume // 2, SEEDS["source"](1))
+    x, info = oracle.cg(g, 4 * 0.1 ** 2, b, 1e-12)
+    lo, hi = oracle.lanczos_extremes(info.alpha, info.beta)
+    return g, ks.Gauge(g.dims, g.fat, g.naik), b, x, hi / lo
+
+
+def true_rel(g, sigma, b, x):
+    return float(np.linalg.norm(b - oracle.apply_A(g, sigma, x)) / np.linalg.norm(b))
+
+
+def solve(ks, G, mass, b, x0=None, **kw):
+    import torch
+    xd = zeros_dev(b.shape) if x0 is None else dev(x0)
+    res = ks.cg_solve(G, mass, dev(b), xd, ks.default_params(**kw), raise_on_error=False)
+    torch.cuda.synchronize()
+    return host(xd), res
+
+
+@pytest.mark.parametrize("inner,recon", [("f64", 18), ("f64", 12), ("f32", 18), ("f32", 12),
+                                         ("f16", 18), ("f16", 12)])
+def test_cg_config1(ks, cfg1, inner, recon):
+    announce("cg 8^4", inner, recon)
+    g, G, b, xo, kappa = cfg1
+    x, res = solve(ks, G, 0.1, b, tol=1e-10, inner=inner, recon=recon, check_every=8)
+    assert res.ok, res
+    tr = true_rel(g, 0.04, b, x)
+    assert tr <= 1e-10
+    assert abs(res.stats["true_rel_resid"] - tr) <= 1e-3 * tr + 1e-15
+    assert rel_l2(x, xo) <= 2 * 1e-10 * kappa
+    if inner != "f64":
+        assert res.stats["reliable_updates"] >= 1
+
+
+def test_cg_f64_iterations_match_oracle(ks, cfg1):
+    """FP64 GPU CG takes the oracle's iteration count (rounding order aside)."""
+    g, G, b, _, _ = cfg1
+    announce("cg iteration count")
+    _, info = oracle.cg(g, 0.04, b, 1e-10)
+    x, res = solve(ks, G, 0.1, b, tol=1e-10, check_every=1)
+    assert abs(res.stats["iters"] - info.iters) <= 1
+
+
+def test_cg_initial_guess(ks, cfg1):
+    g, G, b, xo, _ = cfg1
+    announce("cg initial guess")
+    x, res = solve(ks, G, 0.1, b, x0=xo, tol=1e-10)
+    assert res.ok and res.stats["iters"] <= 2
+    x, res = solve(ks, G, 0.1, b, x0=0.5 * xo, tol=1e-10)
+    assert res.ok and true_rel(g, 0.04, b, x) <= 1e-10
+
+
+def test_cg_zero_source(ks, cfg1):
+    g, G, b, _, _ = cfg1
+    announce("cg zero source")
+    x, res = solve(ks, G, 0.1, np.zeros_like(b), x0=b)
+    assert res.ok and np.all(x == 0)
+
+
+def test_cg_not_converged(ks, cfg1):
+    g, G, b, _, _ = cfg1
+    announce("cg max_iter")
+    x, res = solve(ks, G, 0.1, b, tol=1e-10, max_iter=5, check_every=2)
+    assert res.status == -5
+    assert res.stats["iters"] == 5
+    assert abs(res.stats["true_rel_resid"] - true_rel(g, 0.04, b, x)) <= 1e-6
+
+
+def test_cg_nonfinite_source(ks, cfg1):
+    g, G, b, _, _ = cfg1
+    announce("cg nonfinite")
+    bad = b.copy()
+    bad[3, 1] = np.nan
+    x, res = solve(ks, G, 0.1, bad, tol=1e-10)
+    assert res.status == -7
+
+
+@pytest.mark.parametrize("dims", [(6, 4, 8, 4), (12, 12, 12, 12)])
+def test_cg_ragged_lattices(ks, dims):
+    announce("cg ragged", dims)
+    g = make_gauge(dims, 0.5, 31)
+    G = ks.Gauge(dims, g.fat, g.naik)
+    b = gaussian_source(g.volume // 2, 32)
+    for inner in ("f64", "f32", "f16"):
+        x, res = solve(ks, G, 0.05, b, tol=1e-10, inner=inner, recon=12)
+        assert res.ok and true_rel(g, 0.01, b, x) <= 1e-10
+
+
+@pytest.mark.parametrize("inner", ["f64", "f32"])
+def test_multishift(ks, cfg1, inner):
+    announce("multishift 8^4", inner)
+    g, G, b, _, _ = cfg1
+    masses = np.geomspace(0.002, 0.5, 9)
+    sig = 4 * masses ** 2
+    xs = [zeros_dev(b.shape) for _ in sig]
+    rc, stats = ks.multishift_cg_solve(G, sig, dev(b), xs, 1e-9,
+                                       ks.default_params(inner=ks.PREC[inner], check_every=4),
+                                       raise_on_error=False)
+    assert rc == 0
+    xo, _, _, st = oracle.multishift_cg(g, sig, b, 1e-11)
+    for i, s in enumerate(sig):
+        x = host(xs[i])
+        tr = true_rel(g, s, b, x)
+        assert tr <= 1e-9, (i, tr)
+        assert abs(stats[i]["true_rel_resid"] - tr) <= 1e-3 * tr + 1e-15
+        # -D_eo D_oe is positive semi-definite with norm below 16, so kappa_i <= (16 + s) / s
+        assert rel_l2(x, xo[i]) <= 2e-9 * (16.0 + s) / s
+
+
+def test_multishift_single_shift_equals_cg(ks, cfg1):
+    announce("multishift one shift")
+    g, G, b, _, _ = cfg1
+    xs = [zeros_dev(b.shape)]
+    rc, stats = ks.multishift_cg_solve(G, [0.04], dev(b), xs, 1e-10)
+    x, res = solve(ks, G, 0.1, b, tol=1e-10)
+    assert rc == 0 and abs(stats[0]["iters"] - res.stats["iters"]) <= 1
+    assert rel_l2(host(xs[0]), x) <= 1e-8
+
+
+def test_multishift_argument_errors(ks, cfg1):
+    g, G, b, _, _ = cfg1
+    announce("multishift args")
+    with pytest.raises(ks.KSError):
+        ks.multishift_cg_solve(G, [-1.0], dev(b), [zeros_dev(b.shape)], 1e-9)
+    with pytest.raises(ks.KSError):
+        ks.multishift_cg_solve(G, [0.1] * 33, dev(b), [zeros_dev(b.shape)] * 33, 1e-9)
