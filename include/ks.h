@@ -131,6 +131,19 @@ ks_status_t ks_field_export(ks_field_t f, double* dst_dev, hipStream_t stream);
 ks_status_t ks_dslash_eo(ks_gauge_t g, ks_field_t out, ks_field_t in, ks_recon_t recon,
                          hipStream_t stream);
 
+/* Autotuner: times the Dslash of precision `prec` / Naik storage `recon` on this lattice
+ * over candidate launch configurations (64, 128 or 256 threads per block; blocks per CU
+ * capped through the LDS request) and keeps the fastest for every later launch through this
+ * handle (ks_dslash_eo and the solvers).  Untuned variants use 256 threads, no cap.  Allocates
+ * two scratch fields for the duration of the call; synchronises the stream.  Must not be
+ * called while the stream is being captured into a graph. */
+ks_status_t ks_tune_dslash(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, hipStream_t stream);
+
+/* The launch configuration in use for a variant: threads per block, LDS bytes per block and
+ * the tuned time per launch in microseconds (0 if never tuned).  Any output may be NULL. */
+ks_status_t ks_dslash_config(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, int* threads,
+                             int* lds_bytes, float* tuned_us);
+
 /* out_dev = (sigma - D_eo D_oe) in_dev in FP64 on even sites, complex128 [Vh][3] device
  * arrays (in_dev != out_dev).  Asynchronous. */
 ks_status_t ks_apply_A(ks_gauge_t g, double sigma, const double* in_dev, double* out_dev,

@@ -70,6 +70,9 @@ def lib():
         L.ks_field_export.argtypes = [_vp, _vp, _vp]
         L.ks_dslash_eo.argtypes = [_vp, _vp, _vp, C.c_int, _vp]
         L.ks_apply_A.argtypes = [_vp, C.c_double, _vp, _vp, _vp]
+        L.ks_tune_dslash.argtypes = [_vp, C.c_int, C.c_int, _vp]
+        L.ks_dslash_config.argtypes = [_vp, C.c_int, C.c_int, C.POINTER(C.c_int),
+                                       C.POINTER(C.c_int), C.POINTER(C.c_float)]
         L.ks_cg_solve.argtypes = [_vp, C.c_double, _vp, _vp, C.POINTER(SolverParams),
                                   C.POINTER(SolverStats), _vp]
         L.ks_multishift_cg_solve.argtypes = [_vp, C.c_int, C.POINTER(C.c_double), _vp,
@@ -132,6 +135,17 @@ class Gauge:
 
     def prepare(self, prec=F64, recon=RECON_18, stream=None):
         _check(lib().ks_gauge_prepare(self.handle, prec, recon, _stream(stream)))
+
+    def tune(self, prec=F64, recon=RECON_18, stream=None) -> dict:
+        """Autotunes the Dslash launch of one variant; returns its configuration."""
+        _check(lib().ks_tune_dslash(self.handle, prec, recon, _stream(stream)))
+        return self.config(prec, recon)
+
+    def config(self, prec=F64, recon=RECON_18) -> dict:
+        nt, lds, us = C.c_int(), C.c_int(), C.c_float()
+        _check(lib().ks_dslash_config(self.handle, prec, recon, C.byref(nt), C.byref(lds),
+                                      C.byref(us)))
+        return {"threads": nt.value, "lds_bytes": lds.value, "tuned_us": us.value}
 
     def device_bytes(self) -> int:
         return int(lib().ks_gauge_device_bytes(self.handle))

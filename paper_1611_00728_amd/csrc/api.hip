@@ -240,6 +240,30 @@ ks_status_t ks_dslash_eo(ks_gauge_t g, ks_field_t out, ks_field_t in, ks_recon_t
     KS_API_END
 }
 
+ks_status_t ks_tune_dslash(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, hipStream_t stream)
+{
+    KS_API_BEGIN
+    KS_REQUIRE(g, KS_ERR_ARG, "ks_tune_dslash: null handle");
+    KS_REQUIRE(prec_ok(prec) && recon_ok(recon), KS_ERR_ARG, "ks_tune_dslash: bad precision/recon");
+    dslash_tune(g, prec, recon, stream);
+    return KS_SUCCESS;
+    KS_API_END
+}
+
+ks_status_t ks_dslash_config(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, int* threads,
+                             int* lds_bytes, float* tuned_us)
+{
+    KS_API_BEGIN
+    KS_REQUIRE(g, KS_ERR_ARG, "ks_dslash_config: null handle");
+    KS_REQUIRE(prec_ok(prec) && recon_ok(recon), KS_ERR_ARG, "ks_dslash_config: bad precision/recon");
+    const TuneEntry& t = g->tune[prec][recon_index(recon)];
+    if (threads) *threads = t.nt;
+    if (lds_bytes) *lds_bytes = t.lds;
+    if (tuned_us) *tuned_us = t.tuned ? t.us : 0.f;
+    return KS_SUCCESS;
+    KS_API_END
+}
+
 ks_status_t ks_apply_A(ks_gauge_t g, double sigma, const double* in_dev, double* out_dev,
                        hipStream_t stream)
 {

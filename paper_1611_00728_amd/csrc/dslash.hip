@@ -1,9 +1,11 @@
 // Improved-staggered hopping term on one parity (the staggered dslash of Sec. 3):
 //   (D psi)(x) = sum_mu [ V_mu(x) psi(x+mu) - V_mu(x-mu)^+ psi(x-mu)
 //                       + W_mu(x) psi(x+3mu) - W_mu(x-3mu)^+ psi(x-3mu) ]
-// One thread per output site.  The 16 matrices of a site stream from site-major planes
-// (perfectly coalesced, read once: the bulk of the bytes); the 16 neighbour vectors are
-// gathers that the XCD-aware tile order keeps inside one XCD's L2 for most hops.
+// One thread per output site, looping over the site's 16 matrices (one link in flight per
+// thread keeps the kernel under 128 VGPRs, so 4-8 waves per SIMD hide the latency).  Links
+// stream from packed site-major planes (16-byte coalesced loads, read once: the bulk of the
+// bytes); the 16 neighbour vectors are gathers that the XCD-aware tile order keeps inside
+// one XCD's L2 for most hops.
 #include "ks_device.h"
 #include "ks_naik.h"
 
@@ -20,22 +22,10 @@ __device__ __forceinline__ void matvec_acc(cx<R> acc[3], const cx<R> m[9], const
         for (int b = 0; b < 3; ++b) cfma(acc[a], m[a * 3 + b], v[b]);
 }
 
-template <int P>
-__device__ __forceinline__ void load_link18(const void* base, int slot, int vh, int h,
-                                            cx<typename St<P>::R> m[9])
-{
-#pragma unroll
-    for (int e = 0; e < 9; ++e) m[e] = load_entry<P>(plane_ptr<P>(base, slot * 9 + e, vh), h);
-}
-
 // rows 0, 1 stored; row 2 = conj(row0 x row1)
-template <int P>
-__device__ __forceinline__ void load_link12(const void* base, int slot, int vh, int h,
-                                            cx<typename St<P>::R> m[9])
+template <class R>
+__device__ __forceinline__ void reconstruct_row2(cx<R> m[9])
 {
-    using R = typename St<P>::R;
-#pragma unroll
-    for (int e = 0; e < 6; ++e) m[e] = load_entry<P>(plane_ptr<P>(base, slot * 6 + e, vh), h);
     const cx<R> a0 = m[0], a1 = m[1], a2 = m[2], b0 = m[3], b1 = m[4], b2 = m[5];
     cx<R> t;
     t = cmul(a1, b2);
@@ -49,8 +39,8 @@ __device__ __forceinline__ void load_link12(const void* base, int slot, int vh, 
     m[8] = {t.r, -t.i};
 }
 
-template <int P, int RECON, bool XPAY>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void dslash_kernel(Geom g, int par, const void* __restrict__ fat,
+template <int P, int RECON, bool XPAY, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void dslash_kernel(Geom g, int par, const void* __restrict__ fat,
                                                         const void* __restrict__ naik,
                                                         const void* __restrict__ in,
                                                         void* __restrict__ out,
@@ -63,7 +53,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     using R = typename St<P>::R;
     if (gate && *gate) return;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int h = tile * kBlock + threadIdx.x;
+    const int h = tile * NT + threadIdx.x;
     const int vh = g.Vh;
     double dot = 0.0;
     if (h < vh) {
@@ -84,13 +74,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             cx<R> m[9], v[3], t[3] = {{0, 0}, {0, 0}, {0, 0}};
             R sc;
             if (s < 8) {
-                load_link18<P>(fat, s, vh, h, m);
+                load_link<P, 9>(fat, s, vh, h, m);
                 sc = (R)fat_scale;
             } else if (RECON == 12) {
-                load_link12<P>(naik, s - 8, vh, h, m);
+                load_link<P, 6>(naik, s - 8, vh, h, m);
+                reconstruct_row2(m);
                 sc = (R)(naik_c0 * naik_sign(c, s - 8, g.n[3]));
             } else {
-                load_link18<P>(naik, s - 8, vh, h, m);
+                load_link<P, 9>(naik, s - 8, vh, h, m);
                 sc = (R)naik_scale;
             }
             Spinor<P>::load(in, vh, nb[s], v);
@@ -123,44 +114,139 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         }
     }
     if (partials) {
-        const double s = block_sum<kBlock>(dot);
+        const double s = block_sum<NT>(dot);
         if (threadIdx.x == 0) partials[tile] = s;
     }
 }
 
-template <int P, int RECON>
-void launch_p(const LinkStore& st, const Geom& G, double c0, const DslashArgs& a, hipStream_t s)
+template <int P, int RECON, int NT>
+void launch_nt(const LinkStore& st, const Geom& G, double c0, const DslashArgs& a, int lds,
+               hipStream_t s)
 {
-    const int nb = dslash_blocks(G);
+    const int nb = blocks_for(G.Vh, NT);
     const void* fat = st.fat[a.out_parity];
     const void* naik = st.naik[a.out_parity];
     if (a.x)
-        dslash_kernel<P, RECON, true><<<nb, kBlock, 0, s>>>(G, a.out_parity, fat, naik, a.in, a.out,
-                                                            a.x, a.a, a.dot_partials, a.gate,
-                                                            st.fat_scale, st.naik_scale, c0);
+        dslash_kernel<P, RECON, true, NT><<<nb, NT, lds, s>>>(
+            G, a.out_parity, fat, naik, a.in, a.out, a.x, a.a, a.dot_partials, a.gate,
+            st.fat_scale, st.naik_scale, c0);
     else
-        dslash_kernel<P, RECON, false><<<nb, kBlock, 0, s>>>(G, a.out_parity, fat, naik, a.in, a.out,
-                                                             nullptr, 0.0, nullptr, a.gate,
-                                                             st.fat_scale, st.naik_scale, c0);
+        dslash_kernel<P, RECON, false, NT><<<nb, NT, lds, s>>>(
+            G, a.out_parity, fat, naik, a.in, a.out, nullptr, 0.0, nullptr, a.gate,
+            st.fat_scale, st.naik_scale, c0);
     KS_HIP(hipGetLastError());
+}
+
+template <int P, int RECON>
+void launch_p(const LinkStore& st, const Geom& G, double c0, const DslashArgs& a,
+              const TuneEntry& t, hipStream_t s)
+{
+    if (t.nt == 64) launch_nt<P, RECON, 64>(st, G, c0, a, t.lds, s);
+    else if (t.nt == 128) launch_nt<P, RECON, 128>(st, G, c0, a, t.lds, s);
+    else launch_nt<P, RECON, 256>(st, G, c0, a, t.lds, s);
+}
+
+void launch(ks_gauge_t g, ks_prec_t prec, int ri, const DslashArgs& a, const TuneEntry& t,
+            hipStream_t s)
+{
+    const LinkStore& st = g->store[prec][ri];
+    const Geom& G = g->geom;
+    const double c0 = g->naik_c0;
+    if (prec == KS_F64)
+        ri ? launch_p<KS_F64, 12>(st, G, c0, a, t, s) : launch_p<KS_F64, 18>(st, G, c0, a, t, s);
+    else if (prec == KS_F32)
+        ri ? launch_p<KS_F32, 12>(st, G, c0, a, t, s) : launch_p<KS_F32, 18>(st, G, c0, a, t, s);
+    else
+        ri ? launch_p<KS_F16, 12>(st, G, c0, a, t, s) : launch_p<KS_F16, 18>(st, G, c0, a, t, s);
 }
 
 }  // namespace
 
-int dslash_blocks(const Geom& g) { return blocks_for(g.Vh); }
+int dslash_blocks(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon)
+{
+    return blocks_for(g->geom.Vh, g->tune[prec][recon_index(recon)].nt);
+}
+
+int dslash_max_blocks(const Geom& g) { return blocks_for(g.Vh, 64); }
 
 void dslash(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, const DslashArgs& a, hipStream_t s)
 {
     const int ri = recon_index(recon);
     if (!g->store[prec][ri].ready) gauge_prepare(g, prec, recon, s);
-    const LinkStore& st = g->store[prec][ri];
+    launch(g, prec, ri, a, g->tune[prec][ri], s);
+}
+
+// Candidates: 64, 128 or 256 threads per block, each with the number of resident blocks per
+// CU capped through the dynamic LDS request (how many waves share a SIMD also decides how
+// evenly the last round of waves fills the chip).  Each candidate is timed over a few
+// launches with HIP events on this lattice; the fastest is kept for the handle.
+void dslash_tune(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, hipStream_t s)
+{
+    const int ri = recon_index(recon);
+    gauge_prepare(g, prec, recon, s);
+    int dev = 0;
+    KS_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    KS_HIP(hipGetDeviceProperties(&prop, dev));
+    const long lds_cu = prop.maxSharedMemoryPerMultiProcessor > 0
+                            ? (long)prop.maxSharedMemoryPerMultiProcessor
+                            : 65536L;
+    const long lds_blk = (long)prop.sharedMemPerBlock;
     const Geom& G = g->geom;
-    if (prec == KS_F64)
-        ri ? launch_p<KS_F64, 12>(st, G, g->naik_c0, a, s) : launch_p<KS_F64, 18>(st, G, 0.0, a, s);
-    else if (prec == KS_F32)
-        ri ? launch_p<KS_F32, 12>(st, G, g->naik_c0, a, s) : launch_p<KS_F32, 18>(st, G, 0.0, a, s);
-    else
-        ri ? launch_p<KS_F16, 12>(st, G, g->naik_c0, a, s) : launch_p<KS_F16, 18>(st, G, 0.0, a, s);
+    const size_t fb = field_bytes(G, prec);
+    void* in = device_alloc(fb);
+    void* out = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    TuneEntry best;
+    float best_us = 1e30f;
+    try {
+        out = device_alloc(fb);
+        KS_HIP(hipMemsetAsync(in, 0x3f, fb, s));
+        KS_HIP(hipEventCreate(&e0));
+        KS_HIP(hipEventCreate(&e1));
+        DslashArgs a;
+        a.out_parity = 0;
+        a.in = in;
+        a.out = out;
+        for (int nt : {64, 128, 256}) {
+            for (int blocks_cu : {0, 2, 3, 4, 5, 6, 8, 10, 12, 16, 20, 24, 32}) {
+                TuneEntry t;
+                t.nt = nt;
+                if (blocks_cu > 0) {
+                    long l = lds_cu / blocks_cu - 256;
+                    l -= l % 256;
+                    if (l <= 0 || l > lds_blk) continue;
+                    t.lds = (int)l;
+                }
+                for (int k = 0; k < 2; ++k) launch(g, prec, ri, a, t, s);
+                const int reps = 5;
+                KS_HIP(hipEventRecord(e0, s));
+                for (int k = 0; k < reps; ++k) launch(g, prec, ri, a, t, s);
+                KS_HIP(hipEventRecord(e1, s));
+                KS_HIP(hipEventSynchronize(e1));
+                float ms = 0.f;
+                KS_HIP(hipEventElapsedTime(&ms, e0, e1));
+                const float us = ms * 1e3f / reps;
+                if (us < best_us) {
+                    best_us = us;
+                    best = t;
+                }
+            }
+        }
+    } catch (...) {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        device_free(in);
+        device_free(out);
+        throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    device_free(in);
+    device_free(out);
+    best.us = best_us;
+    best.tuned = true;
+    g->tune[prec][ri] = best;
 }
 
 }  // namespace ks

@@ -54,23 +54,37 @@ __global__ __launch_bounds__(kBlock) void layout_f64_kernel(Geom g, int par,
     }
 }
 
-__global__ void to_f32_kernel(const double2* __restrict__ in, float2* __restrict__ out, size_t n)
+// FP64 planes [8 slots][N][Vh] -> packed planes of precision P (value * scale).
+template <int P, int N>
+__global__ __launch_bounds__(kBlock) void pack_kernel(const double2* __restrict__ src,
+                                                      char* __restrict__ dst, int vh,
+                                                      double scale)
 {
-    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n;
-         k += (size_t)gridDim.x * blockDim.x) {
-        const double2 v = in[k];
-        out[k] = make_float2((float)v.x, (float)v.y);
-    }
+    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= vh) return;
+    using LP = LinkPack<P, N>;
+    for (int slot = 0; slot < 8; ++slot)
+        for (int e = 0; e < N; ++e) {
+            const double2 v = src[(size_t)(slot * N + e) * vh + h];
+            char* d = dst + LP::offset(slot, e, vh, h);
+            if constexpr (P == KS_F64)
+                *reinterpret_cast<double2*>(d) = make_double2(v.x * scale, v.y * scale);
+            else if constexpr (P == KS_F32)
+                *reinterpret_cast<float2*>(d) = make_float2((float)(v.x * scale), (float)(v.y * scale));
+            else
+                *reinterpret_cast<unsigned*>(d) = pack_half2_from_double(v.x * scale, v.y * scale);
+        }
 }
 
-__global__ void to_f16_kernel(const double2* __restrict__ in, unsigned* __restrict__ out, size_t n,
-                              double scale)
+template <int N>
+void pack(ks_prec_t p, const double2* src, void* dst, int vh, double scale, hipStream_t s)
 {
-    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n;
-         k += (size_t)gridDim.x * blockDim.x) {
-        const double2 v = in[k];
-        out[k] = pack_half2_from_double(v.x * scale, v.y * scale);
-    }
+    const int nb = blocks_for(vh);
+    char* d = static_cast<char*>(dst);
+    if (p == KS_F64) pack_kernel<KS_F64, N><<<nb, kBlock, 0, s>>>(src, d, vh, scale);
+    else if (p == KS_F32) pack_kernel<KS_F32, N><<<nb, kBlock, 0, s>>>(src, d, vh, scale);
+    else pack_kernel<KS_F16, N><<<nb, kBlock, 0, s>>>(src, d, vh, scale);
+    KS_HIP(hipGetLastError());
 }
 
 __global__ __launch_bounds__(kBlock) void absmax_kernel(const double* __restrict__ in, size_t n,
@@ -96,10 +110,9 @@ __device__ __forceinline__ double zabs(zd a) { return sqrt(a.r * a.r + a.i * a.i
 
 // 12-real Naik store from the FP64 Naik planes: rows 0 and 1 of U = L / s, s the scale of
 // the slot at the site; per-block maximum of the SU(3) defect |U U^+ - 1|, |det U - 1|.
-template <int P>
 __global__ __launch_bounds__(kBlock) void recon12_kernel(Geom g, int par,
                                                          const double2* __restrict__ naik,
-                                                         void* __restrict__ out, double c0,
+                                                         double2* __restrict__ out, double c0,
                                                          double* __restrict__ partials)
 {
     const int h = blockIdx.x * blockDim.x + threadIdx.x;
@@ -126,26 +139,13 @@ __global__ __launch_bounds__(kBlock) void recon12_kernel(Geom g, int par,
                                 zmul(u[0][2], zsub(zmul(u[1][0], u[2][1]), zmul(u[1][1], u[2][0]))));
             defect = fmax(defect, zabs(zsub(det, zd{1.0, 0.0})));
             for (int e = 0; e < 6; ++e) {
-                const size_t o = (size_t)(s * 6 + e) * g.Vh + h;
                 const zd v = u[e / 3][e % 3];
-                if (P == KS_F64) {
-                    static_cast<double2*>(out)[o] = make_double2(v.r, v.i);
-                } else if (P == KS_F32) {
-                    static_cast<float2*>(out)[o] = make_float2((float)v.r, (float)v.i);
-                } else {
-                    static_cast<unsigned*>(out)[o] = pack_half2_from_double(v.r, v.i);
-                }
+                out[(size_t)(s * 6 + e) * g.Vh + h] = make_double2(v.r, v.i);
             }
         }
     }
     defect = block_max<kBlock>(defect);
     if (threadIdx.x == 0) partials[blockIdx.x] = defect;
-}
-
-int stream_blocks(size_t n)
-{
-    const size_t b = (n + kBlock - 1) / kBlock;
-    return (int)(b < 16384 ? b : 16384);
 }
 
 double device_absmax(const double* data, size_t n, hipStream_t s)
@@ -230,16 +230,7 @@ void gauge_prepare(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, hipStream_t s
         for (int par = 0; par < 2; ++par) {
             base.fat[par] = device_alloc(n18 * entry_bytes(prec));
             base.bytes += n18 * entry_bytes(prec);
-            const double2* src = static_cast<const double2*>(m.fat[par]);
-            if (prec == KS_F32)
-                to_f32_kernel<<<stream_blocks(n18), kBlock, 0, s>>>(
-                    src, static_cast<float2*>(base.fat[par]), n18);
-            else if (prec == KS_F16)
-                to_f16_kernel<<<stream_blocks(n18), kBlock, 0, s>>>(
-                    src, static_cast<unsigned*>(base.fat[par]), n18, fs);
-            else
-                KS_HIP(hipMemcpyAsync(base.fat[par], src, n18 * 16, hipMemcpyDeviceToDevice, s));
-            KS_HIP(hipGetLastError());
+            pack<9>(prec, static_cast<const double2*>(m.fat[par]), base.fat[par], G.Vh, fs, s);
         }
         base.fat_scale = (float)(1.0 / fs);
     }
@@ -264,14 +255,7 @@ void gauge_prepare(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, hipStream_t s
             }
             st.naik[par] = device_alloc(n18 * entry_bytes(prec));
             st.bytes += n18 * entry_bytes(prec);
-            const double2* src = static_cast<const double2*>(m.naik[par]);
-            if (prec == KS_F32)
-                to_f32_kernel<<<stream_blocks(n18), kBlock, 0, s>>>(
-                    src, static_cast<float2*>(st.naik[par]), n18);
-            else
-                to_f16_kernel<<<stream_blocks(n18), kBlock, 0, s>>>(
-                    src, static_cast<unsigned*>(st.naik[par]), n18, ns);
-            KS_HIP(hipGetLastError());
+            pack<9>(prec, static_cast<const double2*>(m.naik[par]), st.naik[par], G.Vh, ns, s);
         }
         st.naik_scale = (float)(1.0 / ns);
     } else {
@@ -297,17 +281,16 @@ void gauge_prepare(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, hipStream_t s
         double* part = static_cast<double*>(device_alloc(sizeof(double) * (nb + 1)));
         double defect[2] = {0, 0};
         void* outs[2] = {nullptr, nullptr};
+        double2* tmp = nullptr;
         try {
+            if (prec != KS_F64) tmp = static_cast<double2*>(device_alloc(n12 * 16));
             for (int par = 0; par < 2; ++par) {
                 outs[par] = device_alloc(n12 * entry_bytes(prec));
                 const double2* src = static_cast<const double2*>(m.naik[par]);
-                if (prec == KS_F64)
-                    recon12_kernel<KS_F64><<<nb, kBlock, 0, s>>>(G, par, src, outs[par], g->naik_c0, part);
-                else if (prec == KS_F32)
-                    recon12_kernel<KS_F32><<<nb, kBlock, 0, s>>>(G, par, src, outs[par], g->naik_c0, part);
-                else
-                    recon12_kernel<KS_F16><<<nb, kBlock, 0, s>>>(G, par, src, outs[par], g->naik_c0, part);
+                double2* u = (prec == KS_F64) ? static_cast<double2*>(outs[par]) : tmp;
+                recon12_kernel<<<nb, kBlock, 0, s>>>(G, par, src, u, g->naik_c0, part);
                 KS_HIP(hipGetLastError());
+                if (prec != KS_F64) pack<6>(prec, tmp, outs[par], G.Vh, 1.0, s);
                 reduce_max(part, nb, part + nb, s);
                 KS_HIP(hipMemcpyAsync(&defect[par], part + nb, sizeof(double),
                                       hipMemcpyDeviceToHost, s));
@@ -315,11 +298,13 @@ void gauge_prepare(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, hipStream_t s
             }
         } catch (...) {
             device_free(part);
+            device_free(tmp);
             device_free(outs[0]);
             device_free(outs[1]);
             throw;
         }
         device_free(part);
+        device_free(tmp);
         if (!(defect[0] <= 1e-10 && defect[1] <= 1e-10)) {
             device_free(outs[0]);
             device_free(outs[1]);

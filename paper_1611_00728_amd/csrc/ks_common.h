@@ -68,6 +68,15 @@ struct LinkStore {
 
 struct Workspace;   // solver buffers, solvers.hip
 
+// Launch configuration of one Dslash variant: threads per block and dynamic LDS bytes per
+// block (LDS only limits how many blocks share a CU; the kernel does not use it).
+struct TuneEntry {
+    int nt = 256;
+    int lds = 0;
+    float us = 0.f;     // measured time per launch when tuned
+    bool tuned = false;
+};
+
 }  // namespace ks
 
 struct ks_gauge_s {
@@ -75,6 +84,7 @@ struct ks_gauge_s {
     // [prec][recon: 0 = 18, 1 = 12]
     ks::LinkStore store[3][2];
     double naik_c0 = 0.0;       // real Naik scale c for 12-real storage
+    ks::TuneEntry tune[3][2];   // Dslash launch configuration per [prec][recon]
     ks::Workspace* ws = nullptr;
     size_t extra_bytes = 0;
 };
@@ -209,7 +219,12 @@ struct DslashArgs {
 };
 void dslash(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, const DslashArgs& a,
             hipStream_t s);
-int dslash_blocks(const Geom& g);
+// number of per-block partial sums a Dslash launch of this variant writes
+int dslash_blocks(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon);
+// upper bound of dslash_blocks over every launch configuration
+int dslash_max_blocks(const Geom& g);
+// times the candidate launch configurations on this lattice and keeps the fastest
+void dslash_tune(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, hipStream_t s);
 
 // Field conversions between complex128 [Vh][3] (AoS) and the internal layouts.
 void import_field(const Geom& g, ks_prec_t prec, const double* src, void* dst, hipStream_t s);

@@ -64,24 +64,11 @@ __device__ __forceinline__ const void* plane_ptr(const void* base, int plane, in
     return static_cast<const char*>(base) + (size_t)plane * (size_t)vh * EntrySize<P>::value;
 }
 
-template <int P>
-__device__ __forceinline__ cx<typename St<P>::R> load_entry(const void* base, int idx);
-
 typedef double dvec2 __attribute__((ext_vector_type(2)));
 typedef float fvec2 __attribute__((ext_vector_type(2)));
-
-template <>
-__device__ __forceinline__ cx<double> load_entry<KS_F64>(const void* base, int idx)
-{
-    const dvec2 v = __builtin_nontemporal_load(static_cast<const dvec2*>(base) + idx);
-    return {v.x, v.y};
-}
-template <>
-__device__ __forceinline__ cx<float> load_entry<KS_F32>(const void* base, int idx)
-{
-    const fvec2 v = __builtin_nontemporal_load(static_cast<const fvec2*>(base) + idx);
-    return {v.x, v.y};
-}
+typedef float fvec4 __attribute__((ext_vector_type(4)));
+typedef unsigned uvec2 __attribute__((ext_vector_type(2)));
+typedef unsigned uvec4 __attribute__((ext_vector_type(4)));
 
 // binary16 pair (round to nearest even, directly from FP64) packed into 32 bits
 __device__ __forceinline__ unsigned pack_half2_from_double(double a, double b)
@@ -92,19 +79,81 @@ __device__ __forceinline__ unsigned pack_half2_from_double(double a, double b)
     __builtin_memcpy(&ub, &hb, 2);
     return (unsigned)ua | ((unsigned)ub << 16);
 }
-template <>
-__device__ __forceinline__ cx<float> load_entry<KS_F16>(const void* base, int idx)
+
+__device__ __forceinline__ cx<float> half2_to_cx(unsigned u)
 {
-    const unsigned u = __builtin_nontemporal_load(static_cast<const unsigned*>(base) + idx);
     __half2 h;
     __builtin_memcpy(&h, &u, 4);
     const float2 f = __half22float2(h);
     return {f.x, f.y};
 }
 
+// Packed link planes.  Per slot, the N complex entries of a link occupy N * ES * Vh bytes:
+// N / W "vector planes" of 16 bytes per site (W = 16 / ES entries each, site-major), then one
+// plane holding the remaining N % W entries per site.  Every lane of a wave reads 16 bytes (or
+// the remainder) of consecutive sites, so each load is one contiguous, fully used segment.
+template <int P, int N>
+struct LinkPack {
+    static constexpr int ES = (int)EntrySize<P>::value;
+    static constexpr int W = 16 / ES;
+    static constexpr int NF = N / W;
+    static constexpr int NR = N % W;
+    // byte offset of entry e of `slot` at site h
+    __host__ __device__ static size_t offset(int slot, int e, int vh, int h)
+    {
+        const size_t sb = (size_t)slot * N * ES * vh;
+        const int j = e / W, t = e % W;
+        if (j < NF) return sb + (size_t)j * 16 * vh + (size_t)h * 16 + t * ES;
+        return sb + (size_t)NF * 16 * vh + (size_t)h * NR * ES + t * ES;
+    }
+};
+
+template <int P, int N>
+__device__ __forceinline__ void load_link(const void* base, int slot, int vh, int h,
+                                          cx<typename St<P>::R> m[9])
+{
+    using LP = LinkPack<P, N>;
+    const char* sb = static_cast<const char*>(base) + (size_t)slot * N * LP::ES * vh;
+#pragma unroll
+    for (int j = 0; j < LP::NF; ++j) {
+        const char* pl = sb + (size_t)j * 16 * vh;
+        if constexpr (P == KS_F64) {
+            const dvec2 v = __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(pl) + h);
+            m[j] = {v.x, v.y};
+        } else if constexpr (P == KS_F32) {
+            const fvec4 v = __builtin_nontemporal_load(reinterpret_cast<const fvec4*>(pl) + h);
+            m[2 * j] = {v.x, v.y};
+            m[2 * j + 1] = {v.z, v.w};
+        } else {
+            const uvec4 v = __builtin_nontemporal_load(reinterpret_cast<const uvec4*>(pl) + h);
+            m[4 * j] = half2_to_cx(v.x);
+            m[4 * j + 1] = half2_to_cx(v.y);
+            m[4 * j + 2] = half2_to_cx(v.z);
+            m[4 * j + 3] = half2_to_cx(v.w);
+        }
+    }
+    if constexpr (LP::NR > 0) {
+        const char* pl = sb + (size_t)LP::NF * 16 * vh;
+        constexpr int o = LP::NF * LP::W;
+        if constexpr (P == KS_F32) {
+            const fvec2 v = __builtin_nontemporal_load(reinterpret_cast<const fvec2*>(pl) + h);
+            m[o] = {v.x, v.y};
+        } else if constexpr (P == KS_F16 && LP::NR == 1) {
+            const unsigned v = __builtin_nontemporal_load(reinterpret_cast<const unsigned*>(pl) + h);
+            m[o] = half2_to_cx(v);
+        } else if constexpr (P == KS_F16 && LP::NR == 2) {
+            const uvec2 v = __builtin_nontemporal_load(reinterpret_cast<const uvec2*>(pl) + h);
+            m[o] = half2_to_cx(v.x);
+            m[o + 1] = half2_to_cx(v.y);
+        } else {
+            static_assert(P == KS_F16 && LP::NR <= 2, "unsupported link packing");
+        }
+    }
+}
+
 // ---------------------------------------------------------------- colour vectors
 
-// FP64 / FP32: three site-major complex planes [3][Vh].  FP16: one 16-byte record per site,
+// FP64: three site-major complex planes [3][Vh].  FP16: one 16-byte record per site,
 // {FP32 scale n, half2 c0, half2 c1, half2 c2}, value = n * half.
 template <int P>
 struct Spinor;
@@ -131,24 +180,23 @@ struct Spinor<KS_F64> {
     }
 };
 
+// FP32: plane A of float4 (colours 0, 1) then plane B of float2 (colour 2), site-major.
 template <>
 struct Spinor<KS_F32> {
     using R = float;
     __device__ static __forceinline__ void load(const void* b, int vh, int h, cx<R> v[3])
     {
-        const float2* p = static_cast<const float2*>(b);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const float2 t = (p + (size_t)k * vh)[h];
-            v[k] = {t.x, t.y};
-        }
+        const float4 a = static_cast<const float4*>(b)[h];
+        const float2 c = reinterpret_cast<const float2*>(static_cast<const float4*>(b) + vh)[h];
+        v[0] = {a.x, a.y};
+        v[1] = {a.z, a.w};
+        v[2] = {c.x, c.y};
     }
     __device__ static __forceinline__ void round(cx<R>[3]) {}
     __device__ static __forceinline__ void store(void* b, int vh, int h, const cx<R> v[3])
     {
-        float2* p = static_cast<float2*>(b);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) (p + (size_t)k * vh)[h] = make_float2(v[k].r, v[k].i);
+        static_cast<float4*>(b)[h] = make_float4(v[0].r, v[0].i, v[1].r, v[1].i);
+        reinterpret_cast<float2*>(static_cast<float4*>(b) + vh)[h] = make_float2(v[2].r, v[2].i);
     }
 };
 

@@ -294,7 +294,7 @@ ks_status_t multishift_core(ks_gauge_t g, int nshift, const double* sigma, const
         a2.dot_partials = w.partials;
         a2.gate = &st->gate;
         dslash(g, P, RC, a2, s);
-        ms_alpha_kernel<<<1, kFinish, 0, s>>>(w.partials, w.npart, st);
+        ms_alpha_kernel<<<1, kFinish, 0, s>>>(w.partials, dslash_blocks(g, P, RC), st);
         if (P == KS_F64) launch_r<KS_F64>(vh, w.ms_q, w.ms_r, st, w.partials, s);
         else if (P == KS_F32) launch_r<KS_F32>(vh, w.ms_q, w.ms_r, st, w.partials, s);
         else launch_r<KS_F16>(vh, w.ms_q, w.ms_r, st, w.partials, s);

@@ -52,9 +52,10 @@ Workspace& workspace(ks_gauge_t g)
     const int vh = g->geom.Vh;
     if (!w.partials) {
         w.npart = blocks_for(vh);
-        w.partials = static_cast<double*>(device_alloc(sizeof(double) * (w.npart + 64)));
-        w.scal = w.partials + w.npart;
-        w.bytes += sizeof(double) * (w.npart + 64);
+        const int cap = std::max(w.npart, dslash_max_blocks(g->geom));
+        w.partials = static_cast<double*>(device_alloc(sizeof(double) * (cap + 64)));
+        w.scal = w.partials + cap;
+        w.bytes += sizeof(double) * (cap + 64);
         w.st = static_cast<CGState*>(device_alloc(sizeof(CGState)));
         KS_HIP(hipHostMalloc(reinterpret_cast<void**>(&w.st_host), sizeof(CGState)));
         KS_HIP(hipHostMalloc(reinterpret_cast<void**>(&w.host_scal), sizeof(double) * 64));
@@ -216,7 +217,7 @@ ks_status_t cg_core(ks_gauge_t g, double sigma, const double* b, double* x,
         a2.dot_partials = w.partials;
         a2.gate = &w.st->gate;
         dslash(g, P, RC, a2, s);
-        cg_alpha(w.partials, w.npart, w.st, s);
+        cg_alpha(w.partials, dslash_blocks(g, P, RC), w.st, s);
         update_xr(vh, P, x, ps, qs, rs, w.st, w.partials, s);
         cg_beta(w.partials, w.npart, w.st, s);
         xpay(vh, P, rs, ps, w.st, s);

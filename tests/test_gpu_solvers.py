@@ -154,3 +154,29 @@ def test_multishift_argument_errors(ks, cfg1):
         ks.multishift_cg_solve(G, [-1.0], dev(b), [zeros_dev(b.shape)], 1e-9)
     with pytest.raises(ks.KSError):
         ks.multishift_cg_solve(G, [0.1] * 33, dev(b), [zeros_dev(b.shape)] * 33, 1e-9)
+
+
+def test_tuned_launches_keep_results(ks):
+    """After autotuning every Dslash variant (other block sizes, LDS caps, partial counts),
+    the Dslash and the solvers give the same answers."""
+    announce("autotuned launches")
+    dims = (12, 12, 12, 12)
+    g = make_gauge(dims, 0.5, 41)
+    G = ks.Gauge(dims, g.fat, g.naik)
+    vh = g.volume // 2
+    b = gaussian_source(vh, 42)
+    for p in (ks.F64, ks.F32, ks.F16):
+        for r in (18, 12):
+            cfg = G.tune(p, r)
+            assert cfg["threads"] in (64, 128, 256) and cfg["tuned_us"] > 0
+    import torch
+    inp = ks.Field(G, 1, ks.F64).load(dev(b))
+    out = ks.Field(G, 0, ks.F64)
+    ks.dslash_eo(G, out, inp)
+    res = zeros_dev((vh, 3))
+    out.store(res)
+    torch.cuda.synchronize()
+    assert rel_l2(host(res), oracle.dslash_eo(g, 0, b)) <= 1e-12
+    for inner in ("f64", "f32", "f16"):
+        x, r = solve(ks, G, 0.05, b, tol=1e-10, inner=inner, recon=12)
+        assert r.ok and true_rel(g, 0.01, b, x) <= 1e-10
