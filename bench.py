@@ -159,6 +159,58 @@ def main():
         if record:
             times[v].extend(a.elapsed_time(c) * 1e-3 for a, c in evs)
 
+    # batched workload: 64 lattices of three sizes x 4 right-hand sides, FP32 inner iterations
+    from ksinputs import batch_masses, SEEDS
+    bdims = [(8, 8, 8, 8)] * 24 + [(12, 12, 12, 12)] * 24 + [(16, 16, 16, 16)] * 16
+    t1 = time.time()
+    bg = [make_gauge(d, 0.4, SEEDS["batch_gauge"](j)) for j, d in enumerate(bdims)]
+    bmass = batch_masses(len(bdims), 0.01, 0.2, SEEDS["batch_mass"])
+    B = ks.Batch(bdims, [x.fat for x in bg], [x.naik for x in bg], 4, ks.F32)
+    bb = [torch.from_numpy(gaussian_source(x.volume // 2, SEEDS["batch_rhs"](j, r))).cuda()
+          for j, x in enumerate(bg) for r in range(4)]
+    bx = [torch.zeros_like(v) for v in bb]
+    del bg
+    batch_cfg = B.tune()
+    log("batch of %d lattices x 4 RHS ready in %.1f s, schedule %s"
+        % (len(bdims), time.time() - t1, json.dumps(batch_cfg)))
+    batch_runs = []
+
+    def batch_solve(record):
+        for v in bx:
+            v.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rc, st = B.solve(bmass, bb, bx, ks.default_params(tol=TOL, check_every=8))
+        torch.cuda.synchronize()
+        if record:
+            batch_runs.append((time.perf_counter() - t, st))
+
+    # multi-shift workload: 32^3 x 48, nine shifts sigma_i = 4 m_i^2, m_i log-spaced 0.002..0.5
+    t1 = time.time()
+    MS_DIMS = (32, 32, 32, 48)
+    gm = make_gauge(MS_DIMS, 0.5, SEEDS["gauge"](3))
+    GM = ks.Gauge(MS_DIMS, gm.fat, gm.naik)
+    for p_ in (ks.F64, ks.F32):
+        GM.prepare(p_, 18)
+        GM.tune(p_, 18)
+    mb_ = torch.from_numpy(gaussian_source(gm.volume // 2, SEEDS["source"](3))).cuda()
+    ms_sigma = 4 * np.geomspace(0.002, 0.5, 9) ** 2
+    ms_x = [torch.zeros_like(mb_) for _ in ms_sigma]
+    ms_vh = gm.volume // 2
+    del gm
+    log("32^3x48 multi-shift field ready in %.1f s" % (time.time() - t1))
+    ms_runs = {"f64": [], "f32": []}
+
+    def multishift(record):
+        for name, p_ in (("f64", ks.F64), ("f32", ks.F32)):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            rc, st = ks.multishift_cg_solve(GM, ms_sigma, mb_, ms_x, 1e-9,
+                                            ks.default_params(inner=p_, check_every=16))
+            torch.cuda.synchronize()
+            if record:
+                ms_runs[name].append((time.perf_counter() - t, st))
+
     solves = {"f64": [], "f32": [], "f16_r12": []}
     solve_cfg = {"f64": dict(inner=ks.F64, recon=18), "f32": dict(inner=ks.F32, recon=18),
                  "f16_r12": dict(inner=ks.F16, recon=12)}
@@ -166,6 +218,8 @@ def main():
     def step(record):
         for v in variants:
             burst(v, record)
+        batch_solve(record)
+        multishift(record)
         for name, kw in solve_cfg.items():
             xd = torch.zeros_like(bd)
             torch.cuda.synchronize()
@@ -204,6 +258,36 @@ def main():
         tts[name] = {"seconds": med, "iters": st["iters"], "reliable_updates": st["reliable_updates"],
                      "true_rel_resid": st["true_rel_resid"], "speedup_vs_f64": base / med,
                      "model_GBps": st["model_bytes"] / st["seconds"] / 1e9}
+    walls = [w for w, _ in batch_runs]
+    per_solve = [x["seconds"] for _, st in batch_runs for x in st]
+    worst = max(x["true_rel_resid"] for _, st in batch_runs for x in st)
+    batch = {"lattices": "24 x 8^4 + 24 x 12^4 + 16 x 16^4, H scale 0.4, m ~ U[0.01, 0.2]",
+             "rhs_per_lattice": 4, "solves": len(bb), "inner": "f32 + FP64 reliable updates",
+             "wall_seconds": float(np.median(walls)),
+             "solves_per_second": len(bb) / float(np.median(walls)),
+             "p50_seconds_per_solve": float(np.percentile(per_solve, 50)),
+             "p99_seconds_per_solve": float(np.percentile(per_solve, 99)),
+             "max_true_rel_resid": worst,
+             "iters_range": [min(x["iters"] for _, st in batch_runs for x in st),
+                             max(x["iters"] for _, st in batch_runs for x in st)],
+             "schedule": batch_cfg}
+
+    msr = {}
+    for name, rs in ms_runs.items():
+        med = float(np.median([d for d, _ in rs]))
+        st = rs[-1][1]
+        shared = min(x["iters"] for x in st)
+        # model flops: shared steps (two hopping terms, xpay, r update and nine shift
+        # updates per site) plus the per-shift refinement steps of a single-mass CG
+        flops = ms_vh * (shared * (2 * 1146 + 12 + 12 + 9 * 24 + 12) +
+                         sum(x["iters"] - shared for x in st) * (2 * 1146 + 72))
+        msr[name] = {"seconds": med, "shared_iters": shared,
+                     "total_iters_per_shift": [x["iters"] for x in st],
+                     "max_true_rel_resid": max(x["true_rel_resid"] for x in st),
+                     "model_gflops": flops / med / 1e9}
+    msr["lattice"] = list(MS_DIMS)
+    msr["shifts"] = "sigma_i = 4 m_i^2, m_i = geomspace(0.002, 0.5, 9), tol 1e-9 per shift"
+
     # achievable-bandwidth reference: a plain elementwise pass (1 GiB read + 1 GiB written)
     src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
     dst = torch.empty_like(src)
@@ -243,6 +327,8 @@ def main():
                      "copy_GBps": copy_gbps, "frac_of_copy": head["model_GBps"] / copy_gbps},
         "dslash": dsl,
         "time_to_solution": tts,
+        "batch": batch,
+        "multishift": msr,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

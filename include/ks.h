@@ -172,6 +172,56 @@ ks_status_t ks_multishift_cg_solve(ks_gauge_t g, int nshift, const double* sigma
                                    const double* tol, const ks_solver_params* p,
                                    ks_solver_stats* st, hipStream_t stream);
 
+/* ------------------------------------------------------------------ batched solves */
+
+/* Many independent lattices (uneven sizes allowed), each with nrhs right-hand sides, solved
+ * by CG together (the single-mass CG of Sec. 3 applied to a whole batch at once). */
+typedef struct ks_batch_s* ks_batch_t;
+
+typedef struct {
+    int iters;                 /* Krylov steps of this (lattice, RHS) pair */
+    int reliable_updates;      /* FP64 recomputations of r = b - A x */
+    int status;                /* KS_SUCCESS, KS_ERR_NOT_CONVERGED, KS_ERR_BREAKDOWN, ... */
+    double true_rel_resid;     /* FP64 |b - A x| / |b| of the last recomputation */
+    double seconds;            /* device clock from the start of the batch to this pair's
+                                  convergence (-1 if it did not converge) */
+} ks_batch_stats;
+
+/* nlat lattices; dims: nlat x 4 extents (each even, >= 4); fat[l], naik[l]: the links of
+ * lattice l in the layout of ks_gauge_load, host (on_device = 0) or device memory; nrhs: 1, 2
+ * or 4 right-hand sides per lattice; inner: KS_F32 (FP32 inner iterations, FP64 reliable
+ * updates) or KS_F64.  Links are held in the library's per-lattice stores; vectors in arenas
+ * that keep the nrhs values of a site and colour adjacent, so one link load serves all of
+ * them.  Synchronises the stream. */
+ks_status_t ks_batch_create(ks_batch_t* out, int nlat, const int* dims, const double* const* fat,
+                            const double* const* naik, int on_device, int nrhs, ks_prec_t inner,
+                            hipStream_t stream);
+
+/* Solves (4 m_l^2 - D_eo D_oe) x = b for every (lattice l, RHS r) pair, pair index
+ * p = l * nrhs + r.  masses: host [nlat]; b_dev, x_dev: host arrays of nlat*nrhs device
+ * pointers to complex128 [Vh_l][3] (x holds the initial guess, then the solution).  Every pair
+ * has its own CG scalars and reliable updates on the device; the host replays a HIP graph of
+ * p->check_every steps (captured on the first call, replayed by later ones) until every pair
+ * has finished.  st: nlat*nrhs entries.  Returns KS_SUCCESS if every pair reached p->tol, else
+ * the first failing pair's code (all stats filled).  p->inner and p->recon are ignored (the
+ * batch's inner precision and 18-real links are used). */
+ks_status_t ks_batch_solve(ks_batch_t b, const double* masses, const double* const* b_dev,
+                           double* const* x_dev, const ks_solver_params* p, ks_batch_stats* st,
+                           hipStream_t stream);
+
+/* Autotuner of the batch: sites per tile (64, 128, 256) and schedule (one workgroup per tile,
+ * or a persistent grid of 1-8 workgroups per CU striding over the tile table), timed on the
+ * batch's multi-RHS Dslash; the fastest is kept.  Must not run during graph capture. */
+ks_status_t ks_batch_tune(ks_batch_t b, hipStream_t stream);
+
+/* Current schedule: sites per tile, persistent grid size (0 = one workgroup per tile), tuned
+ * time of one multi-RHS Dslash in microseconds (0 if never tuned), wall seconds of the last
+ * ks_batch_solve.  Any output may be NULL. */
+ks_status_t ks_batch_config(ks_batch_t b, int* tile_sites, int* persistent_blocks,
+                            float* tuned_us, double* last_solve_seconds);
+
+ks_status_t ks_batch_free(ks_batch_t b);
+
 /* Message of the calling thread's last failure ("" if none). */
 const char* ks_last_error(void);
 

@@ -44,6 +44,14 @@ class SolverStats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class BatchStats(C.Structure):
+    _fields_ = [("iters", C.c_int), ("reliable_updates", C.c_int), ("status", C.c_int),
+                ("true_rel_resid", C.c_double), ("seconds", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 _vp = C.c_void_p
 
@@ -70,6 +78,16 @@ def lib():
         L.ks_field_export.argtypes = [_vp, _vp, _vp]
         L.ks_dslash_eo.argtypes = [_vp, _vp, _vp, C.c_int, _vp]
         L.ks_apply_A.argtypes = [_vp, C.c_double, _vp, _vp, _vp]
+        L.ks_batch_create.argtypes = [C.POINTER(_vp), C.c_int, C.POINTER(C.c_int),
+                                      C.POINTER(_vp), C.POINTER(_vp), C.c_int, C.c_int,
+                                      C.c_int, _vp]
+        L.ks_batch_solve.argtypes = [_vp, C.POINTER(C.c_double), C.POINTER(_vp),
+                                     C.POINTER(_vp), C.POINTER(SolverParams),
+                                     C.POINTER(BatchStats), _vp]
+        L.ks_batch_tune.argtypes = [_vp, _vp]
+        L.ks_batch_config.argtypes = [_vp, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                      C.POINTER(C.c_float), C.POINTER(C.c_double)]
+        L.ks_batch_free.argtypes = [_vp]
         L.ks_tune_dslash.argtypes = [_vp, C.c_int, C.c_int, _vp]
         L.ks_dslash_config.argtypes = [_vp, C.c_int, C.c_int, C.POINTER(C.c_int),
                                        C.POINTER(C.c_int), C.POINTER(C.c_float)]
@@ -102,6 +120,16 @@ def _dev_ptr(t, what="tensor"):
     return _vp(t.data_ptr())
 
 
+def _dev_vec(t, vh: int, what="vector"):
+    """Device pointer of a one-parity field, checked to hold exactly [vh][3] complex128
+    (the library cannot see array extents)."""
+    p = _dev_ptr(t, what)
+    if t.numel() != 3 * vh:
+        raise ValueError("%s must hold %d complex numbers ([%d][3]), has %d"
+                         % (what, 3 * vh, vh, t.numel()))
+    return p
+
+
 def default_params(**kw) -> SolverParams:
     p = SolverParams()
     lib().ks_default_params(C.byref(p))
@@ -123,6 +151,10 @@ class Gauge:
         self.vh = self.volume // 2
         d = (C.c_int * 4)(*self.dims)
         h = _vp()
+        for a, nm in ((fat, "fat"), (naik, "naik")):
+            n = a.numel() if isinstance(a, torch.Tensor) else np.asarray(a).size
+            if n != 36 * self.volume:
+                raise ValueError("%s links must hold [4][V][3][3] complex numbers" % nm)
         if isinstance(fat, torch.Tensor):
             args = (_dev_ptr(fat, "fat"), _dev_ptr(naik, "naik"), 1)
         else:
@@ -174,11 +206,11 @@ class Field:
         self.prec = prec
 
     def load(self, t, stream=None):
-        _check(lib().ks_field_import(self.handle, _dev_ptr(t), _stream(stream)))
+        _check(lib().ks_field_import(self.handle, _dev_vec(t, self.gauge.vh), _stream(stream)))
         return self
 
     def store(self, t, stream=None):
-        _check(lib().ks_field_export(self.handle, _dev_ptr(t), _stream(stream)))
+        _check(lib().ks_field_export(self.handle, _dev_vec(t, self.gauge.vh), _stream(stream)))
         return t
 
     def free(self):
@@ -198,7 +230,8 @@ def dslash_eo(gauge: Gauge, out: Field, inp: Field, recon: int = RECON_18, strea
 
 
 def apply_A(gauge: Gauge, sigma: float, x, out, stream=None):
-    _check(lib().ks_apply_A(gauge.handle, float(sigma), _dev_ptr(x, "x"), _dev_ptr(out, "out"),
+    _check(lib().ks_apply_A(gauge.handle, float(sigma), _dev_vec(x, gauge.vh, "x"),
+                            _dev_vec(out, gauge.vh, "out"),
                             _stream(stream)))
     return out
 
@@ -218,7 +251,8 @@ def cg_solve(gauge: Gauge, mass: float, b, x, params: SolverParams | None = None
     """(4 m^2 - D_eo D_oe) x = b; x holds the initial guess and receives the solution."""
     p = params if params is not None else default_params()
     st = SolverStats()
-    rc = lib().ks_cg_solve(gauge.handle, float(mass), _dev_ptr(b, "b"), _dev_ptr(x, "x"),
+    rc = lib().ks_cg_solve(gauge.handle, float(mass), _dev_vec(b, gauge.vh, "b"),
+                           _dev_vec(x, gauge.vh, "x"),
                            C.byref(p), C.byref(st), _stream(stream))
     if rc != 0 and raise_on_error:
         _check(rc)
@@ -233,10 +267,74 @@ def multishift_cg_solve(gauge: Gauge, sigmas, b, xs, tols, params: SolverParams 
     sig = (C.c_double * n)(*[float(s) for s in sigmas])
     tl = (C.c_double * n)(*([float(tols)] * n if isinstance(tols, (int, float)) else
                             [float(t) for t in tols]))
-    ptrs = (_vp * n)(*[_dev_ptr(x, "x[%d]" % i).value for i, x in enumerate(xs)])
+    if len(xs) != n:
+        raise ValueError("need one solution vector per shift")
+    ptrs = (_vp * n)(*[_dev_vec(x, gauge.vh, "x[%d]" % i).value for i, x in enumerate(xs)])
     st = (SolverStats * n)()
-    rc = lib().ks_multishift_cg_solve(gauge.handle, n, sig, _dev_ptr(b, "b"), ptrs, tl,
+    rc = lib().ks_multishift_cg_solve(gauge.handle, n, sig, _dev_vec(b, gauge.vh, "b"), ptrs, tl,
                                       C.byref(p), st, _stream(stream))
     if rc != 0 and raise_on_error:
         _check(rc)
     return rc, [s.as_dict() for s in st]
+
+
+class Batch:
+    """Many lattices x nrhs right-hand sides solved together (ks_batch_create / _solve)."""
+
+    def __init__(self, dims_list, fats, naiks, nrhs: int = 4, inner: int = F32, stream=None):
+        import numpy as np
+        n = len(dims_list)
+        self.dims = [tuple(int(x) for x in d) for d in dims_list]
+        self.nrhs = nrhs
+        self.nlat = n
+        d = (C.c_int * (4 * n))(*[x for dd in self.dims for x in dd])
+        host = [np.ascontiguousarray(a, dtype=np.complex128) for a in fats] + \
+               [np.ascontiguousarray(a, dtype=np.complex128) for a in naiks]
+        for k, a in enumerate(host):
+            if a.size != 36 * int(np.prod(self.dims[k % n])):
+                raise ValueError("links of lattice %d must hold [4][V][3][3] complex numbers"
+                                 % (k % n))
+        fp = (_vp * n)(*[h.ctypes.data for h in host[:n]])
+        np_ = (_vp * n)(*[h.ctypes.data for h in host[n:]])
+        h = _vp()
+        _check(lib().ks_batch_create(C.byref(h), n, d, fp, np_, 0, nrhs, inner, _stream(stream)))
+        self.handle = h
+
+    def tune(self, stream=None) -> dict:
+        _check(lib().ks_batch_tune(self.handle, _stream(stream)))
+        return self.config()
+
+    def config(self) -> dict:
+        t, p, us, sec = C.c_int(), C.c_int(), C.c_float(), C.c_double()
+        _check(lib().ks_batch_config(self.handle, C.byref(t), C.byref(p), C.byref(us),
+                                     C.byref(sec)))
+        return {"tile_sites": t.value, "persistent_blocks": p.value, "tuned_us": us.value,
+                "last_solve_seconds": sec.value}
+
+    def solve(self, masses, bs, xs, params: SolverParams | None = None, stream=None,
+              raise_on_error: bool = True):
+        """bs, xs: nlat*nrhs complex128 CUDA tensors, pair p = lattice * nrhs + rhs."""
+        npair = self.nlat * self.nrhs
+        if len(bs) != npair or len(xs) != npair or len(masses) != self.nlat:
+            raise ValueError("need %d masses and %d vectors" % (self.nlat, npair))
+        p = params if params is not None else default_params()
+        m = (C.c_double * self.nlat)(*[float(v) for v in masses])
+        vhs = [int(d[0] * d[1] * d[2] * d[3]) // 2 for d in self.dims for _ in range(self.nrhs)]
+        bp = (_vp * npair)(*[_dev_vec(b, vh, "b").value for b, vh in zip(bs, vhs)])
+        xp = (_vp * npair)(*[_dev_vec(x, vh, "x").value for x, vh in zip(xs, vhs)])
+        st = (BatchStats * npair)()
+        rc = lib().ks_batch_solve(self.handle, m, bp, xp, C.byref(p), st, _stream(stream))
+        if rc != 0 and raise_on_error:
+            _check(rc)
+        return rc, [s.as_dict() for s in st]
+
+    def free(self):
+        if self.handle:
+            _check(lib().ks_batch_free(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

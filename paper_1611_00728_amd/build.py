@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libks.so")
-SOURCES = ["api.hip", "gauge.hip", "dslash.hip", "blas.hip", "solvers.hip", "multishift.hip"]
+SOURCES = ["api.hip", "gauge.hip", "dslash.hip", "blas.hip", "solvers.hip", "multishift.hip",
+           "batch.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall",
          "-Wno-unused-function", "-Wno-unused-parameter",

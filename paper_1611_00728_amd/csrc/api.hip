@@ -5,6 +5,7 @@
 #include <vector>
 
 #include "ks_common.h"
+#include "ks_batch.h"
 #include "ks_solvers.h"
 
 namespace ks {
@@ -331,6 +332,65 @@ ks_status_t ks_multishift_cg_solve(ks_gauge_t g, int nshift, const double* sigma
     for (int i = 0; i < nshift; ++i) export_field(g->geom, KS_F64, xs[i], x_dev[i], stream);
     KS_HIP(hipStreamSynchronize(stream));
     return rc;
+    KS_API_END
+}
+
+ks_status_t ks_batch_create(ks_batch_t* out, int nlat, const int* dims, const double* const* fat,
+                            const double* const* naik, int on_device, int nrhs, ks_prec_t inner,
+                            hipStream_t stream)
+{
+    KS_API_BEGIN
+    KS_REQUIRE(out && dims && fat && naik, KS_ERR_ARG, "ks_batch_create: null argument");
+    *out = nullptr;
+    BatchCtx* c = batch_create(nlat, dims, fat, naik, on_device, nrhs, inner, stream);
+    *out = new ks_batch_s{c};
+    return KS_SUCCESS;
+    KS_API_END
+}
+
+ks_status_t ks_batch_solve(ks_batch_t b, const double* masses, const double* const* b_dev,
+                           double* const* x_dev, const ks_solver_params* p, ks_batch_stats* st,
+                           hipStream_t stream)
+{
+    KS_API_BEGIN
+    KS_REQUIRE(b && b->ctx && masses && b_dev && x_dev && st, KS_ERR_ARG,
+               "ks_batch_solve: null argument");
+    check_params(p);
+    return batch_solve(*b->ctx, masses, b_dev, x_dev, *p, st, stream);
+    KS_API_END
+}
+
+ks_status_t ks_batch_tune(ks_batch_t b, hipStream_t stream)
+{
+    KS_API_BEGIN
+    KS_REQUIRE(b && b->ctx, KS_ERR_ARG, "ks_batch_tune: null handle");
+    batch_tune(*b->ctx, stream);
+    return KS_SUCCESS;
+    KS_API_END
+}
+
+ks_status_t ks_batch_config(ks_batch_t b, int* tile_sites, int* persistent_blocks,
+                            float* tuned_us, double* last_solve_seconds)
+{
+    KS_API_BEGIN
+    KS_REQUIRE(b && b->ctx, KS_ERR_ARG, "ks_batch_config: null handle");
+    const BatchCtx& c = *b->ctx;
+    if (tile_sites) *tile_sites = 64 << c.tile_idx;
+    if (persistent_blocks) *persistent_blocks = c.persistent;
+    if (tuned_us) *tuned_us = c.tuned_us;
+    if (last_solve_seconds) *last_solve_seconds = c.last_seconds;
+    return KS_SUCCESS;
+    KS_API_END
+}
+
+ks_status_t ks_batch_free(ks_batch_t b)
+{
+    KS_API_BEGIN
+    if (!b) return KS_SUCCESS;
+    (void)hipDeviceSynchronize();
+    batch_free(b->ctx);
+    delete b;
+    return KS_SUCCESS;
     KS_API_END
 }
 

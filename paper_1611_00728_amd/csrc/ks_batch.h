@@ -1,0 +1,78 @@
+// Batched multi-lattice, multi-RHS CG: internal state.
+#pragma once
+
+#include <vector>
+
+#include "ks_common.h"
+
+namespace ks {
+
+// One lattice of a batch, as the kernels see it.
+struct LatDesc {
+    Geom g;
+    const void* fat32[2];     // inner-precision link planes per output parity
+    const void* naik32[2];
+    const void* fat64[2];     // FP64 link planes (reliable updates)
+    const void* naik64[2];
+    size_t vec_off;           // site offset of this lattice in every vector arena
+    double sigma;             // 4 m^2 of this lattice
+    int tile_begin, tile_end; // its range in the active tile table
+    int pair0;                // first (lattice, RHS) pair index
+};
+
+// CG scalars of one (lattice, RHS) pair.
+struct BatchPair {
+    double rho, alpha, beta, maxr, stop2, delta, true_r2;
+    unsigned long long t_done;   // device wall clock at convergence
+    int iter, max_iter, ru, done, status, ru_now;
+};
+
+struct BatchCtx {
+    int nrhs = 1;
+    int npairs = 0;
+    ks_prec_t prec = KS_F32;
+    size_t total_vh = 0;
+    std::vector<ks_gauge_t> gauges;
+    std::vector<LatDesc> lats_host;
+    LatDesc* lats_dev = nullptr;
+    std::vector<int2> tile_tables[3];
+    int2* tiles[3] = {nullptr, nullptr, nullptr};
+    int ntiles[3] = {0, 0, 0};
+    int tile_idx = 0;          // 0: 64, 1: 128, 2: 256 sites per tile
+    int persistent = 0;        // >0: grid of this many blocks striding over the tiles
+    float tuned_us = 0.f;
+    double* partials = nullptr;
+    BatchPair* pairs = nullptr;
+    BatchPair* pairs_host = nullptr;
+    unsigned long long* clock = nullptr;
+    int* census = nullptr;
+    int* census_host = nullptr;
+    // vector arenas: inner precision p, q, t (odd), r; FP64 x, b, r, t (odd), A x
+    char *ps = nullptr, *qs = nullptr, *ts = nullptr, *rs = nullptr;
+    char *x64 = nullptr, *b64 = nullptr, *r64 = nullptr, *t64 = nullptr, *ax64 = nullptr;
+    void** io_ptrs = nullptr;  // device table of the caller's per-pair vectors
+    double* b2 = nullptr;      // |b|^2 per pair
+    hipStream_t stream = nullptr;     // the batch's own stream (default priority)
+    hipEvent_t order = nullptr;       // orders it after the caller's stream
+    hipGraphExec_t graph_exec = nullptr;
+    int graph_chunk = 0;
+    double last_seconds = 0.0;
+
+    int grid(int ntiles_now) const;
+    void set_tiles(int k, hipStream_t s);
+};
+
+BatchCtx* batch_create(int nlat, const int* dims, const double* const* fat,
+                       const double* const* naik, int on_device, int nrhs, ks_prec_t inner,
+                       hipStream_t s);
+void batch_free(BatchCtx* c);
+ks_status_t batch_solve(BatchCtx& c, const double* masses, const double* const* b,
+                        double* const* x, const ks_solver_params& prm, ks_batch_stats* stats,
+                        hipStream_t s);
+void batch_tune(BatchCtx& c, hipStream_t s);
+
+}  // namespace ks
+
+struct ks_batch_s {
+    ks::BatchCtx* ctx;
+};
