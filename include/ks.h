@@ -222,6 +222,58 @@ ks_status_t ks_batch_config(ks_batch_t b, int* tile_sites, int* persistent_block
 
 ks_status_t ks_batch_free(ks_batch_t b);
 
+/* ------------------------------------------------------------------ learned preconditioner */
+
+/* A gauge-covariant network used as the preconditioner of flexible CG.  Layer l maps c_in to
+ * c_out channels of colour-vector fields on the full lattice:
+ *     y_c(x) = sum_{c', p} w_{c c' p} (T_p phi_{c'})(x),
+ * nine paths p: the identity (p = 0), T_{+mu} phi(x) = V_mu(x) phi(x+mu) (p = 1+mu) and
+ * T_{-mu} phi(x) = V_mu(x-mu)^+ phi(x-mu) (p = 5+mu), V the fat link of the gauge handle, so
+ * the network commutes with gauge transformations.  Four layers, channels 1, 8, 8, 8, 1, no
+ * activation (the network is linear).  Input: an even-site vector (odd sites zero); output:
+ * the even sites of the last layer.  Weights: KS_NET_WEIGHTS complex numbers, layer after
+ * layer, each layer w[c_out][c_in][9], complex128 (re, im) on the host. */
+#define KS_NET_WEIGHTS 1296
+typedef struct ks_net_s* ks_net_t;
+
+ks_status_t ks_net_create(ks_net_t* out, const double* weights);
+ks_status_t ks_net_set_weights(ks_net_t n, const double* weights);   /* also resets Adam */
+ks_status_t ks_net_get_weights(ks_net_t n, double* weights);
+ks_status_t ks_net_free(ks_net_t n);
+
+/* out_dev = N(in_dev), complex128 [Vh][3] device arrays of the handle's lattice.  use_mfma = 0:
+ * FP32 channel mixing on the vector ALUs; 1: the two 8 -> 8 layers mix on the matrix cores
+ * (binary16 operands, FP32 accumulation).  Transports in FP32 with the FP32 fat links.
+ * Synchronous with respect to `stream` order only (no host wait). */
+ks_status_t ks_net_apply(ks_net_t n, ks_gauge_t g, const double* in_dev, double* out_dev,
+                         int use_mfma, hipStream_t stream);
+
+/* Loss L = (1/B) sum_j |N(b_j) - x_j|^2 / |x_j|^2 over npairs = B pairs (b_j, x_j on lattice
+ * gauges[j], complex128 [Vh_j][3] device arrays) and its gradient, G = dL/dRe w + i dL/dIm w,
+ * written to grad (host, complex128 [KS_NET_WEIGHTS]) when not NULL.  FP32 forward and
+ * backward kernels, FP64 reductions.  Synchronises the stream. */
+ks_status_t ks_net_loss_grad(ks_net_t n, int npairs, const ks_gauge_t* gauges,
+                             const double* const* b_dev, const double* const* x_dev,
+                             double* loss, double* grad, hipStream_t stream);
+
+/* steps Adam steps (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr, on the real and
+ * imaginary parts separately); step k uses the minibatch of `batch` pairs starting at pair
+ * (k * batch) mod npairs, cyclically.  loss_history (host, [steps]) receives the minibatch
+ * loss before each step when not NULL.  Synchronises the stream. */
+ks_status_t ks_net_train(ks_net_t n, int npairs, const ks_gauge_t* gauges,
+                         const double* const* b_dev, const double* const* x_dev, int steps,
+                         int batch, double lr, double* loss_history, hipStream_t stream);
+
+/* Flexible CG for (4 m^2 - D_eo D_oe) x = b preconditioned by the network (z = N(r)), with
+ * the inner operator and vectors in p->inner precision (KS_F16 is taken as KS_F32), x in FP64,
+ * FP64 reliable updates, and fallback to ks_cg_solve's method from the current x when N(r)
+ * is not finite, when Re<N(r), r> <= 0, when |r| has not halved in 50 steps, or at
+ * p->max_iter (st->fallback = 1, st->restarts = steps of the fallback).  b_dev, x_dev as in
+ * ks_cg_solve. */
+ks_status_t ks_fcg_solve(ks_gauge_t g, ks_net_t n, double mass, const double* b_dev,
+                         double* x_dev, const ks_solver_params* p, int use_mfma,
+                         ks_solver_stats* st, hipStream_t stream);
+
 /* Message of the calling thread's last failure ("" if none). */
 const char* ks_last_error(void);
 

@@ -7,7 +7,9 @@ step), so both the FP64 CPU oracle's tests and the GPU path may take their input
 from .gauge import (lattice_coords, lattice_volume, staggered_phase, time_bc_sign,
                     random_su3, thin_links, fat_and_naik, make_gauge, GaugeField)
 from .fields import gaussian_source, gaussian_full, batch_masses, SEEDS
+from .network import net_init_weights, flatten_weights, unflatten_weights
 
 __all__ = ["lattice_coords", "lattice_volume", "staggered_phase", "time_bc_sign", "random_su3",
            "thin_links", "fat_and_naik", "make_gauge", "GaugeField", "gaussian_source",
-           "gaussian_full", "batch_masses", "SEEDS"]
+           "gaussian_full", "batch_masses", "SEEDS", "net_init_weights", "flatten_weights",
+           "unflatten_weights"]

@@ -95,17 +95,10 @@ class Network:
     step: int = 0
 
     @staticmethod
-    def init(seed: int = 5000, channels=CHANNELS) -> "Network":
-        """w ~ CN(0, 1/(9 c_in)) plus 1 on the identity path of the channel diagonal."""
-        rng = np.random.default_rng(seed)
-        ws = []
-        for cin, cout in zip(channels[:-1], channels[1:]):
-            g = rng.standard_normal((cout, cin, NPATH, 2)) * np.sqrt(0.5 / (NPATH * cin))
-            w = g[..., 0] + 1j * g[..., 1]
-            for c in range(min(cin, cout)):
-                w[c, c, 0] += 1.0
-            ws.append(w)
-        return Network(ws)
+    def init(seed: int = 5000) -> "Network":
+        """The seeded initial weights (drawn by the input module)."""
+        from ksinputs import net_init_weights
+        return Network([w.copy() for w in net_init_weights(seed)])
 
     @staticmethod
     def identity(channels=CHANNELS) -> "Network":

@@ -338,3 +338,102 @@ class Batch:
             self.free()
         except Exception:
             pass
+
+
+NET_WEIGHTS = 1296
+
+
+class Net:
+    """The preconditioner network (ks_net_create); weights: complex128 [1296] (layer by layer,
+    each w[c_out][c_in][9])."""
+
+    def __init__(self, weights):
+        import numpy as np
+        w = np.ascontiguousarray(np.asarray(weights, dtype=np.complex128).ravel())
+        if w.size != NET_WEIGHTS:
+            raise ValueError("the network has %d complex weights" % NET_WEIGHTS)
+        L = lib()
+        L.ks_net_create.argtypes = [C.POINTER(_vp), _vp]
+        L.ks_net_set_weights.argtypes = [_vp, _vp]
+        L.ks_net_get_weights.argtypes = [_vp, _vp]
+        L.ks_net_free.argtypes = [_vp]
+        L.ks_net_apply.argtypes = [_vp, _vp, _vp, _vp, C.c_int, _vp]
+        L.ks_net_loss_grad.argtypes = [_vp, C.c_int, C.POINTER(_vp), C.POINTER(_vp),
+                                       C.POINTER(_vp), C.POINTER(C.c_double), _vp, _vp]
+        L.ks_net_train.argtypes = [_vp, C.c_int, C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp),
+                                   C.c_int, C.c_int, C.c_double, _vp, _vp]
+        L.ks_fcg_solve.argtypes = [_vp, _vp, C.c_double, _vp, _vp, C.POINTER(SolverParams),
+                                   C.c_int, C.POINTER(SolverStats), _vp]
+        h = _vp()
+        _check(L.ks_net_create(C.byref(h), _vp(w.ctypes.data)))
+        self.handle = h
+
+    def set_weights(self, weights):
+        import numpy as np
+        w = np.ascontiguousarray(np.asarray(weights, dtype=np.complex128).ravel())
+        if w.size != NET_WEIGHTS:
+            raise ValueError("the network has %d complex weights" % NET_WEIGHTS)
+        _check(lib().ks_net_set_weights(self.handle, _vp(w.ctypes.data)))
+
+    def get_weights(self):
+        import numpy as np
+        w = np.zeros(NET_WEIGHTS, dtype=np.complex128)
+        _check(lib().ks_net_get_weights(self.handle, _vp(w.ctypes.data)))
+        return w
+
+    def apply(self, gauge: Gauge, x, out, mfma: bool = False, stream=None):
+        _check(lib().ks_net_apply(self.handle, gauge.handle, _dev_vec(x, gauge.vh, "x"),
+                                  _dev_vec(out, gauge.vh, "out"), int(bool(mfma)),
+                                  _stream(stream)))
+        return out
+
+    @staticmethod
+    def _pairs(gauges, bs, xs):
+        n = len(gauges)
+        if len(bs) != n or len(xs) != n:
+            raise ValueError("one gauge, source and solution per pair")
+        gp = (_vp * n)(*[g.handle.value for g in gauges])
+        bp = (_vp * n)(*[_dev_vec(b, g.vh, "b").value for b, g in zip(bs, gauges)])
+        xp = (_vp * n)(*[_dev_vec(x, g.vh, "x").value for x, g in zip(xs, gauges)])
+        return n, gp, bp, xp
+
+    def loss_grad(self, gauges, bs, xs, stream=None):
+        import numpy as np
+        n, gp, bp, xp = self._pairs(gauges, bs, xs)
+        loss = C.c_double()
+        grad = np.zeros(NET_WEIGHTS, dtype=np.complex128)
+        _check(lib().ks_net_loss_grad(self.handle, n, gp, bp, xp, C.byref(loss),
+                                      _vp(grad.ctypes.data), _stream(stream)))
+        return loss.value, grad
+
+    def train(self, gauges, bs, xs, steps: int, batch: int, lr: float = 1e-3, stream=None):
+        import numpy as np
+        n, gp, bp, xp = self._pairs(gauges, bs, xs)
+        hist = np.zeros(max(steps, 1))
+        _check(lib().ks_net_train(self.handle, n, gp, bp, xp, int(steps), int(batch), float(lr),
+                                  _vp(hist.ctypes.data), _stream(stream)))
+        return hist[:steps]
+
+    def free(self):
+        if self.handle:
+            _check(lib().ks_net_free(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def fcg_solve(gauge: Gauge, net: Net, mass: float, b, x, params: SolverParams | None = None,
+              mfma: bool = False, stream=None, raise_on_error: bool = True) -> SolveResult:
+    """Flexible CG for (4 m^2 - D_eo D_oe) x = b preconditioned by `net`."""
+    p = params if params is not None else default_params()
+    st = SolverStats()
+    rc = lib().ks_fcg_solve(gauge.handle, net.handle, float(mass), _dev_vec(b, gauge.vh, "b"),
+                            _dev_vec(x, gauge.vh, "x"), C.byref(p), int(bool(mfma)),
+                            C.byref(st), _stream(stream))
+    if rc != 0 and raise_on_error:
+        _check(rc)
+    return SolveResult(rc, st.as_dict())

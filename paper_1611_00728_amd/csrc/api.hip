@@ -6,6 +6,7 @@
 
 #include "ks_common.h"
 #include "ks_batch.h"
+#include "ks_net.h"
 #include "ks_solvers.h"
 
 namespace ks {
@@ -153,6 +154,7 @@ ks_status_t ks_gauge_free(ks_gauge_t g)
     KS_API_BEGIN
     if (!g) return KS_SUCCESS;
     (void)hipDeviceSynchronize();
+    fcg_release(g);
     workspace_free(g->ws);
     g->ws = nullptr;
     gauge_release(g);
@@ -380,6 +382,132 @@ ks_status_t ks_batch_config(ks_batch_t b, int* tile_sites, int* persistent_block
     if (tuned_us) *tuned_us = c.tuned_us;
     if (last_solve_seconds) *last_solve_seconds = c.last_seconds;
     return KS_SUCCESS;
+    KS_API_END
+}
+
+ks_status_t ks_net_create(ks_net_t* out, const double* weights)
+{
+    KS_API_BEGIN
+    KS_REQUIRE(out && weights, KS_ERR_ARG, "ks_net_create: null argument");
+    *out = nullptr;
+    NetCtx* n = net_create(weights);
+    *out = new ks_net_s{n};
+    return KS_SUCCESS;
+    KS_API_END
+}
+
+ks_status_t ks_net_set_weights(ks_net_t n, const double* weights)
+{
+    KS_API_BEGIN
+    KS_REQUIRE(n && n->ctx && weights, KS_ERR_ARG, "ks_net_set_weights: null argument");
+    net_set_weights(*n->ctx, weights, nullptr);
+    return KS_SUCCESS;
+    KS_API_END
+}
+
+ks_status_t ks_net_get_weights(ks_net_t n, double* weights)
+{
+    KS_API_BEGIN
+    KS_REQUIRE(n && n->ctx && weights, KS_ERR_ARG, "ks_net_get_weights: null argument");
+    net_get_weights(*n->ctx, weights, nullptr);
+    return KS_SUCCESS;
+    KS_API_END
+}
+
+ks_status_t ks_net_free(ks_net_t n)
+{
+    KS_API_BEGIN
+    if (!n) return KS_SUCCESS;
+    (void)hipDeviceSynchronize();
+    net_free(n->ctx);
+    delete n;
+    return KS_SUCCESS;
+    KS_API_END
+}
+
+ks_status_t ks_net_apply(ks_net_t n, ks_gauge_t g, const double* in_dev, double* out_dev,
+                         int use_mfma, hipStream_t stream)
+{
+    KS_API_BEGIN
+    KS_REQUIRE(n && n->ctx && g && in_dev && out_dev, KS_ERR_ARG, "ks_net_apply: null argument");
+    KS_REQUIRE(in_dev != out_dev, KS_ERR_ARG, "ks_net_apply: out aliases in");
+    if (use_mfma) net_apply_mfma(*n->ctx, g, in_dev, out_dev, 1.0, stream);
+    else net_apply_f32(*n->ctx, g, in_dev, out_dev, 1.0, stream);
+    return KS_SUCCESS;
+    KS_API_END
+}
+
+static void check_pairs(int npairs, const ks_gauge_t* gauges, const double* const* b,
+                        const double* const* x)
+{
+    KS_REQUIRE(npairs >= 1 && gauges && b && x, KS_ERR_ARG, "network: bad training pairs");
+    for (int j = 0; j < npairs; ++j)
+        KS_REQUIRE(gauges[j] && b[j] && x[j], KS_ERR_ARG, "network: null entry in pair %d", j);
+}
+
+ks_status_t ks_net_loss_grad(ks_net_t n, int npairs, const ks_gauge_t* gauges,
+                             const double* const* b_dev, const double* const* x_dev,
+                             double* loss, double* grad, hipStream_t stream)
+{
+    KS_API_BEGIN
+    KS_REQUIRE(n && n->ctx, KS_ERR_ARG, "ks_net_loss_grad: null handle");
+    check_pairs(npairs, gauges, b_dev, x_dev);
+    const double l = net_loss_grad(*n->ctx, npairs, gauges, b_dev, x_dev, stream);
+    if (loss) *loss = l;
+    if (grad) {
+        KS_HIP(hipMemcpyAsync(grad, n->ctx->grad, sizeof(double) * 2 * kNetWeights,
+                              hipMemcpyDeviceToHost, stream));
+        KS_HIP(hipStreamSynchronize(stream));
+    }
+    return KS_SUCCESS;
+    KS_API_END
+}
+
+ks_status_t ks_net_train(ks_net_t n, int npairs, const ks_gauge_t* gauges,
+                         const double* const* b_dev, const double* const* x_dev, int steps,
+                         int batch, double lr, double* loss_history, hipStream_t stream)
+{
+    KS_API_BEGIN
+    KS_REQUIRE(n && n->ctx, KS_ERR_ARG, "ks_net_train: null handle");
+    check_pairs(npairs, gauges, b_dev, x_dev);
+    KS_REQUIRE(steps >= 0 && batch >= 1 && lr > 0, KS_ERR_ARG, "ks_net_train: bad steps/batch/lr");
+    batch = std::min(batch, npairs);
+    std::vector<ks_gauge_t> gs(batch);
+    std::vector<const double*> bs(batch), xs(batch);
+    for (int k = 0; k < steps; ++k) {
+        for (int j = 0; j < batch; ++j) {
+            const int q = (k * batch + j) % npairs;
+            gs[j] = gauges[q];
+            bs[j] = b_dev[q];
+            xs[j] = x_dev[q];
+        }
+        const double l = net_loss_grad(*n->ctx, batch, gs.data(), bs.data(), xs.data(), stream);
+        if (loss_history) loss_history[k] = l;
+        net_adam(*n->ctx, lr, stream);
+    }
+    KS_HIP(hipStreamSynchronize(stream));
+    return KS_SUCCESS;
+    KS_API_END
+}
+
+ks_status_t ks_fcg_solve(ks_gauge_t g, ks_net_t n, double mass, const double* b_dev,
+                         double* x_dev, const ks_solver_params* p, int use_mfma,
+                         ks_solver_stats* st, hipStream_t stream)
+{
+    KS_API_BEGIN
+    KS_REQUIRE(g && n && n->ctx && b_dev && x_dev, KS_ERR_ARG, "ks_fcg_solve: null argument");
+    KS_REQUIRE(b_dev != x_dev, KS_ERR_ARG, "ks_fcg_solve: x aliases b");
+    check_params(p);
+    Workspace& w = workspace(g);
+    import_field(g->geom, KS_F64, b_dev, w.b64, stream);
+    import_field(g->geom, KS_F64, x_dev, w.x64, stream);
+    ks_solver_stats local;
+    const ks_status_t rc = fcg_core(g, *n->ctx, 4.0 * mass * mass, w.b64, w.x64, *p, use_mfma,
+                                    local, stream);
+    export_field(g->geom, KS_F64, w.x64, x_dev, stream);
+    KS_HIP(hipStreamSynchronize(stream));
+    if (st) *st = local;
+    return rc;
     KS_API_END
 }
 

@@ -1,0 +1,72 @@
+// Preconditioner network: internal state.
+#pragma once
+
+#include <map>
+
+#include "ks_common.h"
+
+namespace ks {
+
+constexpr int kNetWeights = 1 * 8 * 9 + 8 * 8 * 9 + 8 * 8 * 9 + 8 * 1 * 9;   // complex weights
+constexpr int kWgradBlocks = 512;
+
+extern const int kLayerIn[4];
+extern const int kLayerOut[4];
+size_t layer_weight_offset(int l);   // complex offset of layer l's weights
+
+// Activation and gradient buffers of one lattice size: levels 0..4 (channels 1, 8, 8, 8, 1),
+// each [parity][channel][colour][Vh] complex FP32.
+struct NetBuffers {
+    int vh = 0;
+    float2* act[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    float2* grad[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    __half* act16[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // MFMA path
+    int npart = 0;
+    double* part = nullptr;
+    double* wpart = nullptr;
+};
+
+struct NetCtx {
+    double* w64 = nullptr;      // master weights, complex as (re, im) pairs, layer by layer
+    float* w32 = nullptr;       // FP32 copy used by the kernels
+    float* wadj = nullptr;      // adjoint-layer weights (backward)
+    double* adam_m = nullptr;
+    double* adam_v = nullptr;
+    double* grad = nullptr;
+    double* scal = nullptr;
+    double* host = nullptr;     // pinned
+    int step = 0;               // Adam steps taken
+    unsigned version = 0;       // bumps whenever the weights change
+    std::map<int, NetBuffers> bufs;
+    // MFMA operand cache
+    __half* wmma = nullptr;
+    unsigned wmma_version = ~0u;
+};
+
+NetCtx* net_create(const double* w_host);
+void net_free(NetCtx* n);
+void net_set_weights(NetCtx& n, const double* w_host, hipStream_t s);
+void net_get_weights(NetCtx& n, double* w_host, hipStream_t s);
+NetBuffers& net_buffers(NetCtx& n, const Geom& g);
+void net_forward(NetCtx& n, NetBuffers& B, ks_gauge_t g, hipStream_t s);
+void net_apply_f32(NetCtx& n, ks_gauge_t g, const double* in, double* out, double in_scale,
+                   hipStream_t s);
+void net_apply_mfma(NetCtx& n, ks_gauge_t g, const double* in, double* out, double in_scale,
+                    hipStream_t s);
+void net_mfma_prepare(NetCtx& n, hipStream_t s);
+void net_layer_mfma(NetCtx& n, ks_gauge_t g, const float2* in, float2* out, int which,
+                    hipStream_t s);
+double net_loss_grad(NetCtx& n, int npairs, const ks_gauge_t* gauges, const double* const* b,
+                     const double* const* x, hipStream_t s);
+void net_adam(NetCtx& n, double lr, hipStream_t s);
+
+ks_status_t fcg_core(ks_gauge_t g, NetCtx& net, double sigma, const double* b, double* x,
+                     const ks_solver_params& prm, int use_mfma, ks_solver_stats& stats,
+                     hipStream_t s);
+void fcg_release(ks_gauge_t g);
+
+}  // namespace ks
+
+struct ks_net_s {
+    ks::NetCtx* ctx;
+};

@@ -1,0 +1,563 @@
+// Gauge-covariant preconditioner network on the GPU: forward (inference), adjoint and
+// weight-gradient passes, loss, Adam.
+//
+// Layer:  y_c(x) = sum_{c', p} w_{c c' p} (T_p phi_{c'})(x), nine paths p: the identity,
+// T_{+mu} phi(x) = V_mu(x) phi(x+mu) (p = 1+mu) and T_{-mu} phi(x) = V_mu(x-mu)^+ phi(x-mu)
+// (p = 5+mu), with the operator's fat link V.  Channels 1 -> 8 -> 8 -> 8 -> 1, no activation.
+// Activations live on the full lattice as two checkerboard halves, [parity][channel][colour][Vh]
+// complex FP32.  The FP32 channel mixing runs on the vector ALUs (training, and the reference
+// inference path); the inference path also has an MFMA form (network_mfma.hip).
+//
+// The adjoint of a layer, y -> sum_p T_p^+ W_p^H y, is again a layer: channels swapped,
+// weights w'_{c' c pbar} = conj(w_{c c' p}), pbar the reversed path (T_{+mu}^+ = T_{-mu}).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "ks_device.h"
+#include "ks_net.h"
+
+namespace ks {
+
+namespace {
+
+constexpr int kNT = 256;
+
+template <int C>
+__device__ __forceinline__ const float2* act_ptr(const float2* a, int par, int c, int k, int vh)
+{
+    return a + ((size_t)(par * C + c) * 3 + k) * vh;
+}
+
+// one thread per site of the full lattice (t < Vh: even, else odd)
+template <int CIN, int COUT>
+__global__ __launch_bounds__(kNT) void net_layer_kernel(Geom g, const float2* __restrict__ in,
+                                                        float2* __restrict__ out,
+                                                        const void* __restrict__ fat_e,
+                                                        const void* __restrict__ fat_o,
+                                                        const float2* __restrict__ w)
+{
+    const int vh = g.Vh;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 2 * vh) return;
+    const int par = t >= vh ? 1 : 0;
+    const int h = t - par * vh;
+    const void* fat = par ? fat_o : fat_e;
+    int c[4];
+    cb_coords(g, h, par, c);
+    const int i = site_index(g, c);
+    cx<float> y[COUT][3];
+#pragma unroll
+    for (int o = 0; o < COUT; ++o)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) y[o][k] = {0.f, 0.f};
+    // identity path
+#pragma unroll
+    for (int ci = 0; ci < CIN; ++ci) {
+        cx<float> v[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float2 q = act_ptr<CIN>(in, par, ci, k, vh)[h];
+            v[k] = {q.x, q.y};
+        }
+#pragma unroll
+        for (int o = 0; o < COUT; ++o) {
+            const float2 ww = w[(o * CIN + ci) * 9];
+            const cx<float> wc = {ww.x, ww.y};
+#pragma unroll
+            for (int k = 0; k < 3; ++k) cfma(y[o][k], wc, v[k]);
+        }
+    }
+#pragma unroll 1
+    for (int s = 0; s < 8; ++s) {
+        const int mu = s & 3;
+        const bool bwd = s >= 4;
+        const int nbh = hop_cb(g, i, c, mu, bwd ? -1 : +1);
+        const int p = bwd ? 5 + mu : 1 + mu;
+        cx<float> m[9];
+        load_link<KS_F32, 9>(fat, s, vh, h, m);
+        if (bwd) {   // stored -V_mu(x-mu)^+
+#pragma unroll
+            for (int e = 0; e < 9; ++e) m[e] = {-m[e].r, -m[e].i};
+        }
+#pragma unroll
+        for (int ci = 0; ci < CIN; ++ci) {
+            cx<float> v[3], tv[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const float2 q = act_ptr<CIN>(in, 1 - par, ci, k, vh)[nbh];
+                v[k] = {q.x, q.y};
+                tv[k] = {0.f, 0.f};
+            }
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) cfma(tv[a], m[a * 3 + b], v[b]);
+#pragma unroll
+            for (int o = 0; o < COUT; ++o) {
+                const float2 ww = w[(o * CIN + ci) * 9 + p];
+                const cx<float> wc = {ww.x, ww.y};
+#pragma unroll
+                for (int k = 0; k < 3; ++k) cfma(y[o][k], wc, tv[k]);
+            }
+        }
+    }
+#pragma unroll
+    for (int o = 0; o < COUT; ++o)
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            const_cast<float2*>(act_ptr<COUT>(out, par, o, k, vh))[h] = make_float2(y[o][k].r, y[o][k].i);
+}
+
+// G_w[c][c'][p] += sum over sites and colours of conj((T_p phi_c')(x)_a) G_c(x)_a.
+// Per path, each value is reduced across the wave with cross-lane sums; lane k % 64 of the
+// wave keeps value k in its slot of the wave's LDS row (path-major order), and the block
+// writes one partial per value.  The order of every sum is fixed.
+template <int CIN, int COUT>
+__global__ __launch_bounds__(kNT) void net_wgrad_kernel(Geom g, const float2* __restrict__ in,
+                                                        const float2* __restrict__ gy,
+                                                        const void* __restrict__ fat_e,
+                                                        const void* __restrict__ fat_o,
+                                                        double* __restrict__ partials)
+{
+    constexpr int NP = COUT * CIN * 2;              // reals per path
+    constexpr int NPL = (NP + 63) / 64;             // slots per lane per path
+    constexpr int NV = 9 * NP;
+    __shared__ double lds[kNT / 64][9 * NPL * 64];
+    const int vh = g.Vh;
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    for (int k = lane; k < 9 * NPL * 64; k += 64) lds[wv][k] = 0.0;
+    for (int t0 = blockIdx.x * blockDim.x; t0 < 2 * vh; t0 += gridDim.x * blockDim.x) {
+        const int t = t0 + threadIdx.x;
+        const bool live = t < 2 * vh;
+        const int par = (live && t >= vh) ? 1 : 0;
+        const int h = live ? t - par * vh : 0;
+        const void* fat = par ? fat_o : fat_e;
+        int c[4];
+        cb_coords(g, h, par, c);
+        const int i = site_index(g, c);
+        cx<float> gv[COUT][3];
+#pragma unroll
+        for (int o = 0; o < COUT; ++o)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const float2 q = live ? act_ptr<COUT>(gy, par, o, k, vh)[h] : make_float2(0.f, 0.f);
+                gv[o][k] = {q.x, q.y};
+            }
+#pragma unroll 1
+        for (int p = 0; p < 9; ++p) {
+            cx<float> m[9];
+            int nbh = h, spar = par;
+            if (p > 0) {
+                const int s = p - 1;
+                const int mu = s & 3;
+                const bool bwd = s >= 4;
+                nbh = hop_cb(g, i, c, mu, bwd ? -1 : +1);
+                spar = 1 - par;
+                load_link<KS_F32, 9>(fat, s, vh, h, m);
+                if (bwd)
+#pragma unroll
+                    for (int e = 0; e < 9; ++e) m[e] = {-m[e].r, -m[e].i};
+            }
+            double acc[NPL];
+#pragma unroll
+            for (int j = 0; j < NPL; ++j) acc[j] = 0.0;
+#pragma unroll 1
+            for (int ci = 0; ci < CIN; ++ci) {
+                cx<float> v[3], tv[3];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const float2 q = live ? act_ptr<CIN>(in, spar, ci, k, vh)[nbh] : make_float2(0.f, 0.f);
+                    v[k] = {q.x, q.y};
+                }
+                if (p == 0) {
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) tv[k] = v[k];
+                } else {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        tv[a] = {0.f, 0.f};
+#pragma unroll
+                        for (int b = 0; b < 3; ++b) cfma(tv[a], m[a * 3 + b], v[b]);
+                    }
+                }
+#pragma unroll
+                for (int o = 0; o < COUT; ++o) {
+                    double sr = 0.0, si = 0.0;
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        const cx<float> z = cconjmul(tv[k], gv[o][k]);
+                        sr += z.r;
+                        si += z.i;
+                    }
+                    sr = wave_sum(sr);
+                    si = wave_sum(si);
+                    // value (o, ci, re/im) sits at local index o*2*CIN + 2*ci + reim; one row
+                    // o never straddles a 64-lane slot (2*CIN <= 16 and rows start at
+                    // multiples of 2*CIN), so the slot is known at compile time
+                    constexpr int row = 2 * CIN;
+                    const int slot = (o * row) >> 6;
+                    const int l0 = ((o * row) & 63) + 2 * ci;
+                    if (l0 == lane) acc[slot] += sr;
+                    if (l0 + 1 == lane) acc[slot] += si;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < NPL; ++j) lds[wv][(p * NPL + j) * 64 + lane] += acc[j];
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < NV; k += blockDim.x) {
+        // k in the weight order ((o*CIN + ci)*9 + p)*2 + reim
+        const int reim = k & 1;
+        const int p = (k >> 1) % 9;
+        const int oc = (k >> 1) / 9;
+        const int local = oc * 2 + reim;
+        const int slot = (p * NPL + (local >> 6)) * 64 + (local & 63);
+        double s = 0.0;
+#pragma unroll
+        for (int w2 = 0; w2 < kNT / 64; ++w2) s += lds[w2][slot];
+        partials[(size_t)blockIdx.x * NV + k] = s;
+    }
+}
+
+// grad[k] += sum_b partials[b][k]  (fixed order)
+__global__ void net_grad_finish_kernel(const double* __restrict__ partials, int nblocks, int nv,
+                                       double* __restrict__ grad)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nv) return;
+    double s = 0.0;
+    for (int b = 0; b < nblocks; ++b) s += partials[(size_t)b * nv + k];
+    grad[k] += s;
+}
+
+// w'[c'][c][pbar] = conj(w[c][c'][p])
+__global__ void net_adjoint_weights_kernel(const float2* __restrict__ w, float2* __restrict__ wa,
+                                           int cin, int cout)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= cin * cout * 9) return;
+    const int p = k % 9, ci = (k / 9) % cin, o = k / (9 * cin);
+    const int pb = p == 0 ? 0 : (p <= 4 ? p + 4 : p - 4);
+    const float2 v = w[k];
+    wa[(ci * cout + o) * 9 + pb] = make_float2(v.x, -v.y);
+}
+
+// network input: even sites from a complex128 [Vh][3] vector times `scale`, odd sites zero
+__global__ void net_embed_kernel(int vh, const double2* __restrict__ src, double scale,
+                                 float2* __restrict__ act)
+{
+    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= vh) return;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double2 v = src[(size_t)h * 3 + k];
+        act[(size_t)k * vh + h] = make_float2((float)(v.x * scale), (float)(v.y * scale));
+        act[(size_t)(3 + k) * vh + h] = make_float2(0.f, 0.f);
+    }
+}
+
+// network output (even sites of the last layer) times `scale` into complex128 [Vh][3]
+__global__ void net_extract_kernel(int vh, const float2* __restrict__ act, double scale,
+                                   double2* __restrict__ dst)
+{
+    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= vh) return;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const float2 v = act[(size_t)k * vh + h];
+        dst[(size_t)h * 3 + k] = make_double2(v.x * scale, v.y * scale);
+    }
+}
+
+// loss term of one pair and the output gradient: diff = N(b) - x on even sites,
+// G = coef * diff (even), 0 (odd); per-block partial sums of |diff|^2
+__global__ __launch_bounds__(kNT) void net_loss_kernel(int vh, const float2* __restrict__ outp,
+                                                       const double2* __restrict__ x, double coef,
+                                                       float2* __restrict__ gy,
+                                                       double* __restrict__ partials)
+{
+    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    double s = 0.0;
+    if (h < vh) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float2 o = outp[(size_t)k * vh + h];
+            const double2 xv = x[(size_t)h * 3 + k];
+            const double dr = o.x - xv.x, di = o.y - xv.y;
+            s += dr * dr + di * di;
+            gy[(size_t)k * vh + h] = make_float2((float)(coef * dr), (float)(coef * di));
+            gy[(size_t)(3 + k) * vh + h] = make_float2(0.f, 0.f);
+        }
+    }
+    s = block_sum<kNT>(s);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// |x|^2 partials of a complex128 [Vh][3] vector
+__global__ __launch_bounds__(kNT) void net_norm_kernel(int vh, const double2* __restrict__ x,
+                                                       double* __restrict__ partials)
+{
+    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    double s = 0.0;
+    if (h < vh)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double2 v = x[(size_t)h * 3 + k];
+            s += v.x * v.x + v.y * v.y;
+        }
+    s = block_sum<kNT>(s);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// One Adam step on every real of the FP64 master weights; refreshes the FP32 copy.
+__global__ void net_adam_kernel(double* __restrict__ w, double* __restrict__ m,
+                                double* __restrict__ v, const double* __restrict__ grad, int n,
+                                double lr, double b1, double b2, double eps, double c1, double c2,
+                                float* __restrict__ w32)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double gk = grad[k];
+    const double mk = b1 * m[k] + (1.0 - b1) * gk;
+    const double vk = b2 * v[k] + (1.0 - b2) * gk * gk;
+    m[k] = mk;
+    v[k] = vk;
+    const double mh = mk / c1, vhat = vk / c2;
+    const double nw = w[k] - lr * mh / (sqrt(vhat) + eps);
+    w[k] = nw;
+    w32[k] = (float)nw;
+}
+
+__global__ void to_f32_vec_kernel(const double* __restrict__ a, float* __restrict__ b, int n)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) b[k] = (float)a[k];
+}
+
+template <int CIN, int COUT>
+void layer(ks_gauge_t g, const float2* in, float2* out, const float2* w, hipStream_t s)
+{
+    const LinkStore& st = g->store[KS_F32][0];
+    net_layer_kernel<CIN, COUT><<<blocks_for(2L * g->geom.Vh, kNT), kNT, 0, s>>>(
+        g->geom, in, out, st.fat[0], st.fat[1], w);
+    KS_HIP(hipGetLastError());
+}
+
+template <int CIN, int COUT>
+void wgrad(NetCtx& n, NetBuffers& B, ks_gauge_t g, const float2* in, const float2* gy,
+           double* grad, hipStream_t s)
+{
+    const LinkStore& st = g->store[KS_F32][0];
+    constexpr int NV = COUT * CIN * 9 * 2;
+    const int nb = std::min(blocks_for(2L * g->geom.Vh, kNT), kWgradBlocks);
+    net_wgrad_kernel<CIN, COUT><<<nb, kNT, 0, s>>>(g->geom, in, gy, st.fat[0], st.fat[1], B.wpart);
+    net_grad_finish_kernel<<<blocks_for(NV, 256), 256, 0, s>>>(B.wpart, nb, NV, grad);
+    KS_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+const int kLayerIn[4] = {1, 8, 8, 8};
+const int kLayerOut[4] = {8, 8, 8, 1};
+
+size_t layer_weight_offset(int l)
+{
+    size_t o = 0;
+    for (int k = 0; k < l; ++k) o += (size_t)kLayerIn[k] * kLayerOut[k] * 9;
+    return o;
+}
+
+NetBuffers& net_buffers(NetCtx& n, const Geom& g)
+{
+    NetBuffers& B = n.bufs[g.Vh];
+    if (!B.act[0]) {
+        const size_t site = (size_t)2 * 3 * g.Vh * sizeof(float2);   // one channel, both parities
+        const int ch[5] = {1, 8, 8, 8, 1};
+        for (int l = 0; l < 5; ++l) {
+            B.act[l] = static_cast<float2*>(device_alloc(site * ch[l]));
+            B.grad[l] = static_cast<float2*>(device_alloc(site * ch[l]));
+        }
+        B.npart = blocks_for(g.Vh, kNT);
+        B.part = static_cast<double*>(device_alloc(sizeof(double) * (B.npart + 8)));
+        B.wpart = static_cast<double*>(device_alloc(sizeof(double) * kWgradBlocks * 8 * 8 * 9 * 2));
+        B.vh = g.Vh;
+    }
+    return B;
+}
+
+void net_free(NetCtx* n)
+{
+    if (!n) return;
+    for (auto& kv : n->bufs) {
+        for (int l = 0; l < 5; ++l) {
+            device_free(kv.second.act[l]);
+            device_free(kv.second.grad[l]);
+        }
+        device_free(kv.second.part);
+        device_free(kv.second.wpart);
+    }
+    device_free(n->w64);
+    device_free(n->w32);
+    device_free(n->wadj);
+    device_free(n->adam_m);
+    device_free(n->adam_v);
+    device_free(n->grad);
+    device_free(n->scal);
+    device_free(n->wmma);
+    if (n->host) (void)hipHostFree(n->host);
+    delete n;
+}
+
+NetCtx* net_create(const double* w_host)
+{
+    NetCtx* n = new NetCtx();
+    try {
+        const size_t nr = 2 * (size_t)kNetWeights;
+        n->w64 = static_cast<double*>(device_alloc(sizeof(double) * nr));
+        n->w32 = static_cast<float*>(device_alloc(sizeof(float) * nr));
+        n->wadj = static_cast<float*>(device_alloc(sizeof(float) * nr));
+        n->adam_m = static_cast<double*>(device_alloc(sizeof(double) * nr));
+        n->adam_v = static_cast<double*>(device_alloc(sizeof(double) * nr));
+        n->grad = static_cast<double*>(device_alloc(sizeof(double) * nr));
+        n->scal = static_cast<double*>(device_alloc(sizeof(double) * 64));
+        KS_HIP(hipHostMalloc(reinterpret_cast<void**>(&n->host), sizeof(double) * 64));
+        net_set_weights(*n, w_host, nullptr);
+    } catch (...) {
+        net_free(n);
+        throw;
+    }
+    return n;
+}
+
+void net_set_weights(NetCtx& n, const double* w_host, hipStream_t s)
+{
+    const int nr = 2 * kNetWeights;
+    KS_HIP(hipMemcpyAsync(n.w64, w_host, sizeof(double) * nr, hipMemcpyHostToDevice, s));
+    KS_HIP(hipMemsetAsync(n.adam_m, 0, sizeof(double) * nr, s));
+    KS_HIP(hipMemsetAsync(n.adam_v, 0, sizeof(double) * nr, s));
+    to_f32_vec_kernel<<<blocks_for(nr, 256), 256, 0, s>>>(n.w64, n.w32, nr);
+    KS_HIP(hipGetLastError());
+    KS_HIP(hipStreamSynchronize(s));
+    n.step = 0;
+    n.version += 1;
+}
+
+void net_get_weights(NetCtx& n, double* w_host, hipStream_t s)
+{
+    KS_HIP(hipMemcpyAsync(w_host, n.w64, sizeof(double) * 2 * kNetWeights, hipMemcpyDeviceToHost, s));
+    KS_HIP(hipStreamSynchronize(s));
+}
+
+// Forward through the four layers, input already in act[0]; activations of every layer kept.
+void net_forward(NetCtx& n, NetBuffers& B, ks_gauge_t g, hipStream_t s)
+{
+    const float2* w = reinterpret_cast<const float2*>(n.w32);
+    layer<1, 8>(g, B.act[0], B.act[1], w + layer_weight_offset(0), s);
+    layer<8, 8>(g, B.act[1], B.act[2], w + layer_weight_offset(1), s);
+    layer<8, 8>(g, B.act[2], B.act[3], w + layer_weight_offset(2), s);
+    layer<8, 1>(g, B.act[3], B.act[4], w + layer_weight_offset(3), s);
+}
+
+// out_dev = N(in_dev) (complex128 [Vh][3], even sites); FP32 vector-ALU mixing.
+void net_apply_f32(NetCtx& n, ks_gauge_t g, const double* in, double* out, double in_scale,
+                   hipStream_t s)
+{
+    gauge_prepare(g, KS_F32, KS_RECON_18, s);
+    NetBuffers& B = net_buffers(n, g->geom);
+    const int vh = g->geom.Vh;
+    net_embed_kernel<<<blocks_for(vh), kBlock, 0, s>>>(vh, reinterpret_cast<const double2*>(in),
+                                                       in_scale, B.act[0]);
+    net_forward(n, B, g, s);
+    net_extract_kernel<<<blocks_for(vh), kBlock, 0, s>>>(vh, B.act[4], 1.0 / in_scale,
+                                                         reinterpret_cast<double2*>(out));
+    KS_HIP(hipGetLastError());
+}
+
+// Same, with the two 8 -> 8 layers' channel mixing on the matrix cores (FP16 operands, FP32
+// accumulation); the 1 -> 8 and 8 -> 1 layers keep the vector-ALU form.
+void net_apply_mfma(NetCtx& n, ks_gauge_t g, const double* in, double* out, double in_scale,
+                    hipStream_t s)
+{
+    gauge_prepare(g, KS_F32, KS_RECON_18, s);
+    net_mfma_prepare(n, s);
+    NetBuffers& B = net_buffers(n, g->geom);
+    const int vh = g->geom.Vh;
+    const float2* w = reinterpret_cast<const float2*>(n.w32);
+    net_embed_kernel<<<blocks_for(vh), kBlock, 0, s>>>(vh, reinterpret_cast<const double2*>(in),
+                                                       in_scale, B.act[0]);
+    layer<1, 8>(g, B.act[0], B.act[1], w + layer_weight_offset(0), s);
+    net_layer_mfma(n, g, B.act[1], B.act[2], 1, s);
+    net_layer_mfma(n, g, B.act[2], B.act[3], 2, s);
+    layer<8, 1>(g, B.act[3], B.act[4], w + layer_weight_offset(3), s);
+    net_extract_kernel<<<blocks_for(vh), kBlock, 0, s>>>(vh, B.act[4], 1.0 / in_scale,
+                                                         reinterpret_cast<double2*>(out));
+    KS_HIP(hipGetLastError());
+}
+
+// Loss of the pairs and its gradient, accumulated into n.grad (zeroed first).
+double net_loss_grad(NetCtx& n, int npairs, const ks_gauge_t* gauges, const double* const* b,
+                     const double* const* x, hipStream_t s)
+{
+    const int nr = 2 * kNetWeights;
+    KS_HIP(hipMemsetAsync(n.grad, 0, sizeof(double) * nr, s));
+    const float2* w = reinterpret_cast<const float2*>(n.w32);
+    float2* wa = reinterpret_cast<float2*>(n.wadj);
+    for (int l = 1; l < 4; ++l) {
+        const size_t o = layer_weight_offset(l);
+        net_adjoint_weights_kernel<<<blocks_for(kLayerIn[l] * kLayerOut[l] * 9, 256), 256, 0, s>>>(
+            w + o, wa + o, kLayerIn[l], kLayerOut[l]);
+    }
+    KS_HIP(hipGetLastError());
+    double loss = 0.0;
+    for (int j = 0; j < npairs; ++j) {
+        ks_gauge_t g = gauges[j];
+        gauge_prepare(g, KS_F32, KS_RECON_18, s);
+        NetBuffers& B = net_buffers(n, g->geom);
+        const int vh = g->geom.Vh;
+        const int nb = blocks_for(vh, kNT);
+        // |x|^2
+        net_norm_kernel<<<nb, kNT, 0, s>>>(vh, reinterpret_cast<const double2*>(x[j]), B.part);
+        reduce_sum(B.part, nb, n.scal, s);
+        KS_HIP(hipMemcpyAsync(n.host, n.scal, sizeof(double), hipMemcpyDeviceToHost, s));
+        KS_HIP(hipStreamSynchronize(s));
+        const double nx2 = n.host[0];
+        KS_REQUIRE(nx2 > 0, KS_ERR_ARG, "network training: solution %d is zero", j);
+        net_embed_kernel<<<blocks_for(vh), kBlock, 0, s>>>(vh, reinterpret_cast<const double2*>(b[j]),
+                                                           1.0, B.act[0]);
+        net_forward(n, B, g, s);
+        net_loss_kernel<<<nb, kNT, 0, s>>>(vh, B.act[4], reinterpret_cast<const double2*>(x[j]),
+                                           2.0 / (nx2 * npairs), B.grad[4], B.part);
+        reduce_sum(B.part, nb, n.scal + 1, s);
+        KS_HIP(hipMemcpyAsync(n.host + 1, n.scal + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+        // backward: weight gradients and the adjoint layers
+        double* gr = n.grad;
+        wgrad<8, 1>(n, B, g, B.act[3], B.grad[4], gr + 2 * layer_weight_offset(3), s);
+        layer<1, 8>(g, B.grad[4], B.grad[3], wa + layer_weight_offset(3), s);
+        wgrad<8, 8>(n, B, g, B.act[2], B.grad[3], gr + 2 * layer_weight_offset(2), s);
+        layer<8, 8>(g, B.grad[3], B.grad[2], wa + layer_weight_offset(2), s);
+        wgrad<8, 8>(n, B, g, B.act[1], B.grad[2], gr + 2 * layer_weight_offset(1), s);
+        layer<8, 8>(g, B.grad[2], B.grad[1], wa + layer_weight_offset(1), s);
+        wgrad<1, 8>(n, B, g, B.act[0], B.grad[1], gr + 2 * layer_weight_offset(0), s);
+        KS_HIP(hipStreamSynchronize(s));
+        loss += n.host[1] / (nx2 * npairs);
+    }
+    return loss;
+}
+
+void net_adam(NetCtx& n, double lr, hipStream_t s)
+{
+    const int nr = 2 * kNetWeights;
+    n.step += 1;
+    const double b1 = 0.9, b2 = 0.999;
+    net_adam_kernel<<<blocks_for(nr, 256), 256, 0, s>>>(n.w64, n.adam_m, n.adam_v, n.grad, nr, lr,
+                                                       b1, b2, 1e-8, 1.0 - std::pow(b1, n.step),
+                                                       1.0 - std::pow(b2, n.step), n.w32);
+    KS_HIP(hipGetLastError());
+    n.version += 1;
+}
+
+}  // namespace ks
