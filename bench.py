@@ -83,12 +83,94 @@ def cpu_baseline(g, b, budget_s: float = 12.0):
             "sample": "%d FP64 oracle Dslash_eo calls on the 32^4 field (%.3f s each)" % (n, dt)}
 
 
+def learned48(args):
+    """48^3 x 64 lattice, thin-link scale 0.5, m = 0.002: 248 training pairs on 16^4 blocks
+    cut from the field plus 8 on the full lattice (FP64 CG solutions), Adam training, then
+    flexible CG with the network (matrix-core mixing) against FP32-inner CG with reliable
+    updates, both to FP64 true relative residual 1e-10."""
+    import numpy as np
+    import torch
+    import paper_1611_00728_amd as ks
+    from paper_1611_00728_amd import learn
+    from ksinputs import (make_gauge, gaussian_source, subblock, net_init_weights,
+                          flatten_weights, SEEDS)
+    dims, mass, tol = (48, 48, 48, 64), 0.002, 1e-10
+    t0 = time.time()
+    g = make_gauge(dims, 0.5, SEEDS["gauge"](5), keep_thin=True)
+    vh = g.volume // 2
+    log("48^3x64 field generated in %.1f s" % (time.time() - t0))
+    G = ks.Gauge(dims, g.fat, g.naik)
+    for p in (ks.F64, ks.F32):
+        G.prepare(p, 18)
+        G.tune(p, 18)
+    origins = learn.block_origins(dims, (16, 16, 16, 16))
+    # inputs first (block fields cut on the host and loaded), then the timed solver work
+    t1 = time.perf_counter()
+    jobs = []
+    k = 0
+    for j, o in enumerate(origins):
+        bk = subblock(g, o, (16, 16, 16, 16))
+        Gk = ks.Gauge(bk.dims, bk.fat, bk.naik)
+        nsrc = 3 if j < 248 - 2 * len(origins) else 2
+        jobs.append((Gk, [gaussian_source(bk.volume // 2, SEEDS["train_source"](k + r))
+                          for r in range(nsrc)]))
+        k += nsrc
+    log("%d block fields cut and loaded in %.1f s (input preparation, not timed)"
+        % (len(jobs), time.perf_counter() - t1))
+    t_gen0 = time.perf_counter()
+    pairs = []
+    for Gk, srcs in jobs:
+        pairs += learn.solve_pairs(Gk, mass, srcs)
+    t_blocks = time.perf_counter() - t_gen0
+    log("%d block pairs in %.1f s" % (len(pairs), t_blocks))
+    full = []
+    for r in range(8):
+        full += learn.solve_pairs(G, mass, [gaussian_source(vh, SEEDS["train_source"](10000 + r))])
+        log("full-lattice pair %d done" % r)
+    pairs += full
+    t_gen = time.perf_counter() - t_gen0
+    net = ks.Net(flatten_weights(net_init_weights(SEEDS["net_init"])))
+    steps = 400
+    hist, t_train = learn.train(net, pairs, steps=steps, batch=8, lr=2e-3)
+    log("trained: loss %.4f -> %.4f in %.1f s" % (hist[0], hist[-1], t_train))
+    b = torch.from_numpy(gaussian_source(vh, SEEDS["source"](5))).cuda()
+    rows = {}
+    for name, fn in (("fp64_cg", lambda x: ks.cg_solve(G, mass, b, x, ks.default_params(tol=tol))),
+                     ("mixed_f32_cg", lambda x: ks.cg_solve(
+                         G, mass, b, x, ks.default_params(tol=tol, inner=ks.F32))),
+                     ("learned_fcg", lambda x: ks.fcg_solve(
+                         G, net, mass, b, x, ks.default_params(tol=tol, inner=ks.F32), mfma=True))):
+        x = torch.zeros_like(b)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        res = fn(x)
+        torch.cuda.synchronize()
+        rows[name] = {"seconds": time.perf_counter() - t, "iters": res.stats["iters"],
+                      "true_rel_resid": res.stats["true_rel_resid"],
+                      "fallback": bool(res.stats["fallback"])}
+        log("%s: %s" % (name, json.dumps(rows[name])))
+    tm, tl = rows["mixed_f32_cg"]["seconds"], rows["learned_fcg"]["seconds"]
+    print(json.dumps({
+        "workload": "learned preconditioner, 48^3x64, H scale 0.5, m=0.002, tol 1e-10",
+        "solves": rows,
+        "training": {"pairs": len(pairs), "block_pairs": len(pairs) - len(full),
+                     "full_lattice_pairs": len(full), "pair_generation_s": t_gen,
+                     "adam_steps": steps, "batch": 8, "training_s": t_train,
+                     "loss_first": float(hist[0]), "loss_last": float(hist[-1])},
+        "learned_vs_mixed_speedup": tm / tl,
+        "break_even_solves": ((t_gen + t_train) / (tm - tl)) if tl < tm else None,
+        "amortised_training_per_solve_s_over_100": (t_gen + t_train) / 100.0}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="default", choices=["default", "learned48"],
+                    help="learned48: the 48^3 x 64, m = 0.002 learned-preconditioner workload "
+                         "(training pairs, training, flexible CG vs mixed CG), its own JSON line")
     ap.add_argument("--dslash-only", type=int, default=0, metavar="N",
                     help="counter runs: N launches of each Dslash_eo variant and one plain "
                          "1 GiB device copy, then exit")
@@ -105,8 +187,11 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.workload == "learned48":
+        learned48(args)
+        return
     t0 = time.time()
-    g = make_gauge(DIMS, 0.5, 1002)
+    g = make_gauge(DIMS, 0.5, 1002, keep_thin=True)
     vh = g.volume // 2
     b = gaussian_source(vh, 2002)
     log("inputs generated in %.1f s" % (time.time() - t0))
@@ -211,6 +296,38 @@ def main():
             if record:
                 ms_runs[name].append((time.perf_counter() - t, st))
 
+    # learned preconditioner: (source, FP64-CG solution) pairs on the sixteen 16^4 blocks of
+    # the 32^4 field (4 sources each) and 4 on the full lattice, Adam on the GPU kernels
+    from paper_1611_00728_amd import learn
+    from ksinputs import subblock, net_init_weights, flatten_weights
+    blocks = [subblock(g, o, (16, 16, 16, 16)) for o in learn.block_origins(DIMS, (16, 16, 16, 16))]
+    jobs = [(ks.Gauge(bk.dims, bk.fat, bk.naik),
+             [gaussian_source(bk.volume // 2, SEEDS["train_source"](4 * j + r)) for r in range(4)])
+            for j, bk in enumerate(blocks)]
+    t_gen0 = time.perf_counter()
+    pairs = []
+    for Gk, srcs in jobs:
+        pairs += learn.solve_pairs(Gk, MASS, srcs)
+    pairs += learn.solve_pairs(G, MASS, [gaussian_source(vh, SEEDS["train_source"](1000 + r))
+                                         for r in range(4)])
+    t_gen = time.perf_counter() - t_gen0
+    del blocks
+    net = ks.Net(flatten_weights(net_init_weights(SEEDS["net_init"])))
+    loss_hist, t_train = learn.train(net, pairs, steps=300, batch=8, lr=2e-3)
+    log("learned preconditioner: %d pairs in %.1f s, 300 Adam steps in %.1f s, loss %.4f -> %.4f"
+        % (len(pairs), t_gen, t_train, loss_hist[0], loss_hist[-1]))
+    learned_runs = []
+
+    def learned(record):
+        xd = torch.zeros_like(bd)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        res = ks.fcg_solve(G, net, MASS, bd, xd, ks.default_params(tol=TOL, inner=ks.F32),
+                           mfma=True)
+        torch.cuda.synchronize()
+        if record:
+            learned_runs.append((time.perf_counter() - t, res.stats))
+
     solves = {"f64": [], "f32": [], "f16_r12": []}
     solve_cfg = {"f64": dict(inner=ks.F64, recon=18), "f32": dict(inner=ks.F32, recon=18),
                  "f16_r12": dict(inner=ks.F16, recon=12)}
@@ -220,6 +337,7 @@ def main():
             burst(v, record)
         batch_solve(record)
         multishift(record)
+        learned(record)
         for name, kw in solve_cfg.items():
             xd = torch.zeros_like(bd)
             torch.cuda.synchronize()
@@ -287,6 +405,22 @@ def main():
                      "model_gflops": flops / med / 1e9}
     msr["lattice"] = list(MS_DIMS)
     msr["shifts"] = "sigma_i = 4 m_i^2, m_i = geomspace(0.002, 0.5, 9), tol 1e-9 per shift"
+
+    lmed = float(np.median([d for d, _ in learned_runs]))
+    lst = learned_runs[-1][1]
+    t_mixed = tts["f32"]["seconds"]
+    overhead = t_gen + t_train
+    tts["learned_fcg_f32"] = {
+        "seconds": lmed, "iters": lst["iters"], "fallback": bool(lst["fallback"]),
+        "fallback_iters": lst["restarts"], "reliable_updates": lst["reliable_updates"],
+        "true_rel_resid": lst["true_rel_resid"], "speedup_vs_f64": base / lmed,
+        "speedup_vs_mixed_f32": t_mixed / lmed,
+        "training": {"pairs": len(pairs), "pair_generation_s": t_gen, "adam_steps": 300,
+                     "training_s": t_train, "loss_first": float(loss_hist[0]),
+                     "loss_last": float(loss_hist[-1]),
+                     "break_even_solves_vs_mixed": (overhead / (t_mixed - lmed))
+                     if lmed < t_mixed else None,
+                     "amortised_per_solve_s_over_100_solves": overhead / 100.0}}
 
     # achievable-bandwidth reference: a plain elementwise pass (1 GiB read + 1 GiB written)
     src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)

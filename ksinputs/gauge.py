@@ -156,3 +156,39 @@ def make_gauge(dims, scale: float, seed: int, keep_thin: bool = False) -> GaugeF
     U = thin_links(dims, scale, seed)
     fat, naik = fat_and_naik(U, dims, seed)
     return GaugeField(dims, fat, naik, U if keep_thin else None, scale, seed)
+
+
+def _block_view(A: np.ndarray, dims, origin, bdims) -> np.ndarray:
+    """The [4][V][3][3] links of the block [origin, origin + bdims) as a block lattice."""
+    nx, ny, nz, nt = (int(d) for d in dims)
+    ox, oy, oz, ot = origin
+    bx, by, bz, bt = bdims
+    shaped = A.reshape(4, nt, nz, ny, nx, 3, 3)
+    sub = shaped[:, ot:ot + bt, oz:oz + bz, oy:oy + by, ox:ox + bx]
+    return np.ascontiguousarray(sub).reshape(4, bx * by * bz * bt, 3, 3)
+
+
+def subblock(field: GaugeField, origin, bdims) -> GaugeField:
+    """A sub-lattice cut from a field generated with keep_thin=True: its thin and fat links
+    are reused with block-periodic wrap, its Naik link rebuilt from the block's thin links,
+    and the phases and the antiperiodic time boundary folded in for the block.  Block origins
+    must be even so that the staggered phases do not change."""
+    if field.thin is None:
+        raise ValueError("the field must keep its thin links")
+    if any(o % 2 for o in origin):
+        raise ValueError("block origins must be even")
+    dims = field.dims
+    bdims = tuple(int(b) for b in bdims)
+    # undo the phases and the boundary signs of the big lattice on the fat link
+    fat_big = field.fat.copy()
+    x, y, z, t = lattice_coords(dims)
+    nt = int(dims[3])
+    for mu in range(4):
+        eta = staggered_phase(mu, x, y, z, t)
+        s1 = eta * (time_bc_sign(1, t, nt) if mu == 3 else 1.0)
+        fat_big[mu] *= s1[:, None, None]
+    U = _block_view(field.thin, dims, origin, bdims)
+    fat = _block_view(fat_big, dims, origin, bdims)
+    naik = naik_from_thin(U, bdims)
+    fold_phases(fat, naik, bdims)
+    return GaugeField(bdims, fat, naik, U, field.scale, field.seed)
