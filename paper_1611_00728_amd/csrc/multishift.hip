@@ -25,7 +25,8 @@ constexpr int kFinish = 1024;
 
 struct MSState {
     double rho, alpha, alpha_prev, beta, beta_prev, pAp;
-    int iter, max_iter, gate, stop_next, status, nactive, nshift, pad;
+    double maxr, ru_delta;   // reliable updates of the base residual (ru_delta 0: none)
+    int iter, max_iter, gate, stop_next, status, nactive, nshift, ru_pending;
     double delta[kMaxShift], stop2[kMaxShift];
     double zeta[kMaxShift], zeta_prev[kMaxShift];
     double alpha_i[kMaxShift], beta_i[kMaxShift];
@@ -48,7 +49,8 @@ __global__ __launch_bounds__(kFinish) void ms_alpha_kernel(const double* __restr
                                                            MSState* __restrict__ st)
 {
     if (st->gate) return;
-    if (st->stop_next) {
+    if (st->stop_next || st->ru_pending) {
+        // finished, or the host recomputes the base residual before the next step
         if (threadIdx.x == 0) st->gate = 1;
         return;
     }
@@ -134,6 +136,10 @@ __global__ __launch_bounds__(kFinish) void ms_beta_kernel(const double* __restri
     st->beta_prev = b;
     st->rho = rn;
     if (st->nactive == 0 || st->iter >= st->max_iter) st->stop_next = 1;
+    // reliable update of the base residual when it fell by ru_delta since the last one
+    const double s = sqrt(rn);
+    if (st->ru_delta > 0.0 && s < st->ru_delta * st->maxr) st->ru_pending = 1;
+    st->maxr = fmax(st->maxr, s);
 }
 
 // x_i += alpha_i p_i; p_i = zeta_i r + beta_i p_i for every shift updated this step, and the
@@ -241,7 +247,12 @@ ks_status_t multishift_core(ks_gauge_t g, int nshift, const double* sigma, const
     MSState* hs = static_cast<MSState*>(w.ms_st_host);
 
     double s0 = sigma[0];
-    for (int i = 1; i < nshift; ++i) s0 = std::min(s0, sigma[i]);
+    int i0 = 0;
+    for (int i = 1; i < nshift; ++i)
+        if (sigma[i] < s0) {
+            s0 = sigma[i];
+            i0 = i;
+        }
 
     // r = p = p_i = b in the inner precision, x_i = 0
     convert_field(vh, KS_F64, b, P, w.ms_r, nullptr, s);
@@ -261,6 +272,8 @@ ks_status_t multishift_core(ks_gauge_t g, int nshift, const double* sigma, const
     hs->rho = r2;
     hs->alpha_prev = 1.0;
     hs->beta_prev = 0.0;
+    hs->maxr = std::sqrt(r2);
+    hs->ru_delta = (P == KS_F64) ? 0.0 : prm.delta;
     hs->max_iter = prm.max_iter;
     hs->nshift = nshift;
     hs->nactive = nshift;
@@ -306,6 +319,7 @@ ks_status_t multishift_core(ks_gauge_t g, int nshift, const double* sigma, const
     };
     double model_bytes = 0.0;
     int last_iter = 0;
+    int ms_ru = 0;
     for (;;) {
         KS_HIP(hipMemcpyAsync(hs, st, sizeof(MSState), hipMemcpyDeviceToHost, s));
         KS_HIP(hipStreamSynchronize(s));
@@ -317,7 +331,25 @@ ks_status_t multishift_core(ks_gauge_t g, int nshift, const double* sigma, const
                       result == KS_ERR_BREAKDOWN ? "breakdown" : "non-finite value", hs->iter);
             break;
         }
-        if (hs->gate || hs->stop_next) break;
+        if (hs->stop_next) break;
+        if (hs->ru_pending) {
+            // r = b - A_0 x_0 in FP64 for the base (smallest) shift; the shifted systems keep
+            // r_i = zeta_i r with the recomputed r
+            apply_A64(g, s0, x[i0], w.ax64, s, nullptr);
+            sub_norm_partials(vh, b, w.ax64, w.r64, w.partials, s);
+            finish_to(w.partials, w.npart, w.scal, s);
+            convert_field(vh, KS_F64, w.r64, P, w.ms_r, nullptr, s);
+            KS_HIP(hipMemcpyAsync(w.host_scal, w.scal, sizeof(double), hipMemcpyDeviceToHost, s));
+            KS_HIP(hipStreamSynchronize(s));
+            hs->rho = w.host_scal[0];
+            hs->maxr = std::sqrt(hs->rho);
+            hs->ru_pending = 0;
+            hs->gate = 0;
+            ++ms_ru;
+            KS_HIP(hipMemcpyAsync(st, hs, sizeof(MSState), hipMemcpyHostToDevice, s));
+        } else if (hs->gate) {
+            break;
+        }
         for (int k = 0; k < chunk; ++k) iteration();
     }
     const int ms_iters = hs->iter;
@@ -327,6 +359,7 @@ ks_status_t multishift_core(ks_gauge_t g, int nshift, const double* sigma, const
         ks_solver_stats& o = stats[i];
         o = ks_solver_stats();
         o.iters = ms_iters;
+        o.reliable_updates = ms_ru;
         o.model_bytes = model_bytes / nshift;
         if (result != KS_SUCCESS) continue;
         const double tr2 = true_resid2(g, sigma[i], b, x[i], s);
@@ -337,7 +370,7 @@ ks_status_t multishift_core(ks_gauge_t g, int nshift, const double* sigma, const
             ks_solver_stats rs;
             const ks_status_t rc = cg_core(g, sigma[i], b, x[i], q, rs, s);
             o.iters += rs.iters;
-            o.reliable_updates = rs.reliable_updates;
+            o.reliable_updates += rs.reliable_updates;
             o.restarts = rs.restarts + 1;
             o.true_rel_resid = rs.true_rel_resid;
             o.model_bytes += rs.model_bytes;
