@@ -139,10 +139,18 @@ ks_status_t ks_dslash_eo(ks_gauge_t g, ks_field_t out, ks_field_t in, ks_recon_t
  * called while the stream is being captured into a graph. */
 ks_status_t ks_tune_dslash(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, hipStream_t stream);
 
-/* The launch configuration in use for a variant: threads per block, LDS bytes per block and
- * the tuned time per launch in microseconds (0 if never tuned).  Any output may be NULL. */
+/* The launch configuration in use for a variant: threads per block, LDS bytes per block, link
+ * matrices loaded per pass of the per-site loop (1, 2 or 4) and the tuned time per launch in
+ * microseconds (0 if never tuned).  Any output may be NULL. */
 ks_status_t ks_dslash_config(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, int* threads,
-                             int* lds_bytes, float* tuned_us);
+                             int* lds_bytes, int* links_per_pass, float* tuned_us);
+
+/* Sets a variant's launch configuration by hand (replacing the tuned one): threads 64, 128 or
+ * 256; lds_bytes 0 to 65536 (the dynamic LDS requested per block, which caps how many blocks
+ * share a CU); links_per_pass 1 or 2 (4 also for FP32 and FP16 with 18-real Naik; FP64 with
+ * 12-real Naik takes 1 only).  KS_ERR_ARG for any other value. */
+ks_status_t ks_dslash_set_config(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, int threads,
+                                 int lds_bytes, int links_per_pass);
 
 /* out_dev = (sigma - D_eo D_oe) in_dev in FP64 on even sites, complex128 [Vh][3] device
  * arrays (in_dev != out_dev).  Asynchronous. */

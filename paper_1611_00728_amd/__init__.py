@@ -90,7 +90,9 @@ def lib():
         L.ks_batch_free.argtypes = [_vp]
         L.ks_tune_dslash.argtypes = [_vp, C.c_int, C.c_int, _vp]
         L.ks_dslash_config.argtypes = [_vp, C.c_int, C.c_int, C.POINTER(C.c_int),
-                                       C.POINTER(C.c_int), C.POINTER(C.c_float)]
+                                       C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                       C.POINTER(C.c_float)]
+        L.ks_dslash_set_config.argtypes = [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
         L.ks_cg_solve.argtypes = [_vp, C.c_double, _vp, _vp, C.POINTER(SolverParams),
                                   C.POINTER(SolverStats), _vp]
         L.ks_multishift_cg_solve.argtypes = [_vp, C.c_int, C.POINTER(C.c_double), _vp,
@@ -174,10 +176,17 @@ class Gauge:
         return self.config(prec, recon)
 
     def config(self, prec=F64, recon=RECON_18) -> dict:
-        nt, lds, us = C.c_int(), C.c_int(), C.c_float()
+        nt, lds, grp, us = C.c_int(), C.c_int(), C.c_int(), C.c_float()
         _check(lib().ks_dslash_config(self.handle, prec, recon, C.byref(nt), C.byref(lds),
-                                      C.byref(us)))
-        return {"threads": nt.value, "lds_bytes": lds.value, "tuned_us": us.value}
+                                      C.byref(grp), C.byref(us)))
+        return {"threads": nt.value, "lds_bytes": lds.value, "links_per_pass": grp.value,
+                "tuned_us": us.value}
+
+    def set_config(self, prec=F64, recon=RECON_18, threads=256, lds_bytes=0,
+                   links_per_pass=1):
+        """Sets one variant's Dslash launch configuration by hand."""
+        _check(lib().ks_dslash_set_config(self.handle, prec, recon, threads, lds_bytes,
+                                          links_per_pass))
 
     def device_bytes(self) -> int:
         return int(lib().ks_gauge_device_bytes(self.handle))

@@ -254,7 +254,7 @@ ks_status_t ks_tune_dslash(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, hipSt
 }
 
 ks_status_t ks_dslash_config(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, int* threads,
-                             int* lds_bytes, float* tuned_us)
+                             int* lds_bytes, int* links_per_pass, float* tuned_us)
 {
     KS_API_BEGIN
     KS_REQUIRE(g, KS_ERR_ARG, "ks_dslash_config: null handle");
@@ -262,7 +262,31 @@ ks_status_t ks_dslash_config(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, int
     const TuneEntry& t = g->tune[prec][recon_index(recon)];
     if (threads) *threads = t.nt;
     if (lds_bytes) *lds_bytes = t.lds;
+    if (links_per_pass) *links_per_pass = t.group;
     if (tuned_us) *tuned_us = t.tuned ? t.us : 0.f;
+    return KS_SUCCESS;
+    KS_API_END
+}
+
+ks_status_t ks_dslash_set_config(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, int threads,
+                                 int lds_bytes, int links_per_pass)
+{
+    KS_API_BEGIN
+    KS_REQUIRE(g, KS_ERR_ARG, "ks_dslash_set_config: null handle");
+    KS_REQUIRE(prec_ok(prec) && recon_ok(recon), KS_ERR_ARG,
+               "ks_dslash_set_config: bad precision/recon");
+    KS_REQUIRE(threads == 64 || threads == 128 || threads == 256, KS_ERR_ARG,
+               "ks_dslash_set_config: threads must be 64, 128 or 256");
+    KS_REQUIRE(lds_bytes >= 0 && lds_bytes <= 65536, KS_ERR_ARG,
+               "ks_dslash_set_config: lds_bytes must lie in [0, 65536]");
+    KS_REQUIRE(dslash_group_built(prec, recon, links_per_pass), KS_ERR_ARG,
+               "ks_dslash_set_config: %d links per pass is not built for this variant",
+               links_per_pass);
+    TuneEntry t;
+    t.nt = threads;
+    t.lds = lds_bytes;
+    t.group = links_per_pass;
+    g->tune[prec][recon_index(recon)] = t;
     return KS_SUCCESS;
     KS_API_END
 }

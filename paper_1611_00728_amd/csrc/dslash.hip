@@ -1,8 +1,9 @@
 // Improved-staggered hopping term on one parity (the staggered dslash of Sec. 3):
 //   (D psi)(x) = sum_mu [ V_mu(x) psi(x+mu) - V_mu(x-mu)^+ psi(x-mu)
 //                       + W_mu(x) psi(x+3mu) - W_mu(x-3mu)^+ psi(x-3mu) ]
-// One thread per output site, looping over the site's 16 matrices (one link in flight per
-// thread keeps the kernel under 128 VGPRs, so 4-8 waves per SIMD hide the latency).  Links
+// One thread per output site, looping over the site's 16 matrices, 1, 2 or 4 of them loaded
+// per pass (a tuning choice: fewer keeps the register count low and the waves per SIMD high,
+// more keeps more loads in flight per wave).  Links
 // stream from packed site-major planes (16-byte coalesced loads, read once: the bulk of the
 // bytes); the 16 neighbour vectors are gathers that the XCD-aware tile order keeps inside
 // one XCD's L2 for most hops.
@@ -39,7 +40,7 @@ __device__ __forceinline__ void reconstruct_row2(cx<R> m[9])
     m[8] = {t.r, -t.i};
 }
 
-template <int P, int RECON, bool XPAY, int NT>
+template <int P, int RECON, bool XPAY, int NT, int U>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void dslash_kernel(Geom g, int par, const void* __restrict__ fat,
                                                         const void* __restrict__ naik,
                                                         const void* __restrict__ in,
@@ -69,27 +70,37 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void ds
             nb[12 + mu] = hop_cb(g, i, c, mu, -3);
         }
         cx<R> res[3] = {{0, 0}, {0, 0}, {0, 0}};
+        // U matrices per pass: their loads are issued together, then consumed in order.  U
+        // divides 8, so a pass holds only fat or only Naik links.
 #pragma unroll 1
-        for (int s = 0; s < 16; ++s) {
-            cx<R> m[9], v[3], t[3] = {{0, 0}, {0, 0}, {0, 0}};
-            R sc;
-            if (s < 8) {
-                load_link<P, 9>(fat, s, vh, h, m);
-                sc = (R)fat_scale;
-            } else if (RECON == 12) {
-                load_link<P, 6>(naik, s - 8, vh, h, m);
-                reconstruct_row2(m);
-                sc = (R)(naik_c0 * naik_sign(c, s - 8, g.n[3]));
-            } else {
-                load_link<P, 9>(naik, s - 8, vh, h, m);
-                sc = (R)naik_scale;
-            }
-            Spinor<P>::load(in, vh, nb[s], v);
-            matvec_acc(t, m, v);
+        for (int s0 = 0; s0 < 16; s0 += U) {
+            cx<R> m[U][9], v[U][3];
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                res[k].r = fma(sc, t[k].r, res[k].r);
-                res[k].i = fma(sc, t[k].i, res[k].i);
+            for (int u = 0; u < U; ++u) {
+                const int s = s0 + u;
+                if (s0 < 8) load_link<P, 9>(fat, s, vh, h, m[u]);
+                else if (RECON == 12) load_link<P, 6>(naik, s - 8, vh, h, m[u]);
+                else load_link<P, 9>(naik, s - 8, vh, h, m[u]);
+                Spinor<P>::load(in, vh, nb[s], v[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                R sc;
+                if (s0 < 8) {
+                    sc = (R)fat_scale;
+                } else if (RECON == 12) {
+                    reconstruct_row2(m[u]);
+                    sc = (R)(naik_c0 * naik_sign(c, s0 + u - 8, g.n[3]));
+                } else {
+                    sc = (R)naik_scale;
+                }
+                cx<R> t[3] = {{0, 0}, {0, 0}, {0, 0}};
+                matvec_acc(t, m[u], v[u]);
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    res[k].r = fma(sc, t[k].r, res[k].r);
+                    res[k].i = fma(sc, t[k].i, res[k].i);
+                }
             }
         }
         if (XPAY) {
@@ -119,31 +130,54 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void ds
     }
 }
 
-template <int P, int RECON, int NT>
-void launch_nt(const LinkStore& st, const Geom& G, double c0, const DslashArgs& a, int lds,
-               hipStream_t s)
+// Link matrices per pass that are built for a precision and Naik storage: more would exceed
+// the 128-VGPR budget of 4 waves per SIMD and spill.
+constexpr bool group_built(int P, int RECON, int U)
+{
+    return U == 1 || (U == 2 && !(P == KS_F64 && RECON == 12)) ||
+           (U == 4 && P != KS_F64 && RECON == 18);
+}
+
+template <int P, int RECON, int NT, int U>
+void launch_u(const LinkStore& st, const Geom& G, double c0, const DslashArgs& a, int lds,
+              hipStream_t s)
 {
     const int nb = blocks_for(G.Vh, NT);
     const void* fat = st.fat[a.out_parity];
     const void* naik = st.naik[a.out_parity];
     if (a.x)
-        dslash_kernel<P, RECON, true, NT><<<nb, NT, lds, s>>>(
+        dslash_kernel<P, RECON, true, NT, U><<<nb, NT, lds, s>>>(
             G, a.out_parity, fat, naik, a.in, a.out, a.x, a.a, a.dot_partials, a.gate,
             st.fat_scale, st.naik_scale, c0);
     else
-        dslash_kernel<P, RECON, false, NT><<<nb, NT, lds, s>>>(
+        dslash_kernel<P, RECON, false, NT, U><<<nb, NT, lds, s>>>(
             G, a.out_parity, fat, naik, a.in, a.out, nullptr, 0.0, nullptr, a.gate,
             st.fat_scale, st.naik_scale, c0);
     KS_HIP(hipGetLastError());
+}
+
+template <int P, int RECON, int NT>
+void launch_nt(const LinkStore& st, const Geom& G, double c0, const DslashArgs& a,
+               const TuneEntry& t, hipStream_t s)
+{
+    if (t.group == 2) {
+        if constexpr (group_built(P, RECON, 2)) launch_u<P, RECON, NT, 2>(st, G, c0, a, t.lds, s);
+        else KS_REQUIRE(false, KS_ERR_ARG, "Dslash: 2 links per pass not built for this storage");
+    } else if (t.group == 4) {
+        if constexpr (group_built(P, RECON, 4)) launch_u<P, RECON, NT, 4>(st, G, c0, a, t.lds, s);
+        else KS_REQUIRE(false, KS_ERR_ARG, "Dslash: 4 links per pass not built for this storage");
+    } else {
+        launch_u<P, RECON, NT, 1>(st, G, c0, a, t.lds, s);
+    }
 }
 
 template <int P, int RECON>
 void launch_p(const LinkStore& st, const Geom& G, double c0, const DslashArgs& a,
               const TuneEntry& t, hipStream_t s)
 {
-    if (t.nt == 64) launch_nt<P, RECON, 64>(st, G, c0, a, t.lds, s);
-    else if (t.nt == 128) launch_nt<P, RECON, 128>(st, G, c0, a, t.lds, s);
-    else launch_nt<P, RECON, 256>(st, G, c0, a, t.lds, s);
+    if (t.nt == 64) launch_nt<P, RECON, 64>(st, G, c0, a, t, s);
+    else if (t.nt == 128) launch_nt<P, RECON, 128>(st, G, c0, a, t, s);
+    else launch_nt<P, RECON, 256>(st, G, c0, a, t, s);
 }
 
 void launch(ks_gauge_t g, ks_prec_t prec, int ri, const DslashArgs& a, const TuneEntry& t,
@@ -167,6 +201,11 @@ int dslash_blocks(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon)
     return blocks_for(g->geom.Vh, g->tune[prec][recon_index(recon)].nt);
 }
 
+bool dslash_group_built(ks_prec_t prec, ks_recon_t recon, int links_per_pass)
+{
+    return links_per_pass > 0 && group_built((int)prec, (int)recon, links_per_pass);
+}
+
 int dslash_max_blocks(const Geom& g) { return blocks_for(g.Vh, 64); }
 
 void dslash(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, const DslashArgs& a, hipStream_t s)
@@ -176,8 +215,9 @@ void dslash(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, const DslashArgs& a,
     launch(g, prec, ri, a, g->tune[prec][ri], s);
 }
 
-// Candidates: 64, 128 or 256 threads per block, each with the number of resident blocks per
-// CU capped through the dynamic LDS request (how many waves share a SIMD also decides how
+// Candidates: 1, 2 or 4 matrices loaded per pass (2 at most in FP64), 64, 128 or 256 threads
+// per block, each with the number of resident blocks per CU capped through the dynamic LDS
+// request (how many waves share a SIMD also decides how
 // evenly the last round of waves fills the chip).  Each candidate is timed over a few
 // launches with HIP events on this lattice; the fastest is kept for the handle.
 void dslash_tune(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, hipStream_t s)
@@ -208,10 +248,14 @@ void dslash_tune(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, hipStream_t s)
         a.out_parity = 0;
         a.in = in;
         a.out = out;
+        for (int group : {1, 2, 4}) {
+        const int rc = ri ? 12 : 18;
+        if (!group_built((int)prec, rc, group)) continue;
         for (int nt : {64, 128, 256}) {
             for (int blocks_cu : {0, 2, 3, 4, 5, 6, 8, 10, 12, 16, 20, 24, 32}) {
                 TuneEntry t;
                 t.nt = nt;
+                t.group = group;
                 if (blocks_cu > 0) {
                     long l = lds_cu / blocks_cu - 256;
                     l -= l % 256;
@@ -232,6 +276,7 @@ void dslash_tune(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, hipStream_t s)
                     best = t;
                 }
             }
+        }
         }
     } catch (...) {
         if (e0) (void)hipEventDestroy(e0);

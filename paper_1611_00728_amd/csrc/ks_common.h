@@ -72,6 +72,7 @@ struct Workspace;   // solver buffers, solvers.hip
 // block (LDS only limits how many blocks share a CU; the kernel does not use it).
 struct TuneEntry {
     int nt = 256;
+    int group = 1;      // link matrices loaded per pass of the Dslash site loop
     int lds = 0;
     float us = 0.f;     // measured time per launch when tuned
     bool tuned = false;
@@ -223,6 +224,8 @@ void dslash(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, const DslashArgs& a,
 int dslash_blocks(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon);
 // upper bound of dslash_blocks over every launch configuration
 int dslash_max_blocks(const Geom& g);
+// whether the kernel with this many link matrices per pass exists for the variant
+bool dslash_group_built(ks_prec_t prec, ks_recon_t recon, int links_per_pass);
 // times the candidate launch configurations on this lattice and keeps the fastest
 void dslash_tune(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, hipStream_t s);
 

@@ -160,6 +160,44 @@ def test_dslash_argument_errors(ks):
         assert e.value.code == -1
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
+@pytest.mark.parametrize("recon", [18, 12])
+def test_every_launch_configuration(ks, prec, recon):
+    """Every built (links per pass, threads per block, LDS cap) form of the kernel gives the
+    oracle's result on a ragged lattice, both parities; unbuilt forms are refused."""
+    announce("dslash launch configurations", prec, recon)
+    dims = (8, 6, 10, 12)
+    g, G = loaded(ks, dims)
+    vh = g.volume // 2
+    P = {"f64": ks.F64, "f32": ks.F32, "f16": ks.F16}[prec]
+    bound = {"f64": 1e-12, "f32": 5e-6, "f16": 5e-3}[prec]
+    built = [1, 2] + ([4] if prec != "f64" and recon == 18 else [])
+    if prec == "f64" and recon == 12:
+        built = [1]
+    psi = [gaussian_source(vh, 500 + p) for p in (0, 1)]
+    ref = [oracle.dslash_eo(g, p, psi[p]) for p in (0, 1)]
+    try:
+        for group in (1, 2, 4):
+            for threads in (64, 128, 256):
+                for lds in (0, 40960):
+                    if group not in built:
+                        with pytest.raises(ks.KSError) as e:
+                            G.set_config(P, recon, threads, lds, group)
+                        assert e.value.code == -1
+                        continue
+                    G.set_config(P, recon, threads, lds, group)
+                    assert G.config(P, recon)["links_per_pass"] == group
+                    for out_par in (0, 1):
+                        got = run_dslash(ks, G, vh, out_par, psi[out_par], P, recon)
+                        assert rel_l2(got, ref[out_par]) <= bound, (group, threads, lds)
+        with pytest.raises(ks.KSError):
+            G.set_config(P, recon, 96, 0, 1)
+        with pytest.raises(ks.KSError):
+            G.set_config(P, recon, 64, -1, 1)
+    finally:
+        G.set_config(P, recon, 256, 0, 1)
+
+
 def test_dslash_full_size_32(ks):
     """32^4 (the benchmark lattice), FP64 and FP32, both parities, every site."""
     announce("dslash 32^4")
