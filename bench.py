@@ -41,13 +41,39 @@ def model_bytes_per_site(prec: str, recon: int) -> int:
     return links + 2 * spinor
 
 
+# one batched CG step for 4 right-hand sides, FP32 vectors and links, FP64 x, per even site:
+# two multi-RHS hopping terms (links 1152 + 4 x 24 in + 4 x 24 out, the second also reading
+# 4 x 24 of p), the x/r update (p, q, r read, r written: 4 x 4 x 24; x read and written:
+# 2 x 4 x 48) and p = r + beta p (3 x 4 x 24)
+BATCH_STEP_BYTES = 1344 + 1440 + 768 + 288
+# one FP64 reliable update for 4 right-hand sides: two FP64 multi-RHS hopping terms, r = b - Ax
+# (2 reads, 1 write of 4 x 48) and the conversion to FP32 (4 x 48 read, 4 x 24 read/written)
+BATCH_RU_BYTES = (2304 + 2 * 4 * 48) * 2 + 4 * 48 + 3 * 4 * 48 + 4 * 48 + 2 * 4 * 24
+# network (per site of the full lattice): four layers, each reading its site's 8 stored FP32
+# fat links (4 forward, 4 backward: 8 x 72 bytes) and its input channels and writing its
+# output channels (FP32 complex colour vectors, 24 bytes each): 1->8, 8->8, 8->8, 8->1
+NET_BYTES_PER_SITE = 4 * 576 + (24 + 192) + 2 * (192 + 192) + (192 + 24)
+
+
+def batch_model_bytes(stats, vhs, nrhs=4):
+    """Algorithmic bytes of one batched solve: a lattice takes CG steps while any of its
+    right-hand sides iterates, and reliable updates while any is due."""
+    total = 0.0
+    for l, vh in enumerate(vhs):
+        st = stats[l * nrhs:(l + 1) * nrhs]
+        total += vh * (max(x["iters"] for x in st) * BATCH_STEP_BYTES +
+                       max(x["reliable_updates"] for x in st) * BATCH_RU_BYTES)
+    return total
+
+
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "dslash_32x32x32x32_hbm_traffic.md")
 KERNEL_SOURCES = ["dslash.hip", "ks_device.h", "ks_common.h"]
 
 
-def measured_traffic(variant: str):
-    """HBM bytes per launch from the committed counter summary, or None once the kernel
-    sources differ from the ones the counters were taken on."""
+def measured_traffic(variant: str, threads: int, group: int):
+    """HBM bytes per launch of one kernel instantiation (variant, threads per block, links per
+    pass) from the committed counter summary, or None once the kernel sources differ from the
+    ones the counters were taken on."""
     import hashlib
     if not os.path.exists(TRAFFIC_SUMMARY):
         return None
@@ -58,13 +84,13 @@ def measured_traffic(variant: str):
     values, recorded = {}, None
     for line in open(TRAFFIC_SUMMARY):
         parts = line.split()
-        if len(parts) == 3 and parts[0] == "traffic_bytes_per_launch":
-            values[parts[1]] = float(parts[2])
+        if len(parts) == 5 and parts[0] == "traffic_bytes_per_launch":
+            values[(parts[1], int(parts[2]), int(parts[3]))] = float(parts[4])
         elif len(parts) == 2 and parts[0] == "source_hash":
             recorded = parts[1]
     if recorded != h.hexdigest()[:16]:
         return None
-    return values.get(variant)
+    return values.get((variant, threads, group))
 
 
 def cpu_baseline(g, b, budget_s: float = 12.0):
@@ -104,31 +130,36 @@ def learned48(args):
         G.prepare(p, 18)
         G.tune(p, 18)
     origins = learn.block_origins(dims, (16, 16, 16, 16))
-    # inputs first (block fields cut on the host and loaded), then the timed solver work
+    # 248 block pairs: two sources on each of the 108 blocks, two more on the first 16, each
+    # group solved by one batched FP64 CG; then 8 full-lattice pairs
     t1 = time.perf_counter()
-    jobs = []
+    blocks = [subblock(g, o, (16, 16, 16, 16)) for o in origins]
     k = 0
-    for j, o in enumerate(origins):
-        bk = subblock(g, o, (16, 16, 16, 16))
-        Gk = ks.Gauge(bk.dims, bk.fat, bk.naik)
-        nsrc = 3 if j < 248 - 2 * len(origins) else 2
-        jobs.append((Gk, [gaussian_source(bk.volume // 2, SEEDS["train_source"](k + r))
-                          for r in range(nsrc)]))
-        k += nsrc
-    log("%d block fields cut and loaded in %.1f s (input preparation, not timed)"
-        % (len(jobs), time.perf_counter() - t1))
+    groups = []
+    for sel in (range(len(blocks)), range(248 // 2 - len(blocks))):
+        srcs = []
+        for j in sel:
+            srcs.append([gaussian_source(blocks[j].volume // 2, SEEDS["train_source"](k + r))
+                         for r in range(2)])
+            k += 2
+        groups.append(([blocks[j] for j in sel], srcs))
+    log("%d block fields cut in %.1f s (input preparation, not timed)"
+        % (len(blocks), time.perf_counter() - t1))
+    pairs, t_blocks = [], 0.0
+    for fields, srcs in groups:
+        pp, dt, st = learn.solve_pairs_batched(fields, srcs, mass)
+        pairs += pp
+        t_blocks += dt
+        log("%d block pairs in %.1f s (batched FP64 CG, iterations %d-%d)"
+            % (len(pp), dt, min(x["iters"] for x in st), max(x["iters"] for x in st)))
+    del blocks, groups
     t_gen0 = time.perf_counter()
-    pairs = []
-    for Gk, srcs in jobs:
-        pairs += learn.solve_pairs(Gk, mass, srcs)
-    t_blocks = time.perf_counter() - t_gen0
-    log("%d block pairs in %.1f s" % (len(pairs), t_blocks))
     full = []
     for r in range(8):
         full += learn.solve_pairs(G, mass, [gaussian_source(vh, SEEDS["train_source"](10000 + r))])
         log("full-lattice pair %d done" % r)
     pairs += full
-    t_gen = time.perf_counter() - t_gen0
+    t_gen = t_blocks + time.perf_counter() - t_gen0
     net = ks.Net(flatten_weights(net_init_weights(SEEDS["net_init"])))
     steps = 400
     hist, t_train = learn.train(net, pairs, steps=steps, batch=8, lr=2e-3)
@@ -220,7 +251,7 @@ def main():
         # a plain copy of known size (1 GiB read + 1 GiB written) calibrates the byte counters
         src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
-        torch.add(src, 1.0, out=dst)
+        ks.stream_copy(dst, src)
         for v in variants:
             ein, eout = fields[v[0]]
             for _ in range(args.dslash_only):
@@ -254,6 +285,7 @@ def main():
     bb = [torch.from_numpy(gaussian_source(x.volume // 2, SEEDS["batch_rhs"](j, r))).cuda()
           for j, x in enumerate(bg) for r in range(4)]
     bx = [torch.zeros_like(v) for v in bb]
+    bvh = [x.volume // 2 for x in bg]
     del bg
     batch_cfg = B.tune()
     log("batch of %d lattices x 4 RHS ready in %.1f s, schedule %s"
@@ -301,22 +333,33 @@ def main():
     from paper_1611_00728_amd import learn
     from ksinputs import subblock, net_init_weights, flatten_weights
     blocks = [subblock(g, o, (16, 16, 16, 16)) for o in learn.block_origins(DIMS, (16, 16, 16, 16))]
-    jobs = [(ks.Gauge(bk.dims, bk.fat, bk.naik),
-             [gaussian_source(bk.volume // 2, SEEDS["train_source"](4 * j + r)) for r in range(4)])
+    srcs = [[gaussian_source(bk.volume // 2, SEEDS["train_source"](4 * j + r)) for r in range(4)]
             for j, bk in enumerate(blocks)]
+    pairs, t_blocks, _ = learn.solve_pairs_batched(blocks, srcs, MASS)
     t_gen0 = time.perf_counter()
-    pairs = []
-    for Gk, srcs in jobs:
-        pairs += learn.solve_pairs(Gk, MASS, srcs)
     pairs += learn.solve_pairs(G, MASS, [gaussian_source(vh, SEEDS["train_source"](1000 + r))
                                          for r in range(4)])
-    t_gen = time.perf_counter() - t_gen0
+    t_gen = t_blocks + time.perf_counter() - t_gen0
     del blocks
     net = ks.Net(flatten_weights(net_init_weights(SEEDS["net_init"])))
     loss_hist, t_train = learn.train(net, pairs, steps=300, batch=8, lr=2e-3)
     log("learned preconditioner: %d pairs in %.1f s, 300 Adam steps in %.1f s, loss %.4f -> %.4f"
         % (len(pairs), t_gen, t_train, loss_hist[0], loss_hist[-1]))
     learned_runs = []
+    net_times = {"f32": [], "mfma": []}
+    net_out = torch.zeros_like(bd)
+
+    def net_burst(record):
+        for name in ("f32", "mfma"):
+            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                   for _ in range(5)]
+            for e0, e1 in evs:
+                e0.record(stream)
+                net.apply(G, bd, net_out, mfma=(name == "mfma"))
+                e1.record(stream)
+            stream.synchronize()
+            if record:
+                net_times[name].extend(a.elapsed_time(c) * 1e-3 for a, c in evs)
 
     def learned(record):
         xd = torch.zeros_like(bd)
@@ -337,6 +380,7 @@ def main():
             burst(v, record)
         batch_solve(record)
         multishift(record)
+        net_burst(record)
         learned(record)
         for name, kw in solve_cfg.items():
             xd = torch.zeros_like(bd)
@@ -375,7 +419,8 @@ def main():
         st = rs[-1][1]
         tts[name] = {"seconds": med, "iters": st["iters"], "reliable_updates": st["reliable_updates"],
                      "true_rel_resid": st["true_rel_resid"], "speedup_vs_f64": base / med,
-                     "model_GBps": st["model_bytes"] / st["seconds"] / 1e9}
+                     "model_GBps": st["model_bytes"] / st["seconds"] / 1e9,
+                     "frac_of_8TBps": st["model_bytes"] / st["seconds"] / 1e9 / HBM_PEAK_GBS}
     walls = [w for w, _ in batch_runs]
     per_solve = [x["seconds"] for _, st in batch_runs for x in st]
     worst = max(x["true_rel_resid"] for _, st in batch_runs for x in st)
@@ -386,6 +431,7 @@ def main():
              "p50_seconds_per_solve": float(np.percentile(per_solve, 50)),
              "p99_seconds_per_solve": float(np.percentile(per_solve, 99)),
              "max_true_rel_resid": worst,
+             "model_GBps": batch_model_bytes(batch_runs[-1][1], bvh) / float(np.median(walls)) / 1e9,
              "iters_range": [min(x["iters"] for _, st in batch_runs for x in st),
                              max(x["iters"] for _, st in batch_runs for x in st)],
              "schedule": batch_cfg}
@@ -399,10 +445,13 @@ def main():
         # updates per site) plus the per-shift refinement steps of a single-mass CG
         flops = ms_vh * (shared * (2 * 1146 + 12 + 12 + 9 * 24 + 12) +
                          sum(x["iters"] - shared for x in st) * (2 * 1146 + 72))
+        mbytes = sum(x["model_bytes"] for x in st)
         msr[name] = {"seconds": med, "shared_iters": shared,
                      "total_iters_per_shift": [x["iters"] for x in st],
                      "max_true_rel_resid": max(x["true_rel_resid"] for x in st),
-                     "model_gflops": flops / med / 1e9}
+                     "model_gflops": flops / med / 1e9,
+                     "model_GBps": mbytes / med / 1e9,
+                     "frac_of_8TBps": mbytes / med / 1e9 / HBM_PEAK_GBS}
     msr["lattice"] = list(MS_DIMS)
     msr["shifts"] = "sigma_i = 4 m_i^2, m_i = geomspace(0.002, 0.5, 9), tol 1e-9 per shift"
 
@@ -422,18 +471,33 @@ def main():
                      if lmed < t_mixed else None,
                      "amortised_per_solve_s_over_100_solves": overhead / 100.0}}
 
-    # achievable-bandwidth reference: a plain elementwise pass (1 GiB read + 1 GiB written)
+    network = {}
+    for name, ts in net_times.items():
+        avg = float(np.mean(ts))
+        network[name] = {"avg_us": avg * 1e6,
+                         "model_GBps": NET_BYTES_PER_SITE * 2 * vh / avg / 1e9,
+                         "frac_of_8TBps": NET_BYTES_PER_SITE * 2 * vh / avg / 1e9 / HBM_PEAK_GBS}
+    network["model_bytes_per_site"] = NET_BYTES_PER_SITE
+    network["lattice"] = list(DIMS)
+
+    # achievable-bandwidth references (1 GiB read + 1 GiB written): the library's streaming
+    # copy kernel and torch's elementwise add
     src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
     dst = torch.empty_like(src)
-    for _ in range(3):
-        torch.add(src, 1.0, out=dst)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(10):
-        torch.add(src, 1.0, out=dst)
-    e1.record(stream)
-    stream.synchronize()
-    copy_gbps = 2 * src.numel() * 8 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+
+    def copy_rate(fn):
+        for _ in range(3):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(10):
+            fn()
+        e1.record(stream)
+        stream.synchronize()
+        return 2 * src.numel() * 8 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+
+    copy_gbps = copy_rate(lambda: ks.stream_copy(dst, src))
+    torch_gbps = copy_rate(lambda: torch.add(src, 1.0, out=dst))
     del src, dst
     cpu = None
     if not args.no_cpu_baseline:
@@ -455,14 +519,18 @@ def main():
                    "lattice": list(DIMS), "mass": MASS, "tol": TOL, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": head["model_GBps"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": head["model_GBps"] / HBM_PEAK_GBS,
-                     "traffic": measured_traffic("f64_r18"),
-                     "kernel": "dslash_kernel<F64,18,false>",
+                     "traffic": measured_traffic("f64_r18", tuned["f64_r18"]["threads"],
+                                                 tuned["f64_r18"]["links_per_pass"]),
+                     "kernel": "dslash_kernel<F64,18,false,%d,%d>" % (
+                         tuned["f64_r18"]["threads"], tuned["f64_r18"]["links_per_pass"]),
                      "bytes_per_launch": model_bytes_per_site("f64", 18) * vh,
-                     "copy_GBps": copy_gbps, "frac_of_copy": head["model_GBps"] / copy_gbps},
+                     "copy_GBps": copy_gbps, "frac_of_copy": head["model_GBps"] / copy_gbps,
+                     "torch_elementwise_GBps": torch_gbps},
         "dslash": dsl,
         "time_to_solution": tts,
         "batch": batch,
         "multishift": msr,
+        "network": network,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -282,6 +282,15 @@ ks_status_t ks_fcg_solve(ks_gauge_t g, ks_net_t n, double mass, const double* b_
                          double* x_dev, const ks_solver_params* p, int use_mfma,
                          ks_solver_stats* st, hipStream_t stream);
 
+/* ------------------------------------------------------------------ measurement */
+
+/* dst_dev = src_dev: a streaming device copy (one 16-byte non-temporal load and one store per
+ * thread), the achievable-HBM-bandwidth reference that the memory-bound kernels
+ * above are measured against (Sec. 4 judges the solver by its memory bandwidth).  bytes and
+ * both addresses must be multiples of 16 and the buffers must not overlap, else KS_ERR_ARG.
+ * Asynchronous on `stream`. */
+ks_status_t ks_stream_copy(void* dst_dev, const void* src_dev, size_t bytes, hipStream_t stream);
+
 /* Message of the calling thread's last failure ("" if none). */
 const char* ks_last_error(void);
 

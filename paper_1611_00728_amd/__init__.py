@@ -92,6 +92,7 @@ def lib():
         L.ks_dslash_config.argtypes = [_vp, C.c_int, C.c_int, C.POINTER(C.c_int),
                                        C.POINTER(C.c_int), C.POINTER(C.c_int),
                                        C.POINTER(C.c_float)]
+        L.ks_stream_copy.argtypes = [_vp, _vp, C.c_size_t, _vp]
         L.ks_dslash_set_config.argtypes = [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
         L.ks_cg_solve.argtypes = [_vp, C.c_double, _vp, _vp, C.POINTER(SolverParams),
                                   C.POINTER(SolverStats), _vp]
@@ -236,6 +237,17 @@ class Field:
 
 def dslash_eo(gauge: Gauge, out: Field, inp: Field, recon: int = RECON_18, stream=None):
     _check(lib().ks_dslash_eo(gauge.handle, out.handle, inp.handle, recon, _stream(stream)))
+
+
+def stream_copy(dst, src, stream=None):
+    """dst = src (device tensors of equal byte size) by the library's streaming copy kernel."""
+    n = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != n or not (src.is_cuda and dst.is_cuda):
+        raise ValueError("stream_copy: two device tensors of equal byte size expected")
+    if not (src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("stream_copy: contiguous tensors expected")
+    _check(lib().ks_stream_copy(dst.data_ptr(), src.data_ptr(), n, _stream(stream)))
+    return dst
 
 
 def apply_A(gauge: Gauge, sigma: float, x, out, stream=None):

@@ -1,6 +1,7 @@
 // C ABI of libks (declared in include/ks.h): argument checks, handle management, error
 // reporting.  Every entry point catches the library's internal failures and returns a code.
 #include <cstdarg>
+#include <cstdint>
 #include <cstring>
 #include <vector>
 
@@ -532,6 +533,21 @@ ks_status_t ks_fcg_solve(ks_gauge_t g, ks_net_t n, double mass, const double* b_
     KS_HIP(hipStreamSynchronize(stream));
     if (st) *st = local;
     return rc;
+    KS_API_END
+}
+
+ks_status_t ks_stream_copy(void* dst_dev, const void* src_dev, size_t bytes, hipStream_t stream)
+{
+    KS_API_BEGIN
+    KS_REQUIRE(bytes == 0 || (dst_dev && src_dev), KS_ERR_ARG, "ks_stream_copy: null pointer");
+    KS_REQUIRE(bytes % 16 == 0 && ((uintptr_t)dst_dev | (uintptr_t)src_dev) % 16 == 0, KS_ERR_ARG,
+               "ks_stream_copy: bytes and both addresses must be multiples of 16");
+    const char* d = static_cast<const char*>(dst_dev);
+    const char* sp = static_cast<const char*>(src_dev);
+    KS_REQUIRE(bytes == 0 || d + bytes <= sp || sp + bytes <= d, KS_ERR_ARG,
+               "ks_stream_copy: buffers overlap");
+    stream_copy(dst_dev, src_dev, bytes, stream);
+    return KS_SUCCESS;
     KS_API_END
 }
 

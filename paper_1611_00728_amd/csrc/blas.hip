@@ -1,5 +1,7 @@
 // Deterministic FP64 reductions, field import/export and the fused BLAS-1 steps of CG.
 #include "ks_device.h"
+#include <algorithm>
+
 #include "ks_blas.h"
 
 namespace ks {
@@ -363,6 +365,32 @@ void cg_beta(const double* part, int n, CGState* st, hipStream_t s)
 void cg_reliable(const double* part, int n, CGState* st, int initial, hipStream_t s)
 {
     cg_reliable_kernel<<<1, kFinish, 0, s>>>(part, n, st, initial);
+    KS_HIP(hipGetLastError());
+}
+
+namespace {
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// dst = src in 16-byte units, one unit per thread, the load non-temporal (measured on gfx950:
+// a one-shot grid beats grid-stride loops and multi-unit threads by 10-30 % here)
+__global__ __launch_bounds__(256) void stream_copy_kernel(const u32x4* __restrict__ src,
+                                                          u32x4* __restrict__ dst, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) dst[i] = __builtin_nontemporal_load(src + i);
+}
+
+}  // namespace
+
+void stream_copy(void* dst, const void* src, size_t bytes, hipStream_t s)
+{
+    const size_t n = bytes / 16;
+    if (n == 0) return;
+    const size_t blocks = (n + 255) / 256;
+    KS_REQUIRE(blocks <= 0x7fffffffu, KS_ERR_ARG, "stream_copy: %zu bytes is too large", bytes);
+    stream_copy_kernel<<<(unsigned)blocks, 256, 0, s>>>(static_cast<const u32x4*>(src),
+                                                        static_cast<u32x4*>(dst), n);
     KS_HIP(hipGetLastError());
 }
 

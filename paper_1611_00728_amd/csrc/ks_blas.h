@@ -36,5 +36,8 @@ void cg_alpha(const double* part, int n, CGState* st, hipStream_t s);
 void cg_beta(const double* part, int n, CGState* st, hipStream_t s);
 void cg_reliable(const double* part, int n, CGState* st, int initial, hipStream_t s);
 void finish_to(const double* part, int n, double* out, hipStream_t s);
+// dst = src, bytes a multiple of 16, both 16-byte aligned (a streaming copy: the
+// achievable-bandwidth reference of the memory-bound kernels)
+void stream_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 
 }  // namespace ks

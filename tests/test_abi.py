@@ -68,3 +68,11 @@ def test_null_handles_rejected(libks):
     assert libks.ks_gauge_prepare(None, 0, 18, None) == -1
     assert libks.ks_gauge_free(None) == 0
     assert libks.ks_field_free(None) == 0
+
+
+def test_stream_copy_argument_checks(libks):
+    """Sizes and addresses that are not multiples of 16, and overlapping buffers, are refused
+    before any device work."""
+    for dst, src, n in ((4096, 8192, 20), (4100, 8192, 32), (4096, 8200, 32), (4096, 4112, 64)):
+        assert libks.ks_stream_copy(dst, src, n, None) == -1
+    assert libks.ks_stream_copy(None, None, 0, None) == 0

@@ -122,6 +122,32 @@ def test_training_reduces_loss(ks, lat):
     net.free()
 
 
+def test_batched_training_pairs(ks):
+    """Training pairs from blocks cut out of a larger lattice, solved together by the batched
+    FP64 CG: every x solves its own block's system to the oracle's FP64 residual, and the pair
+    carries that block's gauge handle."""
+    announce("batched training pairs")
+    import torch
+    from ksinputs import subblock
+    from paper_1611_00728_amd import learn
+    big = make_gauge((8, 8, 8, 8), 0.5, 91, keep_thin=True)
+    origins = learn.block_origins(big.dims, (4, 4, 8, 8))
+    assert len(origins) == 4
+    blocks = [subblock(big, o, (4, 4, 8, 8)) for o in origins]
+    srcs = [[gaussian_source(bk.volume // 2, 300 + 2 * j + r) for r in range(2)]
+            for j, bk in enumerate(blocks)]
+    pairs, secs, stats = learn.solve_pairs_batched(blocks, srcs, 0.05, tol=1e-10)
+    assert len(pairs) == 8 and secs > 0 and all(s["status"] == 0 for s in stats)
+    sigma = 4 * 0.05 ** 2
+    for k, (G, b, x) in enumerate(pairs):
+        bk = blocks[k // 2]
+        assert G.dims == tuple(bk.dims)
+        assert np.array_equal(host(b), srcs[k // 2][k % 2])
+        xh = host(x)
+        r = np.linalg.norm(host(b) - oracle.apply_A(bk, sigma, xh)) / np.linalg.norm(host(b))
+        assert r <= 1e-10
+
+
 @pytest.mark.parametrize("inner", ["f64", "f32"])
 def test_fcg_identity_matches_cg(ks, lat, inner):
     announce("fcg identity", inner)
