@@ -8,18 +8,19 @@ and never imports it; the two meet only in the seeded inputs of `ksinputs`.
   and multi-shift CG, each written out from its definition (Sec. 3 and Sec. 4 name these
   routines; the formulas are restated in that file's header).
 * `network.py`: the gauge-covariant preconditioner network, its loss, gradients and Adam.
-* `solvers.py`: flexible CG with a preconditioner and the quantise-then-FP64 references of
-  the reduced-precision storage formats.
+* `solvers.py`: flexible CG with a preconditioner; M = 2m + D on the full lattice and its
+  solve through the even-odd Schur complement with odd-site reconstruction.
+* `quant.py`: the quantise-then-FP64 references of the reduced-precision storage formats.
 """
 from .core import (lib, dslash_full, dslash_eo, apply_A, cg, multishift_cg, embed, restrict,
                    CGInfo, dense_A, lanczos_extremes, OracleError)
 from .quant import quantise_f32, quantise_f16_sites, quantise_f16_links, f16_link_exponent
 from .network import (Network, PATHS, transport, transport_adj, layer_forward,
                       network_forward, loss_and_grad, adam_step, neighbour_tables)
-from .solvers import fcg
+from .solvers import fcg, apply_M, full_solve, FullInfo
 
 __all__ = ["lib", "dslash_full", "dslash_eo", "apply_A", "cg", "multishift_cg", "embed",
            "restrict", "CGInfo", "dense_A", "lanczos_extremes", "OracleError", "quantise_f32",
            "quantise_f16_sites", "quantise_f16_links", "f16_link_exponent", "Network", "PATHS",
            "transport", "transport_adj", "layer_forward", "network_forward", "loss_and_grad",
-           "adam_step", "neighbour_tables", "fcg"]
+           "adam_step", "neighbour_tables", "fcg", "apply_M", "full_solve", "FullInfo"]
