@@ -180,6 +180,18 @@ ks_status_t ks_multishift_cg_solve(ks_gauge_t g, int nshift, const double* sigma
                                    const double* tol, const ks_solver_params* p,
                                    ks_solver_stats* st, hipStream_t stream);
 
+/* Solves the full staggered system M x = b on both parities, M = 2m + D (mass > 0), by the
+ * even-odd reduction of Sec. 3 with the odd sites reconstructed: the even system
+ * (4 m^2 - D_eo D_oe) x_e = 2m b_e - D_eo b_o is solved by ks_cg_solve's method (p->inner,
+ * p->recon, reliable updates, restarts) to the tolerance that makes |b - M x| <= p->tol |b|,
+ * then x_o = (b_o - D_oe x_e) / (2m) in FP64.  b_even, b_odd: device complex128 [Vh][3] of the
+ * two parities; x_even: initial guess in, solution out; x_odd: output.  No argument may alias
+ * another.  st->true_rel_resid is the FP64 |b - M x| / |b| over both parities, recomputed at
+ * the end; KS_ERR_NOT_CONVERGED if it exceeds p->tol.  Synchronises the stream. */
+ks_status_t ks_full_solve(ks_gauge_t g, double mass, const double* b_even, const double* b_odd,
+                          double* x_even, double* x_odd, const ks_solver_params* p,
+                          ks_solver_stats* st, hipStream_t stream);
+
 /* ------------------------------------------------------------------ batched solves */
 
 /* Many independent lattices (uneven sizes allowed), each with nrhs right-hand sides, solved
@@ -250,8 +262,9 @@ ks_status_t ks_net_get_weights(ks_net_t n, double* weights);
 ks_status_t ks_net_free(ks_net_t n);
 
 /* out_dev = N(in_dev), complex128 [Vh][3] device arrays of the handle's lattice.  use_mfma = 0:
- * FP32 channel mixing on the vector ALUs; 1: the two 8 -> 8 layers mix on the matrix cores
- * (binary16 operands, FP32 accumulation).  Transports in FP32 with the FP32 fat links.
+ * FP32 channel mixing on the vector ALUs, transports with the FP32 fat links; 1: the 8 -> 8 and
+ * 8 -> 1 layers mix on the matrix cores (binary16 operands, FP32 accumulation) and transport
+ * in FP32 arithmetic with the binary16 fat-link store (built on first use).
  * Synchronous with respect to `stream` order only (no host wait). */
 ks_status_t ks_net_apply(ks_net_t n, ks_gauge_t g, const double* in_dev, double* out_dev,
                          int use_mfma, hipStream_t stream);

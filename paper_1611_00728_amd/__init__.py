@@ -96,6 +96,8 @@ def lib():
         L.ks_dslash_set_config.argtypes = [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
         L.ks_cg_solve.argtypes = [_vp, C.c_double, _vp, _vp, C.POINTER(SolverParams),
                                   C.POINTER(SolverStats), _vp]
+        L.ks_full_solve.argtypes = [_vp, C.c_double, _vp, _vp, _vp, _vp, C.POINTER(SolverParams),
+                                    C.POINTER(SolverStats), _vp]
         L.ks_multishift_cg_solve.argtypes = [_vp, C.c_int, C.POINTER(C.c_double), _vp,
                                              C.POINTER(_vp), C.POINTER(C.c_double),
                                              C.POINTER(SolverParams), C.POINTER(SolverStats), _vp]
@@ -275,6 +277,22 @@ def cg_solve(gauge: Gauge, mass: float, b, x, params: SolverParams | None = None
     rc = lib().ks_cg_solve(gauge.handle, float(mass), _dev_vec(b, gauge.vh, "b"),
                            _dev_vec(x, gauge.vh, "x"),
                            C.byref(p), C.byref(st), _stream(stream))
+    if rc != 0 and raise_on_error:
+        _check(rc)
+    return SolveResult(rc, st.as_dict())
+
+
+def full_solve(gauge: Gauge, mass: float, b_even, b_odd, x_even, x_odd,
+               params: SolverParams | None = None, stream=None,
+               raise_on_error: bool = True) -> SolveResult:
+    """(2m + D) x = b on both parities; x_even holds the initial guess of the even solve."""
+    p = params if params is not None else default_params()
+    st = SolverStats()
+    rc = lib().ks_full_solve(gauge.handle, float(mass), _dev_vec(b_even, gauge.vh, "b_even"),
+                             _dev_vec(b_odd, gauge.vh, "b_odd"),
+                             _dev_vec(x_even, gauge.vh, "x_even"),
+                             _dev_vec(x_odd, gauge.vh, "x_odd"), C.byref(p), C.byref(st),
+                             _stream(stream))
     if rc != 0 and raise_on_error:
         _check(rc)
     return SolveResult(rc, st.as_dict())

@@ -1,5 +1,6 @@
 // C ABI of libks (declared in include/ks.h): argument checks, handle management, error
 // reporting.  Every entry point catches the library's internal failures and returns a code.
+#include <cmath>
 #include <cstdarg>
 #include <cstdint>
 #include <cstring>
@@ -329,6 +330,41 @@ ks_status_t ks_cg_solve(ks_gauge_t g, double mass, const double* b_dev, double* 
     const ks_status_t rc = cg_core(g, 4.0 * mass * mass, static_cast<const double*>(w.b64),
                                    static_cast<double*>(w.x64), *p, local, stream);
     export_field(g->geom, KS_F64, w.x64, x_dev, stream);
+    KS_HIP(hipStreamSynchronize(stream));
+    if (st) *st = local;
+    return rc;
+    KS_API_END
+}
+
+ks_status_t ks_full_solve(ks_gauge_t g, double mass, const double* b_even, const double* b_odd,
+                          double* x_even, double* x_odd, const ks_solver_params* p,
+                          ks_solver_stats* st, hipStream_t stream)
+{
+    KS_API_BEGIN
+    KS_REQUIRE(g && b_even && b_odd && x_even && x_odd, KS_ERR_ARG, "ks_full_solve: null argument");
+    KS_REQUIRE(mass > 0.0 && std::isfinite(mass), KS_ERR_ARG, "ks_full_solve: mass must be > 0");
+    const void* ins[2] = {b_even, b_odd};
+    const void* outs[2] = {x_even, x_odd};
+    for (const void* i : ins)
+        for (const void* o : outs)
+            KS_REQUIRE(i != o, KS_ERR_ARG, "ks_full_solve: a solution aliases a source");
+    KS_REQUIRE(x_even != x_odd && b_even != b_odd, KS_ERR_ARG, "ks_full_solve: aliased vectors");
+    check_params(p);
+    Workspace& w = workspace(g);
+    const size_t fb = field_bytes(g->geom, KS_F64);
+    for (double*& v : w.full)
+        if (!v) {
+            v = static_cast<double*>(device_alloc(fb));
+            w.bytes += fb;
+        }
+    import_field(g->geom, KS_F64, b_even, w.b64, stream);
+    import_field(g->geom, KS_F64, b_odd, w.full[3], stream);
+    import_field(g->geom, KS_F64, x_even, w.x64, stream);
+    ks_solver_stats local;
+    const ks_status_t rc = full_solve_core(g, mass, w.b64, w.full[3], w.x64, w.full[4], *p, local,
+                                           stream);
+    export_field(g->geom, KS_F64, w.x64, x_even, stream);
+    export_field(g->geom, KS_F64, w.full[4], x_odd, stream);
     KS_HIP(hipStreamSynchronize(stream));
     if (st) *st = local;
     return rc;

@@ -37,6 +37,9 @@ struct Workspace {
     void* ms_t = nullptr;
     void* ms_st = nullptr;
     void* ms_st_host = nullptr;
+    // full-lattice solve, FP64 planes: even right-hand side of the Schur system, even and odd
+    // temporaries, and the odd b and x of the boundary call
+    double* full[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 
 Workspace& workspace(ks_gauge_t g);
@@ -51,6 +54,10 @@ double true_resid2(ks_gauge_t g, double sigma, const double* b, const double* x,
 
 ks_status_t cg_core(ks_gauge_t g, double sigma, const double* b, double* x,
                     const ks_solver_params& prm, ks_solver_stats& stats, hipStream_t s);
+// M x = b with M = 2m + D on both parities (internal FP64 planes; x_e: initial guess in)
+ks_status_t full_solve_core(ks_gauge_t g, double mass, const double* b_e, const double* b_o,
+                            double* x_e, double* x_o, const ks_solver_params& prm,
+                            ks_solver_stats& stats, hipStream_t s);
 ks_status_t multishift_core(ks_gauge_t g, int nshift, const double* sigma, const double* b,
                             double* const* x, const double* tol, const ks_solver_params& prm,
                             ks_solver_stats* stats, hipStream_t s);

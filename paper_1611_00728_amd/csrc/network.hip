@@ -483,6 +483,7 @@ void net_apply_mfma(NetCtx& n, ks_gauge_t g, const double* in, double* out, doub
                     hipStream_t s)
 {
     gauge_prepare(g, KS_F32, KS_RECON_18, s);
+    gauge_prepare(g, KS_F16, KS_RECON_18, s);
     net_mfma_prepare(n, s);
     NetBuffers& B = net_buffers(n, g->geom);
     const int vh = g->geom.Vh;
@@ -492,7 +493,7 @@ void net_apply_mfma(NetCtx& n, ks_gauge_t g, const double* in, double* out, doub
     layer<1, 8>(g, B.act[0], B.act[1], w + layer_weight_offset(0), s);
     net_layer_mfma(n, g, B.act[1], B.act[2], 1, s);
     net_layer_mfma(n, g, B.act[2], B.act[3], 2, s);
-    layer<8, 1>(g, B.act[3], B.act[4], w + layer_weight_offset(3), s);
+    net_layer_mfma(n, g, B.act[3], B.act[4], 3, s);
     net_extract_kernel<<<blocks_for(vh), kBlock, 0, s>>>(vh, B.act[4], 1.0 / in_scale,
                                                          reinterpret_cast<double2*>(out));
     KS_HIP(hipGetLastError());

@@ -1,8 +1,10 @@
 """GPU preconditioner network and flexible CG through the C ABI, against the FP64 oracle.
 
 Tolerances: the FP32 path (transports and mixing in FP32, four layers) 1e-5 relative L2 on
-outputs and 1e-4 on the gradient; the matrix-core path rounds the two 8 -> 8 layers' mixing
-operands to binary16 (unit roundoff 2^-11 ~ 4.9e-4, 72 terms per output), 3e-3.  One Adam
+outputs and 1e-4 on the gradient; the matrix-core path rounds the mixing operands (weights
+and transported values) of the 8 -> 8, 8 -> 8 and 8 -> 1 layers to binary16 (unit roundoff
+2^-11 ~ 4.9e-4 per operand, errors of 72 terms per output adding in quadrature: a few 1e-4
+per layer), 3e-3.  One Adam
 step moves each real by lr * g / (|g| + eps) ~ lr sign(g): weights after one step agree
 with the oracle's to 1e-6 wherever |g| is not tiny.
 """

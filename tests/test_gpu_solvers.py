@@ -183,3 +183,59 @@ def test_tuned_launches_keep_results(ks):
     for inner in ("f64", "f32", "f16"):
         x, r = solve(ks, G, 0.05, b, tol=1e-10, inner=inner, recon=12)
         assert r.ok and true_rel(g, 0.01, b, x) <= 1e-10
+
+
+@pytest.mark.parametrize("inner,recon", [("f64", 18), ("f32", 18), ("f16", 12)])
+@pytest.mark.parametrize("dims", [(8, 8, 8, 8), (6, 4, 8, 4)])
+def test_full_solve(ks, dims, inner, recon):
+    """M x = b on both parities (M = 2m + D): the oracle's FP64 |b - M x| / |b| of the returned
+    x is within tol, the reported residual matches it, and x agrees with the oracle's own full
+    solve within 2 tol cond(M).  D is anti-Hermitian, so M is normal with singular values
+    |2m + i lambda|: cond(M) = sqrt(lambda_max(A)) / (2m), A = 4m^2 - D_eo D_oe, lambda_max(A)
+    from the oracle's Lanczos estimate."""
+    announce("full solve", dims, inner, recon)
+    import torch
+    g = make_gauge(dims, 0.3, 61)
+    G = ks.Gauge(dims, g.fat, g.naik)
+    vh = g.volume // 2
+    m, tol = 0.1, 1e-10
+    b_e, b_o = gaussian_source(vh, 62), gaussian_source(vh, 63)
+    xe, xo = zeros_dev((vh, 3)), zeros_dev((vh, 3))
+    res = ks.full_solve(G, m, dev(b_e), dev(b_o), xe, xo,
+                        ks.default_params(tol=tol, inner=ks.PREC[inner], recon=recon))
+    torch.cuda.synchronize()
+    assert res.ok
+    he, ho = host(xe), host(xo)
+    me, mo = oracle.apply_M(g, m, he, ho)
+    nb = np.sqrt(np.linalg.norm(b_e) ** 2 + np.linalg.norm(b_o) ** 2)
+    tr = np.sqrt(np.linalg.norm(b_e - me) ** 2 + np.linalg.norm(b_o - mo) ** 2) / nb
+    assert tr <= tol
+    assert abs(res.stats["true_rel_resid"] - tr) <= 1e-3 * tr + 1e-15
+    oe, oo, _ = oracle.full_solve(g, m, b_e, b_o, 1e-12)
+    _, info = oracle.cg(g, 4 * m * m, b_e, 1e-10)
+    _, hi = oracle.lanczos_extremes(info.alpha, info.beta)
+    cond = np.sqrt(1.01 * hi) / (2 * m)
+    x = np.concatenate([he, ho])
+    xo_ = np.concatenate([oe, oo])
+    assert rel_l2(x, xo_) <= 2 * tol * cond
+
+
+def test_full_solve_special_cases(ks, cfg1):
+    """b_o = 0 gives x_e = 2m A^-1 b_e (the even-odd CG's solution scaled); b = 0 gives x = 0;
+    a non-positive mass is refused."""
+    announce("full solve special cases")
+    import torch
+    g, G, b, xo, kappa = cfg1
+    m = 0.1
+    z = np.zeros_like(b)
+    xe, xod = zeros_dev(b.shape), zeros_dev(b.shape)
+    res = ks.full_solve(G, m, dev(b), dev(z), xe, xod, ks.default_params(tol=1e-11))
+    torch.cuda.synchronize()
+    assert res.ok
+    assert rel_l2(host(xe), 2 * m * xo) <= 2 * (1e-11 + 1e-12) * kappa
+    res = ks.full_solve(G, m, dev(z), dev(z), xe, xod, ks.default_params(tol=1e-11))
+    torch.cuda.synchronize()
+    assert res.ok and np.all(host(xe) == 0) and np.all(host(xod) == 0)
+    with pytest.raises(ks.KSError) as e:
+        ks.full_solve(G, 0.0, dev(b), dev(z), xe, xod)
+    assert e.value.code == -1
