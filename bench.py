@@ -70,9 +70,9 @@ TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "dslash_32x32x32x32_hbm_traffic
 KERNEL_SOURCES = ["dslash.hip", "ks_device.h", "ks_common.h"]
 
 
-def measured_traffic(variant: str, threads: int, group: int):
+def measured_traffic(variant: str, threads: int, group: int, way: int):
     """HBM bytes per launch of one kernel instantiation (variant, threads per block, links per
-    pass) from the committed counter summary, or None once the kernel sources differ from the
+    pass, link access) from the committed counter summary, or None once the kernel sources differ from the
     ones the counters were taken on."""
     import hashlib
     if not os.path.exists(TRAFFIC_SUMMARY):
@@ -84,13 +84,13 @@ def measured_traffic(variant: str, threads: int, group: int):
     values, recorded = {}, None
     for line in open(TRAFFIC_SUMMARY):
         parts = line.split()
-        if len(parts) == 5 and parts[0] == "traffic_bytes_per_launch":
-            values[(parts[1], int(parts[2]), int(parts[3]))] = float(parts[4])
+        if len(parts) == 6 and parts[0] == "traffic_bytes_per_launch":
+            values[(parts[1], int(parts[2]), int(parts[3]), int(parts[4]))] = float(parts[5])
         elif len(parts) == 2 and parts[0] == "source_hash":
             recorded = parts[1]
     if recorded != h.hexdigest()[:16]:
         return None
-    return values.get((variant, threads, group))
+    return values.get((variant, threads, group, way))
 
 
 def cpu_baseline(g, b, budget_s: float = 12.0):
@@ -246,6 +246,35 @@ def main():
     for v in variants:
         tuned["%s_r%d" % v] = G.tune(pmap[v[0]], v[1])
     log("autotuned: %s" % json.dumps(tuned))
+
+    def time_variant(v, reps=20):
+        ein, eout = fields[v[0]]
+        for _ in range(3):
+            ks.dslash_eo(G, eout, ein, v[1])
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            ks.dslash_eo(G, eout, ein, v[1])
+        e1.record(stream)
+        stream.synchronize()
+        return e0.elapsed_time(e1) * 1e3 / reps
+
+    # 8-way vs 4-way link access (the storage question Sec. 3 leaves open), each variant at
+    # its tuned launch shape; the tuned configuration is restored afterwards
+    link_study = {}
+    if not args.dslash_only:
+        for v in variants:
+            key = "%s_r%d" % v
+            cfg = tuned[key]
+            row = {}
+            for way in (8, 4):
+                G.set_config(pmap[v[0]], v[1], cfg["threads"], cfg["lds_bytes"],
+                             cfg["links_per_pass"], way)
+                row["%d-way_us" % way] = time_variant(v)
+            G.set_config(pmap[v[0]], v[1], cfg["threads"], cfg["lds_bytes"], cfg["links_per_pass"],
+                         cfg["link_access"])
+            link_study[key] = row
+        log("link access study: %s" % json.dumps(link_study))
 
     if args.dslash_only:
         # a plain copy of known size (1 GiB read + 1 GiB written) calibrates the byte counters
@@ -542,13 +571,16 @@ def main():
         "roofline": {"bound": "hbm", "achieved": head["model_GBps"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": head["model_GBps"] / HBM_PEAK_GBS,
                      "traffic": measured_traffic("f64_r18", tuned["f64_r18"]["threads"],
-                                                 tuned["f64_r18"]["links_per_pass"]),
-                     "kernel": "dslash_kernel<F64,18,false,%d,%d>" % (
-                         tuned["f64_r18"]["threads"], tuned["f64_r18"]["links_per_pass"]),
+                                                 tuned["f64_r18"]["links_per_pass"],
+                                                 tuned["f64_r18"]["link_access"]),
+                     "kernel": "dslash_kernel<F64,18,false,%d,%d,%s>" % (
+                         tuned["f64_r18"]["threads"], tuned["f64_r18"]["links_per_pass"],
+                         "4-way" if tuned["f64_r18"]["link_access"] == 4 else "8-way"),
                      "bytes_per_launch": model_bytes_per_site("f64", 18) * vh,
                      "copy_GBps": copy_gbps, "frac_of_copy": head["model_GBps"] / copy_gbps,
                      "torch_elementwise_GBps": torch_gbps},
         "dslash": dsl,
+        "link_access_study": link_study,
         "time_to_solution": tts,
         "batch": batch,
         "multishift": msr,

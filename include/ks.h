@@ -140,17 +140,21 @@ ks_status_t ks_dslash_eo(ks_gauge_t g, ks_field_t out, ks_field_t in, ks_recon_t
 ks_status_t ks_tune_dslash(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, hipStream_t stream);
 
 /* The launch configuration in use for a variant: threads per block, LDS bytes per block, link
- * matrices loaded per pass of the per-site loop (1, 2 or 4) and the tuned time per launch in
+ * matrices loaded per pass of the per-site loop (1, 2 or 4), link access (8: every site reads
+ * its own 16 stored matrices, the 8-way storage of Sec. 3; 4: the backward matrices are formed
+ * from the forward links of the neighbour sites, so only the forward half of the storage is
+ * read, the 4-way alternative that Sec. 3 leaves untested) and the tuned time per launch in
  * microseconds (0 if never tuned).  Any output may be NULL. */
 ks_status_t ks_dslash_config(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, int* threads,
-                             int* lds_bytes, int* links_per_pass, float* tuned_us);
+                             int* lds_bytes, int* links_per_pass, int* link_access,
+                             float* tuned_us);
 
 /* Sets a variant's launch configuration by hand (replacing the tuned one): threads 64, 128 or
- * 256; lds_bytes 0 to 65536 (the dynamic LDS requested per block, which caps how many blocks
- * share a CU); links_per_pass 1 or 2 (4 also for FP32 and FP16 with 18-real Naik; FP64 with
- * 12-real Naik takes 1 only).  KS_ERR_ARG for any other value. */
+ * 256; lds_bytes 0 to the device's LDS per workgroup (the dynamic LDS requested per block,
+ * which caps how many blocks share a CU); links_per_pass 1 or 2 (4 also for FP32 and FP16 with 18-real Naik; FP64 with
+ * 12-real Naik takes 1 only); link_access 8 or 4.  KS_ERR_ARG for any other value. */
 ks_status_t ks_dslash_set_config(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, int threads,
-                                 int lds_bytes, int links_per_pass);
+                                 int lds_bytes, int links_per_pass, int link_access);
 
 /* out_dev = (sigma - D_eo D_oe) in_dev in FP64 on even sites, complex128 [Vh][3] device
  * arrays (in_dev != out_dev).  Asynchronous. */

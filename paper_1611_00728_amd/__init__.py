@@ -91,9 +91,10 @@ def lib():
         L.ks_tune_dslash.argtypes = [_vp, C.c_int, C.c_int, _vp]
         L.ks_dslash_config.argtypes = [_vp, C.c_int, C.c_int, C.POINTER(C.c_int),
                                        C.POINTER(C.c_int), C.POINTER(C.c_int),
-                                       C.POINTER(C.c_float)]
+                                       C.POINTER(C.c_int), C.POINTER(C.c_float)]
         L.ks_stream_copy.argtypes = [_vp, _vp, C.c_size_t, _vp]
-        L.ks_dslash_set_config.argtypes = [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
+        L.ks_dslash_set_config.argtypes = [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                           C.c_int]
         L.ks_cg_solve.argtypes = [_vp, C.c_double, _vp, _vp, C.POINTER(SolverParams),
                                   C.POINTER(SolverStats), _vp]
         L.ks_full_solve.argtypes = [_vp, C.c_double, _vp, _vp, _vp, _vp, C.POINTER(SolverParams),
@@ -179,17 +180,17 @@ class Gauge:
         return self.config(prec, recon)
 
     def config(self, prec=F64, recon=RECON_18) -> dict:
-        nt, lds, grp, us = C.c_int(), C.c_int(), C.c_int(), C.c_float()
+        nt, lds, grp, way, us = C.c_int(), C.c_int(), C.c_int(), C.c_int(), C.c_float()
         _check(lib().ks_dslash_config(self.handle, prec, recon, C.byref(nt), C.byref(lds),
-                                      C.byref(grp), C.byref(us)))
+                                      C.byref(grp), C.byref(way), C.byref(us)))
         return {"threads": nt.value, "lds_bytes": lds.value, "links_per_pass": grp.value,
-                "tuned_us": us.value}
+                "link_access": way.value, "tuned_us": us.value}
 
     def set_config(self, prec=F64, recon=RECON_18, threads=256, lds_bytes=0,
-                   links_per_pass=1):
+                   links_per_pass=1, link_access=8):
         """Sets one variant's Dslash launch configuration by hand."""
         _check(lib().ks_dslash_set_config(self.handle, prec, recon, threads, lds_bytes,
-                                          links_per_pass))
+                                          links_per_pass, link_access))
 
     def device_bytes(self) -> int:
         return int(lib().ks_gauge_device_bytes(self.handle))

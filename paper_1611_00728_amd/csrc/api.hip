@@ -256,7 +256,8 @@ ks_status_t ks_tune_dslash(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, hipSt
 }
 
 ks_status_t ks_dslash_config(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, int* threads,
-                             int* lds_bytes, int* links_per_pass, float* tuned_us)
+                             int* lds_bytes, int* links_per_pass, int* link_access,
+                             float* tuned_us)
 {
     KS_API_BEGIN
     KS_REQUIRE(g, KS_ERR_ARG, "ks_dslash_config: null handle");
@@ -265,13 +266,14 @@ ks_status_t ks_dslash_config(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, int
     if (threads) *threads = t.nt;
     if (lds_bytes) *lds_bytes = t.lds;
     if (links_per_pass) *links_per_pass = t.group;
+    if (link_access) *link_access = t.way;
     if (tuned_us) *tuned_us = t.tuned ? t.us : 0.f;
     return KS_SUCCESS;
     KS_API_END
 }
 
 ks_status_t ks_dslash_set_config(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, int threads,
-                                 int lds_bytes, int links_per_pass)
+                                 int lds_bytes, int links_per_pass, int link_access)
 {
     KS_API_BEGIN
     KS_REQUIRE(g, KS_ERR_ARG, "ks_dslash_set_config: null handle");
@@ -279,15 +281,21 @@ ks_status_t ks_dslash_set_config(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon,
                "ks_dslash_set_config: bad precision/recon");
     KS_REQUIRE(threads == 64 || threads == 128 || threads == 256, KS_ERR_ARG,
                "ks_dslash_set_config: threads must be 64, 128 or 256");
-    KS_REQUIRE(lds_bytes >= 0 && lds_bytes <= 65536, KS_ERR_ARG,
-               "ks_dslash_set_config: lds_bytes must lie in [0, 65536]");
+    int dev = 0, lds_max = 0;
+    KS_HIP(hipGetDevice(&dev));
+    KS_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    KS_REQUIRE(lds_bytes >= 0 && lds_bytes <= lds_max, KS_ERR_ARG,
+               "ks_dslash_set_config: lds_bytes must lie in [0, %d]", lds_max);
     KS_REQUIRE(dslash_group_built(prec, recon, links_per_pass), KS_ERR_ARG,
                "ks_dslash_set_config: %d links per pass is not built for this variant",
                links_per_pass);
+    KS_REQUIRE(link_access == 8 || link_access == 4, KS_ERR_ARG,
+               "ks_dslash_set_config: link_access must be 8 or 4");
     TuneEntry t;
     t.nt = threads;
     t.lds = lds_bytes;
     t.group = links_per_pass;
+    t.way = link_access;
     g->tune[prec][recon_index(recon)] = t;
     return KS_SUCCESS;
     KS_API_END

@@ -23,6 +23,20 @@ __device__ __forceinline__ void matvec_acc(cx<R> acc[3], const cx<R> m[9], const
         for (int b = 0; b < 3; ++b) cfma(acc[a], m[a * 3 + b], v[b]);
 }
 
+// acc += m^+ v
+template <class R>
+__device__ __forceinline__ void matvec_adj_acc(cx<R> acc[3], const cx<R> m[9], const cx<R> v[3])
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const cx<R> e = m[b * 3 + a];
+            acc[a].r = fma(e.r, v[b].r, fma(e.i, v[b].i, acc[a].r));
+            acc[a].i = fma(e.r, v[b].i, fma(-e.i, v[b].r, acc[a].i));
+        }
+}
+
 // rows 0, 1 stored; row 2 = conj(row0 x row1)
 template <class R>
 __device__ __forceinline__ void reconstruct_row2(cx<R> m[9])
@@ -40,9 +54,15 @@ __device__ __forceinline__ void reconstruct_row2(cx<R> m[9])
     m[8] = {t.r, -t.i};
 }
 
-template <int P, int RECON, bool XPAY, int NT, int U>
+// W4: 4-way link access.  The backward matrices -V_mu(x-mu)^+ and -W_mu(x-3mu)^+ are formed
+// from the forward links of the neighbour sites (slots 0-3 of the other parity's store, read
+// at the neighbour's index) instead of the site's own backward slots 4-7, so only the forward
+// half of each store is read.
+template <int P, int RECON, bool XPAY, int NT, int U, bool W4>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void dslash_kernel(Geom g, int par, const void* __restrict__ fat,
                                                         const void* __restrict__ naik,
+                                                        const void* __restrict__ fat_o,
+                                                        const void* __restrict__ naik_o,
                                                         const void* __restrict__ in,
                                                         void* __restrict__ out,
                                                         const void* __restrict__ xv, double a,
@@ -75,27 +95,36 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void ds
 #pragma unroll 1
         for (int s0 = 0; s0 < 16; s0 += U) {
             cx<R> m[U][9], v[U][3];
+            const bool bwd4 = W4 && (s0 & 7) >= 4;   // U divides 4: a pass is all one kind
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int s = s0 + u;
-                if (s0 < 8) load_link<P, 9>(fat, s, vh, h, m[u]);
-                else if (RECON == 12) load_link<P, 6>(naik, s - 8, vh, h, m[u]);
-                else load_link<P, 9>(naik, s - 8, vh, h, m[u]);
+                if (bwd4) {
+                    if (s0 < 8) load_link<P, 9>(fat_o, s - 4, vh, nb[s], m[u]);
+                    else if (RECON == 12) load_link<P, 6>(naik_o, s - 12, vh, nb[s], m[u]);
+                    else load_link<P, 9>(naik_o, s - 12, vh, nb[s], m[u]);
+                } else {
+                    if (s0 < 8) load_link<P, 9>(fat, s, vh, h, m[u]);
+                    else if (RECON == 12) load_link<P, 6>(naik, s - 8, vh, h, m[u]);
+                    else load_link<P, 9>(naik, s - 8, vh, h, m[u]);
+                }
                 Spinor<P>::load(in, vh, nb[s], v[u]);
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 R sc;
                 if (s0 < 8) {
-                    sc = (R)fat_scale;
+                    sc = (R)(bwd4 ? -fat_scale : fat_scale);
                 } else if (RECON == 12) {
+                    // the sign of the 8-way slot covers the backward minus and adjoint
                     reconstruct_row2(m[u]);
                     sc = (R)(naik_c0 * naik_sign(c, s0 + u - 8, g.n[3]));
                 } else {
-                    sc = (R)naik_scale;
+                    sc = (R)(bwd4 ? -naik_scale : naik_scale);
                 }
                 cx<R> t[3] = {{0, 0}, {0, 0}, {0, 0}};
-                matvec_acc(t, m[u], v[u]);
+                if (bwd4) matvec_adj_acc(t, m[u], v[u]);
+                else matvec_acc(t, m[u], v[u]);
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
                     res[k].r = fma(sc, t[k].r, res[k].r);
@@ -138,22 +167,29 @@ constexpr bool group_built(int P, int RECON, int U)
            (U == 4 && P != KS_F64 && RECON == 18);
 }
 
-template <int P, int RECON, int NT, int U>
-void launch_u(const LinkStore& st, const Geom& G, double c0, const DslashArgs& a, int lds,
+template <int P, int RECON, int NT, int U, bool W4>
+void launch_w(const LinkStore& st, const Geom& G, double c0, const DslashArgs& a, int lds,
               hipStream_t s)
 {
     const int nb = blocks_for(G.Vh, NT);
-    const void* fat = st.fat[a.out_parity];
-    const void* naik = st.naik[a.out_parity];
+    const int p = a.out_parity;
     if (a.x)
-        dslash_kernel<P, RECON, true, NT, U><<<nb, NT, lds, s>>>(
-            G, a.out_parity, fat, naik, a.in, a.out, a.x, a.a, a.dot_partials, a.gate,
-            st.fat_scale, st.naik_scale, c0);
+        dslash_kernel<P, RECON, true, NT, U, W4><<<nb, NT, lds, s>>>(
+            G, p, st.fat[p], st.naik[p], st.fat[1 - p], st.naik[1 - p], a.in, a.out, a.x, a.a,
+            a.dot_partials, a.gate, st.fat_scale, st.naik_scale, c0);
     else
-        dslash_kernel<P, RECON, false, NT, U><<<nb, NT, lds, s>>>(
-            G, a.out_parity, fat, naik, a.in, a.out, nullptr, 0.0, nullptr, a.gate,
-            st.fat_scale, st.naik_scale, c0);
+        dslash_kernel<P, RECON, false, NT, U, W4><<<nb, NT, lds, s>>>(
+            G, p, st.fat[p], st.naik[p], st.fat[1 - p], st.naik[1 - p], a.in, a.out, nullptr,
+            0.0, nullptr, a.gate, st.fat_scale, st.naik_scale, c0);
     KS_HIP(hipGetLastError());
+}
+
+template <int P, int RECON, int NT, int U>
+void launch_u(const LinkStore& st, const Geom& G, double c0, const DslashArgs& a,
+              const TuneEntry& t, hipStream_t s)
+{
+    if (t.way == 4) launch_w<P, RECON, NT, U, true>(st, G, c0, a, t.lds, s);
+    else launch_w<P, RECON, NT, U, false>(st, G, c0, a, t.lds, s);
 }
 
 template <int P, int RECON, int NT>
@@ -161,13 +197,13 @@ void launch_nt(const LinkStore& st, const Geom& G, double c0, const DslashArgs& 
                const TuneEntry& t, hipStream_t s)
 {
     if (t.group == 2) {
-        if constexpr (group_built(P, RECON, 2)) launch_u<P, RECON, NT, 2>(st, G, c0, a, t.lds, s);
+        if constexpr (group_built(P, RECON, 2)) launch_u<P, RECON, NT, 2>(st, G, c0, a, t, s);
         else KS_REQUIRE(false, KS_ERR_ARG, "Dslash: 2 links per pass not built for this storage");
     } else if (t.group == 4) {
-        if constexpr (group_built(P, RECON, 4)) launch_u<P, RECON, NT, 4>(st, G, c0, a, t.lds, s);
+        if constexpr (group_built(P, RECON, 4)) launch_u<P, RECON, NT, 4>(st, G, c0, a, t, s);
         else KS_REQUIRE(false, KS_ERR_ARG, "Dslash: 4 links per pass not built for this storage");
     } else {
-        launch_u<P, RECON, NT, 1>(st, G, c0, a, t.lds, s);
+        launch_u<P, RECON, NT, 1>(st, G, c0, a, t, s);
     }
 }
 
@@ -215,8 +251,8 @@ void dslash(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, const DslashArgs& a,
     launch(g, prec, ri, a, g->tune[prec][ri], s);
 }
 
-// Candidates: 1, 2 or 4 matrices loaded per pass (2 at most in FP64), 64, 128 or 256 threads
-// per block, each with the number of resident blocks per CU capped through the dynamic LDS
+// Candidates: 8-way or 4-way link access, 1, 2 or 4 matrices loaded per pass (2 at most in
+// FP64), 64, 128 or 256 threads per block, each with the number of resident blocks per CU capped through the dynamic LDS
 // request (how many waves share a SIMD also decides how
 // evenly the last round of waves fills the chip).  Each candidate is timed over a few
 // launches with HIP events on this lattice; the fastest is kept for the handle.
@@ -248,6 +284,7 @@ void dslash_tune(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, hipStream_t s)
         a.out_parity = 0;
         a.in = in;
         a.out = out;
+        for (int way : {8, 4}) {
         for (int group : {1, 2, 4}) {
         const int rc = ri ? 12 : 18;
         if (!group_built((int)prec, rc, group)) continue;
@@ -256,6 +293,7 @@ void dslash_tune(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, hipStream_t s)
                 TuneEntry t;
                 t.nt = nt;
                 t.group = group;
+                t.way = way;
                 if (blocks_cu > 0) {
                     long l = lds_cu / blocks_cu - 256;
                     l -= l % 256;
@@ -276,6 +314,7 @@ void dslash_tune(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, hipStream_t s)
                     best = t;
                 }
             }
+        }
         }
         }
     } catch (...) {

@@ -73,6 +73,7 @@ struct Workspace;   // solver buffers, solvers.hip
 struct TuneEntry {
     int nt = 256;
     int group = 1;      // link matrices loaded per pass of the Dslash site loop
+    int way = 8;        // 8: a site's own backward slots; 4: neighbours' forward slots
     int lds = 0;
     float us = 0.f;     // measured time per launch when tuned
     bool tuned = false;
