@@ -106,3 +106,61 @@ def full_solve(g, mass: float, b_e: np.ndarray, b_o: np.ndarray, tol: float):
     me, mo = apply_M(g, mass, x_e, x_o)
     res = np.sqrt(np.linalg.norm(b_e - me) ** 2 + np.linalg.norm(b_o - mo) ** 2)
     return x_e, x_o, FullInfo(info_iters, cg_tol, float(res / nb) if nb > 0 else 0.0)
+
+
+def _lattice_view(dims, full: np.ndarray) -> np.ndarray:
+    """[V][3] (site index x + Nx (y + Ny (z + Nz t))) viewed as [t][z][y][x][3]."""
+    nx, ny, nz, nt = dims
+    return full.reshape(nt, nz, ny, nx, 3)
+
+
+def _shift(dims, full: np.ndarray, mu: int, k: int) -> np.ndarray:
+    """psi(x + k mu) at every site x (periodic; boundary signs live in the links)."""
+    axis = 3 - mu      # x is the last lattice axis of the view
+    v = _lattice_view(dims, full)
+    return np.roll(v, -k, axis=axis).reshape(full.shape)
+
+
+def parity_sign(dims) -> np.ndarray:
+    """eps(x) = (-1)^(x+y+z+t) over the full lattice, [V]."""
+    nx, ny, nz, nt = dims
+    t, z, y, x = np.meshgrid(np.arange(nt), np.arange(nz), np.arange(ny), np.arange(nx),
+                             indexing="ij")
+    return (1 - 2 * ((x + y + z + t) % 2)).reshape(-1).astype(np.float64)
+
+
+def force_outer(g, residues, xs):
+    """Link derivative of S = sum_i r_i phi^+ A_i^-1 phi given the solutions X_i = A_i^-1 phi.
+
+    With Y_i = D_oe X_i and Psi_i = X_i on even sites, Y_i on odd sites, a variation of the
+    links changes S by  sum_{x,mu} 2 Re Tr[dV_mu(x) FV_mu(x) + dW_mu(x) FW_mu(x)],
+        FV_mu(x) = eps(x) sum_i r_i Psi_i(x+mu) Psi_i(x)^+,
+        FW_mu(x) = eps(x) sum_i r_i Psi_i(x+3mu) Psi_i(x)^+,
+    eps(x) = +1 on even and -1 on odd sites.  (dS_i = -X_i^+ dA_i X_i with
+    dA_i = -(dD_eo D_oe + D_eo dD_oe), D anti-Hermitian for any links, so
+    dS_i = X_i^+ dD_eo Y_i - Y_i^+ dD_oe X_i; each link enters D once forward and once as
+    minus its adjoint backward.)  Returns FV, FW as [4][V][3][3] complex128.
+    """
+    dims = g.dims
+    vol = int(np.prod(dims))
+    eps = parity_sign(dims)
+    fv = np.zeros((4, vol, 3, 3), dtype=np.complex128)
+    fw = np.zeros((4, vol, 3, 3), dtype=np.complex128)
+    for r, x in zip(residues, xs):
+        y = dslash_eo(g, 1, x)
+        psi = embed(dims, 0, x) + embed(dims, 1, y)
+        for mu in range(4):
+            p1 = _shift(dims, psi, mu, 1)
+            p3 = _shift(dims, psi, mu, 3)
+            fv[mu] += r * eps[:, None, None] * p1[:, :, None] * psi.conj()[:, None, :]
+            fw[mu] += r * eps[:, None, None] * p3[:, :, None] * psi.conj()[:, None, :]
+    return fv, fw
+
+
+def rational_action(g, residues, sigmas, phi, tol: float = 1e-13):
+    """S = sum_i r_i phi^+ (sigma_i - D_eo D_oe)^-1 phi by one CG solve per shift (real)."""
+    s = 0.0
+    for r, sg in zip(residues, sigmas):
+        x, _ = cg(g, sg, phi, tol)
+        s += r * float(np.vdot(phi, x).real)
+    return s
