@@ -196,6 +196,21 @@ ks_status_t ks_full_solve(ks_gauge_t g, double mass, const double* b_even, const
                           double* x_even, double* x_odd, const ks_solver_params* p,
                           ks_solver_stats* st, hipStream_t stream);
 
+/* Link derivative ("fermion force") of S = sum_i r_i phi^+ (sigma_i - D_eo D_oe)^-1 phi from
+ * the solutions X_i of ks_multishift_cg_solve: the next consumer of the multi-mass solver's
+ * output in molecular dynamics (the fermion force named as future work in Sec. 5).  With
+ * Y_i = D_oe X_i and Psi_i = X_i on even, Y_i on odd sites, a change of the links changes S by
+ * sum_{x,mu} 2 Re Tr[dV_mu(x) FV_mu(x) + dW_mu(x) FW_mu(x)], where
+ *     FV_mu(x) = eps(x) sum_i r_i Psi_i(x+mu) Psi_i(x)^+,
+ *     FW_mu(x) = eps(x) sum_i r_i Psi_i(x+3mu) Psi_i(x)^+,   eps = +1 even, -1 odd sites,
+ * with respect to the links as loaded (phases and boundary signs folded in); the chain rule
+ * through the construction of V and W from thin links is the caller's.  nterm in [1, 32];
+ * residues: host [nterm]; x_even: host array of nterm device complex128 [Vh][3] pointers;
+ * force_fat, force_naik: device complex128 [4][V][3][3] in the layout of ks_gauge_load.  FP64
+ * throughout.  Asynchronous on `stream`. */
+ks_status_t ks_force(ks_gauge_t g, int nterm, const double* residues, const double* const* x_even,
+                     double* force_fat, double* force_naik, hipStream_t stream);
+
 /* ------------------------------------------------------------------ batched solves */
 
 /* Many independent lattices (uneven sizes allowed), each with nrhs right-hand sides, solved

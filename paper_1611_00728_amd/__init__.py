@@ -99,6 +99,7 @@ def lib():
                                   C.POINTER(SolverStats), _vp]
         L.ks_full_solve.argtypes = [_vp, C.c_double, _vp, _vp, _vp, _vp, C.POINTER(SolverParams),
                                     C.POINTER(SolverStats), _vp]
+        L.ks_force.argtypes = [_vp, C.c_int, C.POINTER(C.c_double), C.POINTER(_vp), _vp, _vp, _vp]
         L.ks_multishift_cg_solve.argtypes = [_vp, C.c_int, C.POINTER(C.c_double), _vp,
                                              C.POINTER(_vp), C.POINTER(C.c_double),
                                              C.POINTER(SolverParams), C.POINTER(SolverStats), _vp]
@@ -297,6 +298,22 @@ def full_solve(gauge: Gauge, mass: float, b_even, b_odd, x_even, x_odd,
     if rc != 0 and raise_on_error:
         _check(rc)
     return SolveResult(rc, st.as_dict())
+
+
+def force(gauge: Gauge, residues, xs, force_fat, force_naik, stream=None):
+    """Link derivative of sum_i r_i phi^+ A_i^-1 phi from the solutions xs (ks_force);
+    force_fat, force_naik: complex128 CUDA tensors of 4 * V * 9 elements."""
+    n = len(residues)
+    if len(xs) != n:
+        raise ValueError("need one solution per residue")
+    outs = []
+    for f, name in ((force_fat, "force_fat"), (force_naik, "force_naik")):
+        outs.append(_dev_ptr(f, name))
+        if f.numel() != 36 * gauge.volume:
+            raise ValueError("%s must hold 4 * V * 9 complex numbers" % name)
+    r = (C.c_double * n)(*[float(v) for v in residues])
+    ptrs = (_vp * n)(*[_dev_vec(x, gauge.vh, "x[%d]" % i).value for i, x in enumerate(xs)])
+    _check(lib().ks_force(gauge.handle, n, r, ptrs, outs[0], outs[1], _stream(stream)))
 
 
 def multishift_cg_solve(gauge: Gauge, sigmas, b, xs, tols, params: SolverParams | None = None,

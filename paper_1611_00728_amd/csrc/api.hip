@@ -379,6 +379,24 @@ ks_status_t ks_full_solve(ks_gauge_t g, double mass, const double* b_even, const
     KS_API_END
 }
 
+ks_status_t ks_force(ks_gauge_t g, int nterm, const double* residues, const double* const* x_even,
+                     double* force_fat, double* force_naik, hipStream_t stream)
+{
+    KS_API_BEGIN
+    KS_REQUIRE(g && residues && x_even && force_fat && force_naik, KS_ERR_ARG,
+               "ks_force: null argument");
+    KS_REQUIRE(nterm >= 1 && nterm <= force_max_terms(), KS_ERR_ARG,
+               "ks_force: nterm must lie in [1, %d]", force_max_terms());
+    KS_REQUIRE(force_fat != force_naik, KS_ERR_ARG, "ks_force: the two outputs alias");
+    for (int i = 0; i < nterm; ++i) {
+        KS_REQUIRE(x_even[i], KS_ERR_ARG, "ks_force: null solution %d", i);
+        KS_REQUIRE(std::isfinite(residues[i]), KS_ERR_ARG, "ks_force: residue %d not finite", i);
+    }
+    force_core(g, nterm, residues, x_even, force_fat, force_naik, stream);
+    return KS_SUCCESS;
+    KS_API_END
+}
+
 ks_status_t ks_multishift_cg_solve(ks_gauge_t g, int nshift, const double* sigma,
                                    const double* b_dev, double* const* x_dev, const double* tol,
                                    const ks_solver_params* p, ks_solver_stats* st,

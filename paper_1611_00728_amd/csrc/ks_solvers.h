@@ -40,6 +40,8 @@ struct Workspace {
     // full-lattice solve, FP64 planes: even right-hand side of the Schur system, even and odd
     // temporaries, and the odd b and x of the boundary call
     double* full[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    // force: per term the even solution and its odd hopping image, FP64 planes
+    std::vector<double*> force_psi;
 };
 
 Workspace& workspace(ks_gauge_t g);
@@ -58,6 +60,10 @@ ks_status_t cg_core(ks_gauge_t g, double sigma, const double* b, double* x,
 ks_status_t full_solve_core(ks_gauge_t g, double mass, const double* b_e, const double* b_o,
                             double* x_e, double* x_o, const ks_solver_params& prm,
                             ks_solver_stats& stats, hipStream_t s);
+// link derivative of sum_i r_i phi^+ A_i^-1 phi from X_i = A_i^-1 phi (boundary layout)
+int force_max_terms();
+void force_core(ks_gauge_t g, int nterm, const double* residues, const double* const* x_even,
+                double* force_fat, double* force_naik, hipStream_t s);
 ks_status_t multishift_core(ks_gauge_t g, int nshift, const double* sigma, const double* b,
                             double* const* x, const double* tol, const ks_solver_params& prm,
                             ks_solver_stats* stats, hipStream_t s);

@@ -104,6 +104,7 @@ void workspace_free(Workspace* w)
     device_free(w->ms_t);
     device_free(w->ms_st);
     for (double* v : w->full) device_free(v);
+    for (double* v : w->force_psi) device_free(v);
     if (w->ms_st_host) (void)hipHostFree(w->ms_st_host);
     delete w;
 }
