@@ -11,17 +11,20 @@ and never imports it; the two meet only in the seeded inputs of `ksinputs`.
 * `solvers.py`: flexible CG with a preconditioner; M = 2m + D on the full lattice and its
   solve through the even-odd Schur complement with odd-site reconstruction; the link
   derivative (force) of the multi-shift pseudofermion action from the shifted solutions.
+* `hisq.py`: two-level smeared fat links (fat7, U(3) projection, fat7 + Lepage) and the
+  Naik link built from thin links.
 * `quant.py`: the quantise-then-FP64 references of the reduced-precision storage formats.
 """
 from .core import (lib, dslash_full, dslash_eo, apply_A, cg, multishift_cg, embed, restrict,
                    CGInfo, dense_A, lanczos_extremes, OracleError)
+from . import hisq
 from .quant import quantise_f32, quantise_f16_sites, quantise_f16_links, f16_link_exponent
 from .network import (Network, PATHS, transport, transport_adj, layer_forward,
                       network_forward, loss_and_grad, adam_step, neighbour_tables)
 from .solvers import (fcg, apply_M, full_solve, FullInfo, force_outer, rational_action,
                       parity_sign)
 
-__all__ = ["lib", "dslash_full", "dslash_eo", "apply_A", "cg", "multishift_cg", "embed",
+__all__ = ["hisq", "lib", "dslash_full", "dslash_eo", "apply_A", "cg", "multishift_cg", "embed",
            "restrict", "CGInfo", "dense_A", "lanczos_extremes", "OracleError", "quantise_f32",
            "quantise_f16_sites", "quantise_f16_links", "f16_link_exponent", "Network", "PATHS",
            "transport", "transport_adj", "layer_forward", "network_forward", "loss_and_grad",
