@@ -211,6 +211,24 @@ ks_status_t ks_full_solve(ks_gauge_t g, double mass, const double* b_even, const
 ks_status_t ks_force(ks_gauge_t g, int nterm, const double* residues, const double* const* x_even,
                      double* force_fat, double* force_naik, hipStream_t stream);
 
+/* Fat and Naik links from unsigned thin links U (SU(3), periodic): the link construction that
+ * precedes the solve in production (HISQ-type).  With staples of a field M on mu-links in a
+ * signed transverse direction a, S_a[M](x) = L_a(x) M(x+a) L_a(x+mu)^+ (L_a the thin link from
+ * x toward a), a smearing with coefficients c = (c1, c3, c5, c7, cL) is
+ *     F_mu = c1 U_mu + c3 sum S_a[U_mu] + c5 sum S_a S_b[U_mu] + c7 sum S_a S_b S_c[U_mu]
+ *            + cL sum S_a S_a[U_mu]   (a, b, c on distinct transverse axes).
+ * Output: V = F(U; level1), W = V (V^+ V)^-1/2 (U(3) projection, Newton polar iteration),
+ * fat = F(W; level2), naik_mu(x) = c_naik W_mu(x) W_mu(x+mu) W_mu(x+2mu), then the staggered
+ * phases eta_mu(x) and the antiperiodic time sign folded in as ks_gauge_load expects.
+ * level1 = NULL: (1/8, 1/16, 1/64, 1/384, 0); level2 = NULL: (1, 1/16, 1/64, 1/384, -1/8)
+ * (fat = 9/8 for unit links, so 9/8 - 3/24 = 1 normalises the free derivative); c_naik: -1/24
+ * for HISQ.  thin_dev, fat_dev, naik_dev: device complex128 [4][V][3][3] (layout of
+ * ks_gauge_load), distinct.  KS_ERR_NONFINITE when a level-1 link is singular.  Allocates
+ * about 12 link fields of scratch for the call; synchronises the stream. */
+ks_status_t ks_hisq_links(const int dims[4], const double* thin_dev, double* fat_dev,
+                          double* naik_dev, const double* level1, const double* level2,
+                          double c_naik, hipStream_t stream);
+
 /* ------------------------------------------------------------------ batched solves */
 
 /* Many independent lattices (uneven sizes allowed), each with nrhs right-hand sides, solved

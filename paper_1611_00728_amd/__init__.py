@@ -99,6 +99,8 @@ def lib():
                                   C.POINTER(SolverStats), _vp]
         L.ks_full_solve.argtypes = [_vp, C.c_double, _vp, _vp, _vp, _vp, C.POINTER(SolverParams),
                                     C.POINTER(SolverStats), _vp]
+        L.ks_hisq_links.argtypes = [C.POINTER(C.c_int), _vp, _vp, _vp, C.POINTER(C.c_double),
+                                    C.POINTER(C.c_double), C.c_double, _vp]
         L.ks_force.argtypes = [_vp, C.c_int, C.POINTER(C.c_double), C.POINTER(_vp), _vp, _vp, _vp]
         L.ks_multishift_cg_solve.argtypes = [_vp, C.c_int, C.POINTER(C.c_double), _vp,
                                              C.POINTER(_vp), C.POINTER(C.c_double),
@@ -298,6 +300,24 @@ def full_solve(gauge: Gauge, mass: float, b_even, b_odd, x_even, x_odd,
     if rc != 0 and raise_on_error:
         _check(rc)
     return SolveResult(rc, st.as_dict())
+
+
+def hisq_links(dims, thin, fat, naik, level1=None, level2=None, c_naik=-1.0 / 24.0,
+               stream=None):
+    """Fat and Naik links from thin links (ks_hisq_links); thin, fat, naik: complex128 CUDA
+    tensors of 4 * V * 9 elements; level1, level2: five smearing coefficients or None."""
+    dims = tuple(int(d) for d in dims)
+    vol = dims[0] * dims[1] * dims[2] * dims[3]
+    ptrs = []
+    for t, name in ((thin, "thin"), (fat, "fat"), (naik, "naik")):
+        ptrs.append(_dev_ptr(t, name))
+        if t.numel() != 36 * vol:
+            raise ValueError("%s must hold 4 * V * 9 complex numbers" % name)
+    d = (C.c_int * 4)(*dims)
+    l1 = None if level1 is None else (C.c_double * 5)(*[float(v) for v in level1])
+    l2 = None if level2 is None else (C.c_double * 5)(*[float(v) for v in level2])
+    _check(lib().ks_hisq_links(d, ptrs[0], ptrs[1], ptrs[2], l1, l2, float(c_naik),
+                               _stream(stream)))
 
 
 def force(gauge: Gauge, residues, xs, force_fat, force_naik, stream=None):

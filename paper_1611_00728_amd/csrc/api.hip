@@ -598,6 +598,33 @@ ks_status_t ks_fcg_solve(ks_gauge_t g, ks_net_t n, double mass, const double* b_
     KS_API_END
 }
 
+ks_status_t ks_hisq_links(const int dims[4], const double* thin_dev, double* fat_dev,
+                          double* naik_dev, const double* level1, const double* level2,
+                          double c_naik, hipStream_t stream)
+{
+    KS_API_BEGIN
+    KS_REQUIRE(dims && thin_dev && fat_dev && naik_dev, KS_ERR_ARG, "ks_hisq_links: null argument");
+    long v = 1;
+    for (int mu = 0; mu < 4; ++mu) {
+        KS_REQUIRE(dims[mu] >= 4 && dims[mu] % 2 == 0, KS_ERR_ARG,
+                   "ks_hisq_links: extent %d of direction %d must be even and >= 4", dims[mu], mu);
+        v *= dims[mu];
+    }
+    KS_REQUIRE(v <= (1L << 29), KS_ERR_ARG, "ks_hisq_links: volume %ld too large", v);
+    KS_REQUIRE(fat_dev != naik_dev && (const double*)fat_dev != thin_dev &&
+                   (const double*)naik_dev != thin_dev,
+               KS_ERR_ARG, "ks_hisq_links: outputs must not alias each other or the input");
+    KS_REQUIRE(std::isfinite(c_naik), KS_ERR_ARG, "ks_hisq_links: Naik coefficient not finite");
+    const double* l1 = level1 ? level1 : kHisqLevel1;
+    const double* l2 = level2 ? level2 : kHisqLevel2;
+    for (int k = 0; k < 5; ++k)
+        KS_REQUIRE(std::isfinite(l1[k]) && std::isfinite(l2[k]), KS_ERR_ARG,
+                   "ks_hisq_links: smearing coefficient %d not finite", k);
+    hisq_links(make_geom(dims), thin_dev, fat_dev, naik_dev, l1, l2, c_naik, stream);
+    return KS_SUCCESS;
+    KS_API_END
+}
+
 ks_status_t ks_stream_copy(void* dst_dev, const void* src_dev, size_t bytes, hipStream_t stream)
 {
     KS_API_BEGIN

@@ -225,6 +225,12 @@ void dslash(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, const DslashArgs& a,
 int dslash_blocks(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon);
 // upper bound of dslash_blocks over every launch configuration
 int dslash_max_blocks(const Geom& g);
+// fat and Naik links from thin links by two smearing levels with a U(3) projection between
+extern const double kHisqLevel1[5];
+extern const double kHisqLevel2[5];
+extern const double kHisqNaik;
+void hisq_links(const Geom& G, const double* thin, double* fat, double* naik,
+                const double* level1, const double* level2, double c_naik, hipStream_t st);
 // whether the kernel with this many link matrices per pass exists for the variant
 bool dslash_group_built(ks_prec_t prec, ks_recon_t recon, int links_per_pass);
 // times the candidate launch configurations on this lattice and keeps the fastest
