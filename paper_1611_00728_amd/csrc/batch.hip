@@ -211,8 +211,11 @@ __global__ __launch_bounds__(NT) void batch_update_kernel(const LatDesc* __restr
 #pragma unroll
             for (int k = 0; k < R; ++k) {
                 const BatchPair& pp = pairs[L.pair0 + k];
-                const bool on = !pp.done;
-                const double a = on ? pp.alpha : 0.0;
+                // a finished pair keeps x and r as they are: its direction p is no longer
+                // maintained (never written for a pair that starts finished), so it must not
+                // enter even with a zero step
+                if (pp.done) continue;
+                const double a = pp.alpha;
                 const T af = (T)a;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
@@ -737,6 +740,11 @@ BatchCtx* batch_create(int nlat, const int* dims, const double* const* fat,
         c->r64 = static_cast<char*>(device_alloc(nrec * 16));
         c->t64 = static_cast<char*>(device_alloc(nrec * 16));
         c->ax64 = static_cast<char*>(device_alloc(nrec * 16));
+        // finished pairs leave their slots of p, q, t untouched: start every arena finite
+        for (char* a : {c->ps, c->qs, c->ts, c->rs})
+            KS_HIP(hipMemsetAsync(a, 0, nrec * cs, s));
+        for (char* a : {c->x64, c->b64, c->r64, c->t64, c->ax64})
+            KS_HIP(hipMemsetAsync(a, 0, nrec * 16, s));
         KS_HIP(hipStreamSynchronize(s));
     } catch (...) {
         batch_free(c);
