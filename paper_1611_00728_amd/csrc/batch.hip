@@ -382,6 +382,7 @@ __global__ __launch_bounds__(kFin) void batch_alpha_kernel(const LatDesc* __rest
     q.alpha = q.rho / pap;
 }
 
+// |r|^2 of the step and the pair's own decision; rho and beta are set by batch_sync_kernel
 __global__ __launch_bounds__(kFin) void batch_beta_kernel(const LatDesc* __restrict__ lats, int R,
                                                           BatchPair* __restrict__ pairs,
                                                           const double* __restrict__ part)
@@ -393,20 +394,40 @@ __global__ __launch_bounds__(kFin) void batch_beta_kernel(const LatDesc* __restr
     const double rn = pair_sum(L, part, R, pi % R);
     if (threadIdx.x != 0) return;
     q.iter += 1;
+    q.rn = rn;
     if (!isfinite(rn)) {
         q.status = KS_ERR_NONFINITE;
         q.done = 1;
         q.t_done = wall_clock64();
         return;
     }
-    const double s = sqrt(rn);
-    if (rn <= q.stop2 || s < q.delta * q.maxr || q.iter >= q.max_iter) {
-        q.ru_now = 1;
-        return;
+    if (rn <= q.stop2 || q.iter >= q.max_iter) q.ru_now = 1;
+    else if (sqrt(rn) < q.delta * q.maxr) q.ru_now = 2;
+}
+
+// One thread per lattice.  A reliable update costs a lattice one FP64 multi-RHS A-apply
+// whatever the number of its pairs that take part, so when one pair's residual has fallen by
+// delta every unfinished pair of the lattice takes the update with it (the right-hand sides
+// then stay in step instead of each paying its own).  Pairs without an update continue:
+// beta = |r|^2 / rho, rho = |r|^2.
+__global__ void batch_sync_kernel(int nlat, int R, BatchPair* __restrict__ pairs)
+{
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= nlat) return;
+    bool drop = false;
+    for (int r = 0; r < R; ++r) {
+        const BatchPair& q = pairs[l * R + r];
+        drop = drop || (!q.done && q.ru_now == 2);
     }
-    q.beta = rn / q.rho;
-    q.rho = rn;
-    q.maxr = fmax(q.maxr, s);
+    for (int r = 0; r < R; ++r) {
+        BatchPair& q = pairs[l * R + r];
+        if (q.done) continue;
+        if (drop && q.ru_now == 0) q.ru_now = 1;
+        if (q.ru_now) continue;
+        q.beta = q.rn / q.rho;
+        q.rho = q.rn;
+        q.maxr = fmax(q.maxr, sqrt(q.rn));
+    }
 }
 
 __global__ __launch_bounds__(kFin) void batch_reliable_kernel(const LatDesc* __restrict__ lats, int R,
@@ -547,6 +568,8 @@ struct BatchLaunch {
         else
             batch_update_kernel<KS_F32, R, NT><<<grid, NT, 0, s>>>(c.lats_dev, tl, nt, c.x64, c.ps, c.qs, c.rs, c.pairs, c.partials);
         batch_beta_kernel<<<np, kFin, 0, s>>>(c.lats_dev, R, c.pairs, c.partials);
+        const int nlat = (int)c.lats_host.size();
+        batch_sync_kernel<<<blocks_for(nlat, 64), 64, 0, s>>>(nlat, R, c.pairs);
         reliable(c, 0, s);
         if (P == KS_F64)
             batch_xpay_kernel<KS_F64, R, NT><<<grid, NT, 0, s>>>(c.lats_dev, tl, nt, c.rs, c.ps, c.pairs, 0);

@@ -23,8 +23,10 @@ struct LatDesc {
 // CG scalars of one (lattice, RHS) pair.
 struct BatchPair {
     double rho, alpha, beta, maxr, stop2, delta, true_r2;
+    double rn;                   // |r|^2 of the step, applied to rho once the step's updates are known
     unsigned long long t_done;   // device wall clock at convergence
-    int iter, max_iter, ru, done, status, ru_now;
+    int iter, max_iter, ru, done, status;
+    int ru_now;                  // 0: none; 1: update due (target met, step cap, or forced); 2: |r| fell by delta
 };
 
 struct BatchCtx {
