@@ -70,9 +70,10 @@ TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "dslash_32x32x32x32_hbm_traffic
 KERNEL_SOURCES = ["dslash.hip", "ks_device.h", "ks_common.h"]
 
 
-def measured_traffic(variant: str, threads: int, group: int, way: int):
+def measured_traffic(variant: str, threads: int, group: int, way: int, staged: int):
     """HBM bytes per launch of one kernel instantiation (variant, threads per block, links per
-    pass, link access) from the committed counter summary, or None once the kernel sources differ from the
+    pass, link access, staged gathers) from the committed counter summary, or None once the
+    kernel sources differ from the
     ones the counters were taken on."""
     import hashlib
     if not os.path.exists(TRAFFIC_SUMMARY):
@@ -84,13 +85,14 @@ def measured_traffic(variant: str, threads: int, group: int, way: int):
     values, recorded = {}, None
     for line in open(TRAFFIC_SUMMARY):
         parts = line.split()
-        if len(parts) == 6 and parts[0] == "traffic_bytes_per_launch":
-            values[(parts[1], int(parts[2]), int(parts[3]), int(parts[4]))] = float(parts[5])
+        if len(parts) == 7 and parts[0] == "traffic_bytes_per_launch":
+            values[(parts[1], int(parts[2]), int(parts[3]), int(parts[4]), int(parts[5]))] = \
+                float(parts[6])
         elif len(parts) == 2 and parts[0] == "source_hash":
             recorded = parts[1]
     if recorded != h.hexdigest()[:16]:
         return None
-    return values.get((variant, threads, group, way))
+    return values.get((variant, threads, group, way, staged))
 
 
 def cpu_baseline(g, b, budget_s: float = 12.0):
@@ -259,8 +261,9 @@ def main():
         stream.synchronize()
         return e0.elapsed_time(e1) * 1e3 / reps
 
-    # 8-way vs 4-way link access (the storage question Sec. 3 leaves open): the best launch
-    # shape of each access mode per variant; the tuned configuration is restored afterwards
+    # 8-way vs 4-way link access (the storage question Sec. 3 leaves open), and neighbour
+    # gathers through the caches vs staged in LDS: the best launch shape of each combination
+    # per variant; the tuned configuration is restored afterwards
     link_study = {}
     if not args.dslash_only:
         for v in variants:
@@ -268,23 +271,25 @@ def main():
             cfg = tuned[key]
             row = {}
             for way in (8, 4):
-                best = None
-                for group in (1, 2, 4):
-                    for nt in (64, 128, 256):
-                        for lds in (0, 13312, 20224, 32512, 54272):
-                            try:
-                                G.set_config(pmap[v[0]], v[1], nt, lds, group, way)
-                            except ks.KSError:
-                                continue        # a form that is not built
-                            us = time_variant(v, reps=5)
-                            if best is None or us < best[0]:
-                                best = (us, nt, lds, group)
-                G.set_config(pmap[v[0]], v[1], best[1], best[2], best[3], way)
-                row["%d-way_us" % way] = time_variant(v)
-                row["%d-way_shape" % way] = {"threads": best[1], "lds_bytes": best[2],
-                                             "links_per_pass": best[3]}
+                for staged in (0, 1):
+                    best = None
+                    for group in (1, 2, 4):
+                        for nt in (64, 128, 256):
+                            for lds in (0, 13312, 20224, 32512, 54272):
+                                try:
+                                    G.set_config(pmap[v[0]], v[1], nt, lds, group, way, staged)
+                                except ks.KSError:
+                                    continue        # a form that is not built
+                                us = time_variant(v, reps=5)
+                                if best is None or us < best[0]:
+                                    best = (us, nt, lds, group)
+                    G.set_config(pmap[v[0]], v[1], best[1], best[2], best[3], way, staged)
+                    name = "%d-way_%s" % (way, "staged" if staged else "cached")
+                    row[name + "_us"] = time_variant(v)
+                    row[name + "_shape"] = {"threads": best[1], "lds_bytes": best[2],
+                                            "links_per_pass": best[3]}
             G.set_config(pmap[v[0]], v[1], cfg["threads"], cfg["lds_bytes"], cfg["links_per_pass"],
-                         cfg["link_access"])
+                         cfg["link_access"], cfg["staged"])
             link_study[key] = row
         log("link access study: %s" % json.dumps(link_study))
 
@@ -637,10 +642,12 @@ def main():
                      "unit": "GB/s", "frac": head["model_GBps"] / HBM_PEAK_GBS,
                      "traffic": measured_traffic("f64_r18", tuned["f64_r18"]["threads"],
                                                  tuned["f64_r18"]["links_per_pass"],
-                                                 tuned["f64_r18"]["link_access"]),
-                     "kernel": "dslash_kernel<F64,18,false,%d,%d,%s>" % (
+                                                 tuned["f64_r18"]["link_access"],
+                                                 tuned["f64_r18"]["staged"]),
+                     "kernel": "dslash_kernel<F64,18,false,%d,%d,%s,%s>" % (
                          tuned["f64_r18"]["threads"], tuned["f64_r18"]["links_per_pass"],
-                         "4-way" if tuned["f64_r18"]["link_access"] == 4 else "8-way"),
+                         "4-way" if tuned["f64_r18"]["link_access"] == 4 else "8-way",
+                         "staged" if tuned["f64_r18"]["staged"] else "cached"),
                      "bytes_per_launch": model_bytes_per_site("f64", 18) * vh,
                      "copy_GBps": copy_gbps, "frac_of_copy": head["model_GBps"] / copy_gbps,
                      "torch_elementwise_GBps": torch_gbps},

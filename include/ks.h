@@ -139,22 +139,40 @@ ks_status_t ks_dslash_eo(ks_gauge_t g, ks_field_t out, ks_field_t in, ks_recon_t
  * called while the stream is being captured into a graph. */
 ks_status_t ks_tune_dslash(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, hipStream_t stream);
 
-/* The launch configuration in use for a variant: threads per block, LDS bytes per block, link
- * matrices loaded per pass of the per-site loop (1, 2 or 4), link access (8: every site reads
- * its own 16 stored matrices, the 8-way storage of Sec. 3; 4: the backward matrices are formed
- * from the forward links of the neighbour sites, so only the forward half of the storage is
- * read, the 4-way alternative that Sec. 3 leaves untested) and the tuned time per launch in
- * microseconds (0 if never tuned).  Any output may be NULL. */
-ks_status_t ks_dslash_config(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, int* threads,
-                             int* lds_bytes, int* links_per_pass, int* link_access,
-                             float* tuned_us);
+/* Launch configuration of one Dslash variant:
+ *   threads         64, 128 or 256 threads per block (one output site per thread);
+ *   lds_bytes       dynamic LDS requested per block (0 to the device's LDS per workgroup);
+ *                   it caps how many blocks share a CU, and the staged form uses at least
+ *                   what its staging needs;
+ *   links_per_pass  1, 2 or 4 link matrices loaded per pass of the per-site loop (4 only for
+ *                   FP32 and FP16 with 18-real Naik; FP64 takes 2 only with 18-real Naik,
+ *                   8-way access and unstaged gathers);
+ *   link_access     8: every site reads its own 16 stored matrices, the 8-way storage of
+ *                   Sec. 3; 4: the backward matrices are formed from the forward links of the
+ *                   neighbour sites, so only the forward half of the storage is read (the
+ *                   4-way alternative Sec. 3 leaves untested);
+ *   staged          0: neighbour vectors read through the caches; 1: the vectors of the
+ *                   block's x and y neighbourhood are first staged in LDS by one coalesced read
+ *                   and those gathers read LDS;
+ *   tuned_us        time per launch measured by the autotuner (0 if never tuned; ignored by
+ *                   ks_dslash_set_config). */
+typedef struct {
+    int threads;
+    int lds_bytes;
+    int links_per_pass;
+    int link_access;
+    int staged;
+    float tuned_us;
+} ks_dslash_launch;
 
-/* Sets a variant's launch configuration by hand (replacing the tuned one): threads 64, 128 or
- * 256; lds_bytes 0 to the device's LDS per workgroup (the dynamic LDS requested per block,
- * which caps how many blocks share a CU); links_per_pass 1 or 2 (4 also for FP32 and FP16 with 18-real Naik; FP64 with
- * 12-real Naik takes 1 only); link_access 8 or 4.  KS_ERR_ARG for any other value. */
-ks_status_t ks_dslash_set_config(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, int threads,
-                                 int lds_bytes, int links_per_pass, int link_access);
+/* The configuration in use for a variant. */
+ks_status_t ks_dslash_config(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon,
+                             ks_dslash_launch* out);
+
+/* Sets a variant's configuration by hand, replacing the tuned one; KS_ERR_ARG for a value
+ * outside the ranges above. */
+ks_status_t ks_dslash_set_config(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon,
+                                 const ks_dslash_launch* cfg);
 
 /* out_dev = (sigma - D_eo D_oe) in_dev in FP64 on even sites, complex128 [Vh][3] device
  * arrays (in_dev != out_dev).  Asynchronous. */

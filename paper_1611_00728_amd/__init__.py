@@ -44,6 +44,14 @@ class SolverStats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class DslashLaunch(C.Structure):
+    _fields_ = [("threads", C.c_int), ("lds_bytes", C.c_int), ("links_per_pass", C.c_int),
+                ("link_access", C.c_int), ("staged", C.c_int), ("tuned_us", C.c_float)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class BatchStats(C.Structure):
     _fields_ = [("iters", C.c_int), ("reliable_updates", C.c_int), ("status", C.c_int),
                 ("true_rel_resid", C.c_double), ("seconds", C.c_double)]
@@ -89,12 +97,9 @@ def lib():
                                       C.POINTER(C.c_float), C.POINTER(C.c_double)]
         L.ks_batch_free.argtypes = [_vp]
         L.ks_tune_dslash.argtypes = [_vp, C.c_int, C.c_int, _vp]
-        L.ks_dslash_config.argtypes = [_vp, C.c_int, C.c_int, C.POINTER(C.c_int),
-                                       C.POINTER(C.c_int), C.POINTER(C.c_int),
-                                       C.POINTER(C.c_int), C.POINTER(C.c_float)]
+        L.ks_dslash_config.argtypes = [_vp, C.c_int, C.c_int, C.POINTER(DslashLaunch)]
         L.ks_stream_copy.argtypes = [_vp, _vp, C.c_size_t, _vp]
-        L.ks_dslash_set_config.argtypes = [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
-                                           C.c_int]
+        L.ks_dslash_set_config.argtypes = [_vp, C.c_int, C.c_int, C.POINTER(DslashLaunch)]
         L.ks_cg_solve.argtypes = [_vp, C.c_double, _vp, _vp, C.POINTER(SolverParams),
                                   C.POINTER(SolverStats), _vp]
         L.ks_full_solve.argtypes = [_vp, C.c_double, _vp, _vp, _vp, _vp, C.POINTER(SolverParams),
@@ -183,17 +188,15 @@ class Gauge:
         return self.config(prec, recon)
 
     def config(self, prec=F64, recon=RECON_18) -> dict:
-        nt, lds, grp, way, us = C.c_int(), C.c_int(), C.c_int(), C.c_int(), C.c_float()
-        _check(lib().ks_dslash_config(self.handle, prec, recon, C.byref(nt), C.byref(lds),
-                                      C.byref(grp), C.byref(way), C.byref(us)))
-        return {"threads": nt.value, "lds_bytes": lds.value, "links_per_pass": grp.value,
-                "link_access": way.value, "tuned_us": us.value}
+        cfg = DslashLaunch()
+        _check(lib().ks_dslash_config(self.handle, prec, recon, C.byref(cfg)))
+        return cfg.as_dict()
 
     def set_config(self, prec=F64, recon=RECON_18, threads=256, lds_bytes=0,
-                   links_per_pass=1, link_access=8):
+                   links_per_pass=1, link_access=8, staged=0):
         """Sets one variant's Dslash launch configuration by hand."""
-        _check(lib().ks_dslash_set_config(self.handle, prec, recon, threads, lds_bytes,
-                                          links_per_pass, link_access))
+        cfg = DslashLaunch(threads, lds_bytes, links_per_pass, link_access, staged, 0.0)
+        _check(lib().ks_dslash_set_config(self.handle, prec, recon, C.byref(cfg)))
 
     def device_bytes(self) -> int:
         return int(lib().ks_gauge_device_bytes(self.handle))

@@ -255,47 +255,51 @@ ks_status_t ks_tune_dslash(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, hipSt
     KS_API_END
 }
 
-ks_status_t ks_dslash_config(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, int* threads,
-                             int* lds_bytes, int* links_per_pass, int* link_access,
-                             float* tuned_us)
+ks_status_t ks_dslash_config(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon,
+                             ks_dslash_launch* out)
 {
     KS_API_BEGIN
-    KS_REQUIRE(g, KS_ERR_ARG, "ks_dslash_config: null handle");
+    KS_REQUIRE(g && out, KS_ERR_ARG, "ks_dslash_config: null argument");
     KS_REQUIRE(prec_ok(prec) && recon_ok(recon), KS_ERR_ARG, "ks_dslash_config: bad precision/recon");
     const TuneEntry& t = g->tune[prec][recon_index(recon)];
-    if (threads) *threads = t.nt;
-    if (lds_bytes) *lds_bytes = t.lds;
-    if (links_per_pass) *links_per_pass = t.group;
-    if (link_access) *link_access = t.way;
-    if (tuned_us) *tuned_us = t.tuned ? t.us : 0.f;
+    out->threads = t.nt;
+    out->lds_bytes = t.lds;
+    out->links_per_pass = t.group;
+    out->link_access = t.way;
+    out->staged = t.staged;
+    out->tuned_us = t.tuned ? t.us : 0.f;
     return KS_SUCCESS;
     KS_API_END
 }
 
-ks_status_t ks_dslash_set_config(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, int threads,
-                                 int lds_bytes, int links_per_pass, int link_access)
+ks_status_t ks_dslash_set_config(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon,
+                                 const ks_dslash_launch* cfg)
 {
     KS_API_BEGIN
-    KS_REQUIRE(g, KS_ERR_ARG, "ks_dslash_set_config: null handle");
+    KS_REQUIRE(g && cfg, KS_ERR_ARG, "ks_dslash_set_config: null argument");
     KS_REQUIRE(prec_ok(prec) && recon_ok(recon), KS_ERR_ARG,
                "ks_dslash_set_config: bad precision/recon");
-    KS_REQUIRE(threads == 64 || threads == 128 || threads == 256, KS_ERR_ARG,
+    KS_REQUIRE(cfg->threads == 64 || cfg->threads == 128 || cfg->threads == 256, KS_ERR_ARG,
                "ks_dslash_set_config: threads must be 64, 128 or 256");
     int dev = 0, lds_max = 0;
     KS_HIP(hipGetDevice(&dev));
     KS_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    KS_REQUIRE(lds_bytes >= 0 && lds_bytes <= lds_max, KS_ERR_ARG,
+    KS_REQUIRE(cfg->lds_bytes >= 0 && cfg->lds_bytes <= lds_max, KS_ERR_ARG,
                "ks_dslash_set_config: lds_bytes must lie in [0, %d]", lds_max);
-    KS_REQUIRE(dslash_group_built(prec, recon, links_per_pass), KS_ERR_ARG,
-               "ks_dslash_set_config: %d links per pass is not built for this variant",
-               links_per_pass);
-    KS_REQUIRE(link_access == 8 || link_access == 4, KS_ERR_ARG,
+    KS_REQUIRE(cfg->link_access == 8 || cfg->link_access == 4, KS_ERR_ARG,
                "ks_dslash_set_config: link_access must be 8 or 4");
+    KS_REQUIRE(cfg->staged == 0 || cfg->staged == 1, KS_ERR_ARG,
+               "ks_dslash_set_config: staged must be 0 or 1");
+    KS_REQUIRE(dslash_form_built(prec, recon, cfg->links_per_pass, cfg->link_access, cfg->staged),
+               KS_ERR_ARG, "ks_dslash_set_config: %d links per pass with %d-way access%s is "
+               "not built for this variant", cfg->links_per_pass, cfg->link_access,
+               cfg->staged ? " and staged gathers" : "");
     TuneEntry t;
-    t.nt = threads;
-    t.lds = lds_bytes;
-    t.group = links_per_pass;
-    t.way = link_access;
+    t.nt = cfg->threads;
+    t.lds = cfg->lds_bytes;
+    t.group = cfg->links_per_pass;
+    t.way = cfg->link_access;
+    t.staged = cfg->staged;
     g->tune[prec][recon_index(recon)] = t;
     return KS_SUCCESS;
     KS_API_END

@@ -7,6 +7,8 @@
 // stream from packed site-major planes (16-byte coalesced loads, read once: the bulk of the
 // bytes); the 16 neighbour vectors are gathers that the XCD-aware tile order keeps inside
 // one XCD's L2 for most hops.
+#include <algorithm>
+
 #include "ks_device.h"
 #include "ks_naik.h"
 
@@ -54,11 +56,48 @@ __device__ __forceinline__ void reconstruct_row2(cx<R> m[9])
     m[8] = {t.r, -t.i};
 }
 
+// Bytes of one colour vector of precision P and the LDS halo (in checkerboard sites) around a
+// block's sites that covers every x and y neighbour: x hops move the checkerboard index by at
+// most 2, y hops by 1 or 3 rows of Nx/2 (hops that wrap around the lattice fall outside and
+// are read from memory).
+__host__ __device__ constexpr int spinor_bytes_of(int P) { return P == KS_F64 ? 48 : P == KS_F32 ? 24 : 16; }
+__host__ __device__ inline int staged_halo(int nx) { return 3 * (nx / 2) + 2; }
+
+// Copies sites [lo, lo + len) of a colour-vector field into LDS with the field's own plane
+// structure (plane length len), so that Spinor<P>::load(lds, len, h - lo, v) reads site h.
+template <int P, int NT>
+__device__ __forceinline__ void stage_spinor(const void* __restrict__ in, int vh, int lo, int len,
+                                             void* lds)
+{
+    if constexpr (P == KS_F64) {
+        const double2* src = static_cast<const double2*>(in);
+        double2* dst = static_cast<double2*>(lds);
+        for (int k = 0; k < 3; ++k)
+            for (int j = threadIdx.x; j < len; j += NT) dst[k * len + j] = src[(size_t)k * vh + lo + j];
+    } else if constexpr (P == KS_F32) {
+        const float4* a = static_cast<const float4*>(in);
+        const float2* b = reinterpret_cast<const float2*>(a + vh);
+        float4* da = static_cast<float4*>(lds);
+        float2* db = reinterpret_cast<float2*>(da + len);
+        for (int j = threadIdx.x; j < len; j += NT) {
+            da[j] = a[lo + j];
+            db[j] = b[lo + j];
+        }
+    } else {
+        const uint4* src = static_cast<const uint4*>(in);
+        uint4* dst = static_cast<uint4*>(lds);
+        for (int j = threadIdx.x; j < len; j += NT) dst[j] = src[lo + j];
+    }
+}
+
 // W4: 4-way link access.  The backward matrices -V_mu(x-mu)^+ and -W_mu(x-3mu)^+ are formed
 // from the forward links of the neighbour sites (slots 0-3 of the other parity's store, read
 // at the neighbour's index) instead of the site's own backward slots 4-7, so only the forward
 // half of each store is read.
-template <int P, int RECON, bool XPAY, int NT, int U, bool W4>
+// LG: the input sites of the block's x and y neighbourhood are first staged in LDS (one
+// coalesced read of the range) and those gathers read LDS; z and t gathers, and wrapped
+// hops, read memory through the caches.
+template <int P, int RECON, bool XPAY, int NT, int U, bool W4, bool LG>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void dslash_kernel(Geom g, int par, const void* __restrict__ fat,
                                                         const void* __restrict__ naik,
                                                         const void* __restrict__ fat_o,
@@ -77,6 +116,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void ds
     const int h = tile * NT + threadIdx.x;
     const int vh = g.Vh;
     double dot = 0.0;
+    extern __shared__ __align__(16) char staged[];
+    int lo = 0, len = 0;
+    if constexpr (LG) {
+        const int halo = staged_halo(g.n[0]);
+        lo = max(0, tile * NT - halo);
+        len = min(vh, tile * NT + NT + halo) - lo;
+        stage_spinor<P, NT>(in, vh, lo, len, staged);
+        __syncthreads();
+    }
     if (h < vh) {
         int c[4];
         cb_coords(g, h, par, c);
@@ -108,7 +156,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void ds
                     else if (RECON == 12) load_link<P, 6>(naik, s - 8, vh, h, m[u]);
                     else load_link<P, 9>(naik, s - 8, vh, h, m[u]);
                 }
-                Spinor<P>::load(in, vh, nb[s], v[u]);
+                const int j = nb[s] - lo;
+                if (LG && (s & 3) < 2 && j >= 0 && j < len) Spinor<P>::load(staged, len, j, v[u]);
+                else Spinor<P>::load(in, vh, nb[s], v[u]);
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -159,52 +209,65 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void ds
     }
 }
 
-// Link matrices per pass that are built for a precision and Naik storage: more would exceed
-// the 128-VGPR budget of 4 waves per SIMD and spill.
-constexpr bool group_built(int P, int RECON, int U)
+// dynamic LDS of the staged form: the block's sites and the x/y halo on both sides
+int staged_lds_bytes(int P, int NT, const Geom& G)
 {
-    return U == 1 || (U == 2 && !(P == KS_F64 && RECON == 12)) ||
+    const int halo = staged_halo(G.n[0]);
+    const int sites = std::min(G.Vh, NT + 2 * halo);
+    return ((sites * spinor_bytes_of(P) + 255) / 256) * 256;
+}
+
+// Forms that are built: more link matrices per pass would exceed the 128-VGPR budget of 4
+// waves per SIMD and spill (FP64 holds two passes' matrices only with its own backward slots
+// and cache-read neighbours).
+constexpr bool form_built(int P, int RECON, int U, bool W4, bool LG)
+{
+    return U == 1 || (U == 2 && P != KS_F64) || (U == 2 && RECON == 18 && !W4 && !LG) ||
            (U == 4 && P != KS_F64 && RECON == 18);
 }
 
-template <int P, int RECON, int NT, int U, bool W4>
-void launch_w(const LinkStore& st, const Geom& G, double c0, const DslashArgs& a, int lds,
+template <int P, int RECON, int NT, int U, bool W4, bool LG>
+void launch_g(const LinkStore& st, const Geom& G, double c0, const DslashArgs& a, int lds,
               hipStream_t s)
 {
+    if constexpr (!form_built(P, RECON, U, W4, LG)) {
+        KS_REQUIRE(false, KS_ERR_ARG, "Dslash: this launch form is not built");
+    } else {
     const int nb = blocks_for(G.Vh, NT);
     const int p = a.out_parity;
+    if (LG) lds = std::max(lds, staged_lds_bytes(P, NT, G));
     if (a.x)
-        dslash_kernel<P, RECON, true, NT, U, W4><<<nb, NT, lds, s>>>(
+        dslash_kernel<P, RECON, true, NT, U, W4, LG><<<nb, NT, lds, s>>>(
             G, p, st.fat[p], st.naik[p], st.fat[1 - p], st.naik[1 - p], a.in, a.out, a.x, a.a,
             a.dot_partials, a.gate, st.fat_scale, st.naik_scale, c0);
     else
-        dslash_kernel<P, RECON, false, NT, U, W4><<<nb, NT, lds, s>>>(
+        dslash_kernel<P, RECON, false, NT, U, W4, LG><<<nb, NT, lds, s>>>(
             G, p, st.fat[p], st.naik[p], st.fat[1 - p], st.naik[1 - p], a.in, a.out, nullptr,
             0.0, nullptr, a.gate, st.fat_scale, st.naik_scale, c0);
     KS_HIP(hipGetLastError());
+    }
 }
 
 template <int P, int RECON, int NT, int U>
 void launch_u(const LinkStore& st, const Geom& G, double c0, const DslashArgs& a,
               const TuneEntry& t, hipStream_t s)
 {
-    if (t.way == 4) launch_w<P, RECON, NT, U, true>(st, G, c0, a, t.lds, s);
-    else launch_w<P, RECON, NT, U, false>(st, G, c0, a, t.lds, s);
+    if (t.way == 4) {
+        if (t.staged) launch_g<P, RECON, NT, U, true, true>(st, G, c0, a, t.lds, s);
+        else launch_g<P, RECON, NT, U, true, false>(st, G, c0, a, t.lds, s);
+    } else {
+        if (t.staged) launch_g<P, RECON, NT, U, false, true>(st, G, c0, a, t.lds, s);
+        else launch_g<P, RECON, NT, U, false, false>(st, G, c0, a, t.lds, s);
+    }
 }
 
 template <int P, int RECON, int NT>
 void launch_nt(const LinkStore& st, const Geom& G, double c0, const DslashArgs& a,
                const TuneEntry& t, hipStream_t s)
 {
-    if (t.group == 2) {
-        if constexpr (group_built(P, RECON, 2)) launch_u<P, RECON, NT, 2>(st, G, c0, a, t, s);
-        else KS_REQUIRE(false, KS_ERR_ARG, "Dslash: 2 links per pass not built for this storage");
-    } else if (t.group == 4) {
-        if constexpr (group_built(P, RECON, 4)) launch_u<P, RECON, NT, 4>(st, G, c0, a, t, s);
-        else KS_REQUIRE(false, KS_ERR_ARG, "Dslash: 4 links per pass not built for this storage");
-    } else {
-        launch_u<P, RECON, NT, 1>(st, G, c0, a, t, s);
-    }
+    if (t.group == 2) launch_u<P, RECON, NT, 2>(st, G, c0, a, t, s);
+    else if (t.group == 4) launch_u<P, RECON, NT, 4>(st, G, c0, a, t, s);
+    else launch_u<P, RECON, NT, 1>(st, G, c0, a, t, s);
 }
 
 template <int P, int RECON>
@@ -237,9 +300,11 @@ int dslash_blocks(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon)
     return blocks_for(g->geom.Vh, g->tune[prec][recon_index(recon)].nt);
 }
 
-bool dslash_group_built(ks_prec_t prec, ks_recon_t recon, int links_per_pass)
+bool dslash_form_built(ks_prec_t prec, ks_recon_t recon, int links_per_pass, int link_access,
+                       int staged)
 {
-    return links_per_pass > 0 && group_built((int)prec, (int)recon, links_per_pass);
+    return (links_per_pass == 1 || links_per_pass == 2 || links_per_pass == 4) &&
+           form_built((int)prec, (int)recon, links_per_pass, link_access == 4, staged != 0);
 }
 
 int dslash_max_blocks(const Geom& g) { return blocks_for(g.Vh, 64); }
@@ -251,7 +316,8 @@ void dslash(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, const DslashArgs& a,
     launch(g, prec, ri, a, g->tune[prec][ri], s);
 }
 
-// Candidates: 8-way or 4-way link access, 1, 2 or 4 matrices loaded per pass (2 at most in
+// Candidates: neighbours through the caches or x/y neighbours staged in LDS, 8-way or 4-way
+// link access, 1, 2 or 4 matrices loaded per pass (2 at most in
 // FP64), 64, 128 or 256 threads per block, each with the number of resident blocks per CU capped through the dynamic LDS
 // request (how many waves share a SIMD also decides how
 // evenly the last round of waves fills the chip).  Each candidate is timed over a few
@@ -284,16 +350,18 @@ void dslash_tune(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, hipStream_t s)
         a.out_parity = 0;
         a.in = in;
         a.out = out;
+        for (int staged : {0, 1}) {
         for (int way : {8, 4}) {
         for (int group : {1, 2, 4}) {
         const int rc = ri ? 12 : 18;
-        if (!group_built((int)prec, rc, group)) continue;
+        if (!form_built((int)prec, rc, group, way == 4, staged != 0)) continue;
         for (int nt : {64, 128, 256}) {
             for (int blocks_cu : {0, 2, 3, 4, 5, 6, 8, 10, 12, 16, 20, 24, 32}) {
                 TuneEntry t;
                 t.nt = nt;
                 t.group = group;
                 t.way = way;
+                t.staged = staged;
                 if (blocks_cu > 0) {
                     long l = lds_cu / blocks_cu - 256;
                     l -= l % 256;
@@ -314,6 +382,7 @@ void dslash_tune(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, hipStream_t s)
                     best = t;
                 }
             }
+        }
         }
         }
         }

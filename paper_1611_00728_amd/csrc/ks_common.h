@@ -74,6 +74,7 @@ struct TuneEntry {
     int nt = 256;
     int group = 1;      // link matrices loaded per pass of the Dslash site loop
     int way = 8;        // 8: a site's own backward slots; 4: neighbours' forward slots
+    int staged = 0;     // 1: x/y neighbour vectors staged in LDS
     int lds = 0;
     float us = 0.f;     // measured time per launch when tuned
     bool tuned = false;
@@ -231,8 +232,9 @@ extern const double kHisqLevel2[5];
 extern const double kHisqNaik;
 void hisq_links(const Geom& G, const double* thin, double* fat, double* naik,
                 const double* level1, const double* level2, double c_naik, hipStream_t st);
-// whether the kernel with this many link matrices per pass exists for the variant
-bool dslash_group_built(ks_prec_t prec, ks_recon_t recon, int links_per_pass);
+// whether the kernel of this launch form exists for the variant
+bool dslash_form_built(ks_prec_t prec, ks_recon_t recon, int links_per_pass, int link_access,
+                       int staged);
 // times the candidate launch configurations on this lattice and keeps the fastest
 void dslash_tune(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, hipStream_t s);
 
