@@ -111,9 +111,14 @@ __global__ __launch_bounds__(kNT) void net_layer_kernel(Geom g, const float2* __
 }
 
 // G_w[c][c'][p] += sum over sites and colours of conj((T_p phi_c')(x)_a) G_c(x)_a.
-// Per path, each value is reduced across the wave with cross-lane sums; lane k % 64 of the
-// wave keeps value k in its slot of the wave's LDS row (path-major order), and the block
-// writes one partial per value.  The order of every sum is fixed.
+// A block walks tiles of kWTile sites.  Per tile it stages G (all output channels) in LDS once,
+// then per path the transported inputs u = T_p phi (all input channels, two per thread); every
+// thread owns one (c, c') pair and a slice of the tile's sites and accumulates its conj(u) G
+// products per path in FP64 registers across all tiles.  At the end the slices of each pair
+// are summed in a fixed order and the block writes one partial per value.
+constexpr int kWTile = 64;
+constexpr int kWPitch = 3 * kWTile + 4;    // float2 per channel row of a stage (bank spread)
+
 template <int CIN, int COUT>
 __global__ __launch_bounds__(kNT) void net_wgrad_kernel(Geom g, const float2* __restrict__ in,
                                                         const float2* __restrict__ gy,
@@ -121,117 +126,129 @@ __global__ __launch_bounds__(kNT) void net_wgrad_kernel(Geom g, const float2* __
                                                         const void* __restrict__ fat_o,
                                                         double* __restrict__ partials)
 {
-    constexpr int NP = COUT * CIN * 2;              // reals per path
-    constexpr int NPL = (NP + 63) / 64;             // slots per lane per path
-    constexpr int NV = 9 * NP;
-    __shared__ double lds[kNT / 64][9 * NPL * 64];
+    constexpr int NPAIR = COUT * CIN;
+    constexpr int TPP = kNT / NPAIR;            // threads per (c, c') pair
+    constexpr int SPT = kWTile / TPP;           // sites per thread and tile
+    static_assert(kNT % NPAIR == 0 && kWTile % TPP == 0, "wgrad tiling");
+    __shared__ float2 gs[COUT * kWPitch];
+    __shared__ float2 us[CIN * kWPitch];
+    __shared__ double red[2 * 9 * kNT];
     const int vh = g.Vh;
-    const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
-    for (int k = lane; k < 9 * NPL * 64; k += 64) lds[wv][k] = 0.0;
-    for (int t0 = blockIdx.x * blockDim.x; t0 < 2 * vh; t0 += gridDim.x * blockDim.x) {
-        const int t = t0 + threadIdx.x;
+    const int tid = threadIdx.x;
+    const int pair = tid % NPAIR, slice = tid / NPAIR;
+    const int co = pair / CIN, ci = pair % CIN;
+    double ar[9], ai[9];
+#pragma unroll
+    for (int p = 0; p < 9; ++p) ar[p] = ai[p] = 0.0;
+    const int ntiles = (2 * vh + kWTile - 1) / kWTile;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        // ---- G of the tile's sites, every output channel
+        for (int e = tid; e < COUT * 3 * kWTile; e += kNT) {
+            const int site = e % kWTile, k = (e / kWTile) % 3, o = e / (3 * kWTile);
+            const int t = tile * kWTile + site;
+            float2 v = make_float2(0.f, 0.f);
+            if (t < 2 * vh) {
+                const int par = t >= vh ? 1 : 0;
+                v = act_ptr<COUT>(gy, par, o, k, vh)[t - par * vh];
+            }
+            gs[o * kWPitch + k * kWTile + site] = v;
+        }
+        // ---- per path: u = T_p phi for every input channel, then the products
+        const int site = tid % kWTile, cgrp = tid / kWTile;     // 4 groups of input channels
+        const int t = tile * kWTile + site;
         const bool live = t < 2 * vh;
         const int par = (live && t >= vh) ? 1 : 0;
         const int h = live ? t - par * vh : 0;
-        const void* fat = par ? fat_o : fat_e;
         int c[4];
         cb_coords(g, h, par, c);
         const int i = site_index(g, c);
-        cx<float> gv[COUT][3];
-#pragma unroll
-        for (int o = 0; o < COUT; ++o)
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const float2 q = live ? act_ptr<COUT>(gy, par, o, k, vh)[h] : make_float2(0.f, 0.f);
-                gv[o][k] = {q.x, q.y};
-            }
+        const void* fat = par ? fat_o : fat_e;
 #pragma unroll 1
         for (int p = 0; p < 9; ++p) {
+            __syncthreads();     // the previous path's products are done with us (and gs is in)
             cx<float> m[9];
             int nbh = h, spar = par;
             if (p > 0) {
                 const int s = p - 1;
-                const int mu = s & 3;
-                const bool bwd = s >= 4;
-                nbh = hop_cb(g, i, c, mu, bwd ? -1 : +1);
+                nbh = hop_cb(g, i, c, s & 3, s >= 4 ? -1 : +1);
                 spar = 1 - par;
                 load_link<KS_F32, 9>(fat, s, vh, h, m);
-                if (bwd)
+                if (s >= 4)   // the store holds -V(x-mu)^+
 #pragma unroll
                     for (int e = 0; e < 9; ++e) m[e] = {-m[e].r, -m[e].i};
             }
-            double acc[NPL];
-#pragma unroll
-            for (int j = 0; j < NPL; ++j) acc[j] = 0.0;
-#pragma unroll 1
-            for (int ci = 0; ci < CIN; ++ci) {
-                cx<float> v[3], tv[3];
+            for (int q = cgrp; q < CIN; q += kNT / kWTile) {
+                cx<float> v[3], u[3];
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
-                    const float2 q = live ? act_ptr<CIN>(in, spar, ci, k, vh)[nbh] : make_float2(0.f, 0.f);
-                    v[k] = {q.x, q.y};
+                    const float2 x = live ? act_ptr<CIN>(in, spar, q, k, vh)[nbh]
+                                          : make_float2(0.f, 0.f);
+                    v[k] = {x.x, x.y};
                 }
                 if (p == 0) {
 #pragma unroll
-                    for (int k = 0; k < 3; ++k) tv[k] = v[k];
+                    for (int k = 0; k < 3; ++k) u[k] = v[k];
                 } else {
 #pragma unroll
                     for (int a = 0; a < 3; ++a) {
-                        tv[a] = {0.f, 0.f};
+                        u[a] = {0.f, 0.f};
 #pragma unroll
-                        for (int b = 0; b < 3; ++b) cfma(tv[a], m[a * 3 + b], v[b]);
+                        for (int b = 0; b < 3; ++b) cfma(u[a], m[a * 3 + b], v[b]);
                     }
                 }
 #pragma unroll
-                for (int o = 0; o < COUT; ++o) {
-                    double sr = 0.0, si = 0.0;
+                for (int k = 0; k < 3; ++k)
+                    us[q * kWPitch + k * kWTile + site] = make_float2(u[k].r, u[k].i);
+            }
+            __syncthreads();
+            float sr = 0.f, si = 0.f;
+#pragma unroll 4
+            for (int j = 0; j < SPT; ++j) {
+                const int st = slice * SPT + j;
 #pragma unroll
-                    for (int k = 0; k < 3; ++k) {
-                        const cx<float> z = cconjmul(tv[k], gv[o][k]);
-                        sr += z.r;
-                        si += z.i;
-                    }
-                    sr = wave_sum(sr);
-                    si = wave_sum(si);
-                    // value (o, ci, re/im) sits at local index o*2*CIN + 2*ci + reim; one row
-                    // o never straddles a 64-lane slot (2*CIN <= 16 and rows start at
-                    // multiples of 2*CIN), so the slot is known at compile time
-                    constexpr int row = 2 * CIN;
-                    const int slot = (o * row) >> 6;
-                    const int l0 = ((o * row) & 63) + 2 * ci;
-                    if (l0 == lane) acc[slot] += sr;
-                    if (l0 + 1 == lane) acc[slot] += si;
+                for (int k = 0; k < 3; ++k) {
+                    const float2 u = us[ci * kWPitch + k * kWTile + st];
+                    const float2 gv = gs[co * kWPitch + k * kWTile + st];
+                    // conj(u) g
+                    sr = fmaf(u.x, gv.x, fmaf(u.y, gv.y, sr));
+                    si = fmaf(u.x, gv.y, fmaf(-u.y, gv.x, si));
                 }
             }
-#pragma unroll
-            for (int j = 0; j < NPL; ++j) lds[wv][(p * NPL + j) * 64 + lane] += acc[j];
+            ar[p] += sr;
+            ai[p] += si;
         }
+        __syncthreads();         // gs is rewritten by the next tile
+    }
+    // ---- sum the TPP slices of each pair in slice order, one partial per value
+#pragma unroll
+    for (int p = 0; p < 9; ++p) {
+        red[(2 * p) * kNT + tid] = ar[p];
+        red[(2 * p + 1) * kNT + tid] = ai[p];
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < NV; k += blockDim.x) {
+    constexpr int NV = NPAIR * 9 * 2;
+    for (int k = tid; k < NV; k += kNT) {
         // k in the weight order ((o*CIN + ci)*9 + p)*2 + reim
         const int reim = k & 1;
         const int p = (k >> 1) % 9;
-        const int oc = (k >> 1) / 9;
-        const int local = oc * 2 + reim;
-        const int slot = (p * NPL + (local >> 6)) * 64 + (local & 63);
+        const int pr = (k >> 1) / 9;           // = o * CIN + ci
         double s = 0.0;
-#pragma unroll
-        for (int w2 = 0; w2 < kNT / 64; ++w2) s += lds[w2][slot];
+        for (int sl = 0; sl < TPP; ++sl) s += red[(2 * p + reim) * kNT + sl * NPAIR + pr];
         partials[(size_t)blockIdx.x * NV + k] = s;
     }
 }
 
-// grad[k] += sum_b partials[b][k]  (fixed order)
-__global__ void net_grad_finish_kernel(const double* __restrict__ partials, int nblocks, int nv,
-                                       double* __restrict__ grad)
+// grad[k] += sum_b partials[b][k]: one block per value, strided thread sums and a block tree
+// (fixed order)
+__global__ __launch_bounds__(kNT) void net_grad_finish_kernel(const double* __restrict__ partials,
+                                                              int nblocks, int nv,
+                                                              double* __restrict__ grad)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nv) return;
+    const int k = blockIdx.x;
     double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += partials[(size_t)b * nv + k];
-    grad[k] += s;
+    for (int b = threadIdx.x; b < nblocks; b += kNT) s += partials[(size_t)b * nv + k];
+    s = block_sum<kNT>(s);
+    if (threadIdx.x == 0) grad[k] += s;
 }
 
 // w'[c'][c][pbar] = conj(w[c][c'][p])
@@ -353,9 +370,9 @@ void wgrad(NetCtx& n, NetBuffers& B, ks_gauge_t g, const float2* in, const float
 {
     const LinkStore& st = g->store[KS_F32][0];
     constexpr int NV = COUT * CIN * 9 * 2;
-    const int nb = std::min(blocks_for(2L * g->geom.Vh, kNT), kWgradBlocks);
+    const int nb = std::min(blocks_for(2L * g->geom.Vh, kWTile), kWgradBlocks);
     net_wgrad_kernel<CIN, COUT><<<nb, kNT, 0, s>>>(g->geom, in, gy, st.fat[0], st.fat[1], B.wpart);
-    net_grad_finish_kernel<<<blocks_for(NV, 256), 256, 0, s>>>(B.wpart, nb, NV, grad);
+    net_grad_finish_kernel<<<NV, kNT, 0, s>>>(B.wpart, nb, NV, grad);
     KS_HIP(hipGetLastError());
 }
 
