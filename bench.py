@@ -195,15 +195,105 @@ def learned48(args):
         "amortised_training_per_solve_s_over_100": (t_gen + t_train) / 100.0}), flush=True)
 
 
+def sweep(args):
+    """Dslash_eo bandwidth over lattice sizes (L^4 for L = 8 ... 48 and the paper's 20^3 x 64 and
+    24^3 x 60), every precision and Naik storage, each variant autotuned per lattice; and the
+    FP64 oracle on the host: Dslash_eo per site at 8^4, 16^4 and 32^4 on one thread and on all,
+    full CG solves at 8^4 and 16^4, and the 32^4 solve extrapolated from the time of 20 steps
+    times the GPU's step count.  One JSON line."""
+    import numpy as np
+    import torch
+    import paper_1611_00728_amd as ks
+    import oracle
+    from ksinputs import make_gauge, gaussian_source
+    lattices = [(L, L, L, L) for L in (8, 12, 16, 20, 24, 28, 32, 40, 48)] + \
+               [(20, 20, 20, 64), (24, 24, 24, 60)]
+    pmap = {"f64": ks.F64, "f32": ks.F32, "f16": ks.F16}
+    variants = [("f64", 18), ("f64", 12), ("f32", 18), ("f32", 12), ("f16", 18), ("f16", 12)]
+    stream = torch.cuda.current_stream()
+    rows = []
+    for dims in lattices:
+        seed = 1100 + dims[0] if dims[3] == dims[0] else 1200 + dims[0]
+        t0 = time.time()
+        g = make_gauge(dims, 0.5, seed)
+        vh = g.volume // 2
+        G = ks.Gauge(dims, g.fat, g.naik)
+        b = torch.from_numpy(gaussian_source(vh, seed + 1000)).cuda()
+        del g
+        row = {"lattice": list(dims), "even_sites": vh,
+               "cache_resident": vh * 2400 * 2 < 256e6}
+        for prec, rc in variants:
+            G.prepare(pmap[prec], rc)
+            cfg = G.tune(pmap[prec], rc)
+            ein = ks.Field(G, ks.EVEN, pmap[prec]).load(b)
+            eout = ks.Field(G, ks.ODD, pmap[prec])
+            for _ in range(3):
+                ks.dslash_eo(G, eout, ein, rc)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(BURST):
+                ks.dslash_eo(G, eout, ein, rc)
+            e1.record(stream)
+            stream.synchronize()
+            us = e0.elapsed_time(e1) * 1e3 / BURST
+            gbs = model_bytes_per_site(prec, rc) * vh / (us * 1e-6) / 1e9
+            row["%s_r%d" % (prec, rc)] = {"us": us, "GBps": gbs, "frac_of_8TBps": gbs / HBM_PEAK_GBS,
+                                          "launch": cfg}
+            del ein, eout
+        G.free()
+        torch.cuda.synchronize()
+        rows.append(row)
+        log("sweep %s: FP64 %.0f GB/s, FP16-12 %.0f GB/s (%.0f s)"
+            % ("x".join(map(str, dims)), row["f64_r18"]["GBps"], row["f16_r12"]["GBps"],
+               time.time() - t0))
+    # the oracle on the host cores
+    nthreads = oracle.max_threads()
+    cpu = {"threads_all": nthreads, "dslash_s_per_site": {}, "cg": {}}
+    for dims in ((8, 8, 8, 8), (16, 16, 16, 16), (32, 32, 32, 32)):
+        g = make_gauge(dims, 0.5, 1100 + dims[0])
+        vh = g.volume // 2
+        psi = gaussian_source(vh, 7)
+        entry = {}
+        for nt in (1, nthreads):
+            oracle.set_threads(nt)
+            oracle.dslash_eo(g, 0, psi)
+            n, t1 = 0, time.perf_counter()
+            while time.perf_counter() - t1 < 1.0 or n < 2:
+                oracle.dslash_eo(g, 0, psi)
+                n += 1
+            entry["threads_%d" % nt] = (time.perf_counter() - t1) / n / vh
+        cpu["dslash_s_per_site"]["x".join(map(str, dims))] = entry
+        oracle.set_threads(nthreads)
+        if dims[0] <= 16:
+            mass = 0.1 if dims[0] == 8 else 0.01
+            b = gaussian_source(vh, 8)
+            t1 = time.perf_counter()
+            _, info = oracle.cg(g, 4 * mass * mass, b, 1e-10)
+            cpu["cg"]["x".join(map(str, dims))] = {"seconds": time.perf_counter() - t1,
+                                                   "iters": info.iters, "mass": mass}
+        else:
+            b = gaussian_source(vh, 2002)
+            t1 = time.perf_counter()
+            oracle.cg(g, 4 * MASS * MASS, b, 1e-30, max_iter=20, max_restarts=0)
+            per = (time.perf_counter() - t1) / 20
+            cpu["cg"]["32x32x32x32"] = {"seconds_per_step": per, "extrapolated_seconds": per * 601,
+                                        "note": "20 timed steps x the GPU's 601 steps (extrapolated)"}
+        log("oracle %s done" % "x".join(map(str, dims)))
+    print(json.dumps({"workload": "Dslash_eo sweep over lattice sizes (H scale 0.5) and the FP64 "
+                                  "oracle's host timings", "rows": rows, "cpu_oracle": cpu}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="default", choices=["default", "learned48"],
+    ap.add_argument("--workload", default="default", choices=["default", "learned48", "sweep"],
                     help="learned48: the 48^3 x 64, m = 0.002 learned-preconditioner workload "
-                         "(training pairs, training, flexible CG vs mixed CG), its own JSON line")
+                         "(training pairs, training, flexible CG vs mixed CG); sweep: Dslash_eo "
+                         "over lattice sizes and the oracle's host timings; each its own JSON line")
     ap.add_argument("--dslash-only", type=int, default=0, metavar="N",
                     help="counter runs: N launches of each Dslash_eo variant and one plain "
                          "1 GiB device copy, then exit")
@@ -222,6 +312,9 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "learned48":
         learned48(args)
+        return
+    if args.workload == "sweep":
+        sweep(args)
         return
     t0 = time.time()
     g = make_gauge(DIMS, 0.5, 1002, keep_thin=True)

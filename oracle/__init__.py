@@ -15,7 +15,7 @@ and never imports it; the two meet only in the seeded inputs of `ksinputs`.
   Naik link built from thin links.
 * `quant.py`: the quantise-then-FP64 references of the reduced-precision storage formats.
 """
-from .core import (lib, dslash_full, dslash_eo, apply_A, cg, multishift_cg, embed, restrict,
+from .core import (lib, set_threads, max_threads, dslash_full, dslash_eo, apply_A, cg, multishift_cg, embed, restrict,
                    CGInfo, dense_A, lanczos_extremes, OracleError)
 from . import hisq
 from .quant import quantise_f32, quantise_f16_sites, quantise_f16_links, f16_link_exponent
@@ -24,7 +24,7 @@ from .network import (Network, PATHS, transport, transport_adj, layer_forward,
 from .solvers import (fcg, apply_M, full_solve, FullInfo, force_outer, rational_action,
                       parity_sign)
 
-__all__ = ["hisq", "lib", "dslash_full", "dslash_eo", "apply_A", "cg", "multishift_cg", "embed",
+__all__ = ["hisq", "lib", "set_threads", "max_threads", "dslash_full", "dslash_eo", "apply_A", "cg", "multishift_cg", "embed",
            "restrict", "CGInfo", "dense_A", "lanczos_extremes", "OracleError", "quantise_f32",
            "quantise_f16_sites", "quantise_f16_links", "f16_link_exponent", "Network", "PATHS",
            "transport", "transport_adj", "layer_forward", "network_forward", "loss_and_grad",

@@ -35,6 +35,8 @@ def lib():
         L.orc_cg.argtypes = [ip, dp, dp, C.c_double, dp, dp, C.c_double, C.c_int, C.c_int,
                              C.c_void_p, dp, dp]
         L.orc_multishift_cg.argtypes = [ip, dp, dp, C.c_int, dp, dp, dp, dp, C.c_int, ip, dp]
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_max_threads.argtypes = []
         _lib = L
     return _lib
 
@@ -65,6 +67,15 @@ def _links(g):
     fat = np.ascontiguousarray(g.fat, dtype=np.complex128)
     naik = np.ascontiguousarray(g.naik, dtype=np.complex128)
     return fat, naik
+
+
+def set_threads(n: int) -> None:
+    """Number of host threads the oracle's loops use (for timing it)."""
+    _check(lib().orc_set_threads(int(n)), "set_threads")
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())
 
 
 def dslash_full(g, psi: np.ndarray) -> np.ndarray:

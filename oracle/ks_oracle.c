@@ -25,6 +25,7 @@
  * neighbour arithmetic, no blocking or fusion.  OpenMP only splits the site loop.
  */
 #include <complex.h>
+#include <omp.h>
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -371,3 +372,13 @@ int orc_multishift_cg(const int n[4], const double* fat, const double* naik, int
     free(r); free(p); free(q); free(ps); free(zeta); free(zeta_prev); free(frozen);
     return status;
 }
+
+/* Thread count of the OpenMP loops (harness control for timing the oracle on n host cores). */
+int orc_set_threads(int n)
+{
+    if (n < 1) return ORC_BAD_ARG;
+    omp_set_num_threads(n);
+    return ORC_OK;
+}
+
+int orc_max_threads(void) { return omp_get_max_threads(); }
