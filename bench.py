@@ -1,16 +1,21 @@
 """Benchmark of the improved-staggered solver on one MI355X.
 
 Workload: the 32^4 lattice (thin-link scale 0.5, gauge seed 1002, source seed 2002, m = 0.01).
-One step is one pass of the hot path over it:
-  1. a timed burst of FP64 Dslash_eo launches (HIP events around every launch, on the stream
-     the library launches on), plus FP32 / FP16 and 12-real bursts;
-  2. the plain FP64 GPU CG solve to true relative residual 1e-10;
-  3. the mixed-precision CG solves (FP32 inner, FP16 inner with 12-real Naik) to the same
-     FP64 true residual.
+One step is one pass of the hot path:
+  1. timed bursts of Dslash_eo launches of all six variants (FP64 / FP32 / FP16, 18- and
+     12-real Naik; HIP events around every launch, on the stream the library launches on);
+  2. the batched solve (64 lattices of 8^4, 12^4, 16^4 x 4 right-hand sides, FP32 + RU);
+  3. the multi-shift solve on 32^3 x 48 (9 shifts, FP64 and FP32 + RU) and the force from
+     its solutions;
+  4. network bursts and the learned flexible CG;
+  5. the full-system solve M x = b and the link construction from thin links;
+  6. the plain FP64 GPU CG and the mixed-precision CG solves (FP32 inner, FP16 inner with
+     12-real Naik) to FP64 true relative residual 1e-10.
 `value` is the FP64 Dslash_eo's algorithmic HBM bandwidth (least-data model: 2400 bytes per
-output site) averaged over every launch of the timed steps.
+output site) averaged over every launch of the timed steps; the other rows report their own
+figures in the same JSON line.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload default|learned48|sweep]
 """
 from __future__ import annotations
 
@@ -27,7 +32,7 @@ HBM_PEAK_GBS = 8000.0
 DIMS = (32, 32, 32, 32)
 MASS = 0.01
 TOL = 1e-10
-BURST = 20
+BURST = 50
 
 
 def log(*a):
@@ -287,7 +292,7 @@ def sweep(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="default", choices=["default", "learned48", "sweep"],
