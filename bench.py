@@ -185,7 +185,10 @@ def learned48(args):
         torch.cuda.synchronize()
         rows[name] = {"seconds": time.perf_counter() - t, "iters": res.stats["iters"],
                       "true_rel_resid": res.stats["true_rel_resid"],
-                      "fallback": bool(res.stats["fallback"])}
+                      "fallback": bool(res.stats["fallback"]),
+                      "fallback_code": res.stats["fallback"],
+                      "flexible_steps": res.stats["iters"] - res.stats["restarts"]
+                      if res.stats["fallback"] else res.stats["iters"]}
         log("%s: %s" % (name, json.dumps(rows[name])))
     tm, tl = rows["mixed_f32_cg"]["seconds"], rows["learned_fcg"]["seconds"]
     print(json.dumps({
@@ -680,6 +683,9 @@ def main():
     overhead = t_gen + t_train
     tts["learned_fcg_f32"] = {
         "seconds": lmed, "iters": lst["iters"], "fallback": bool(lst["fallback"]),
+        "fallback_reason": {0: None, 1: "N(r) not finite", 2: "Re<N(r), r> <= 0",
+                            3: "<p, Ap> <= 0", 4: "|r| not halved in 50 steps",
+                            5: "max_iter"}[lst["fallback"]],
         "fallback_iters": lst["restarts"], "reliable_updates": lst["reliable_updates"],
         "true_rel_resid": lst["true_rel_resid"], "speedup_vs_f64": base / lmed,
         "speedup_vs_mixed_f32": t_mixed / lmed,

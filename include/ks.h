@@ -73,7 +73,9 @@ typedef struct {
     int iters;                 /* Krylov steps taken */
     int reliable_updates;      /* FP64 recomputations of r = b - A x */
     int restarts;              /* FP64 checks that failed and continued the loop */
-    int fallback;              /* flexible CG only: 1 when it fell back to plain CG */
+    int fallback;              /* flexible CG only: 0, or why it fell back to plain CG: 1 N(r) not
+                                  finite, 2 Re<N(r), r> <= 0, 3 <p, A p> <= 0, 4 |r| not halved
+                                  in 50 steps, 5 max_iter */
     double true_rel_resid;     /* FP64 |b - A x| / |b| at return, computed on the GPU */
     double seconds;            /* wall time of the call */
     double model_bytes;        /* least-data model bytes of the work done */
@@ -344,7 +346,7 @@ ks_status_t ks_net_train(ks_net_t n, int npairs, const ks_gauge_t* gauges,
  * the inner operator and vectors in p->inner precision (KS_F16 is taken as KS_F32), x in FP64,
  * FP64 reliable updates, and fallback to ks_cg_solve's method from the current x when N(r)
  * is not finite, when Re<N(r), r> <= 0, when |r| has not halved in 50 steps, or at
- * p->max_iter (st->fallback = 1, st->restarts = steps of the fallback).  b_dev, x_dev as in
+ * p->max_iter (st->fallback = the reason's code, st->restarts = steps of the fallback).  b_dev, x_dev as in
  * ks_cg_solve. */
 ks_status_t ks_fcg_solve(ks_gauge_t g, ks_net_t n, double mass, const double* b_dev,
                          double* x_dev, const ks_solver_params* p, int use_mfma,

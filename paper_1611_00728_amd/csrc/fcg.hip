@@ -221,6 +221,7 @@ ks_status_t fcg_core(ks_gauge_t g, NetCtx& net, double sigma, const double* b, d
     double true_r2 = rho;
     int it = 0, ru = 0;
     bool done = rho <= stop2, fallback = false;
+    int reason = 0;   // why the flexible iteration stopped (see ks_solver_stats.fallback)
     std::deque<double> hist;
     hist.push_back(std::sqrt(rho));
     std::complex<double> zr;
@@ -232,8 +233,10 @@ ks_status_t fcg_core(ks_gauge_t g, NetCtx& net, double sigma, const double* b, d
         zr = {hs[0], hs[1]};
     }
     while (!done) {
-        if (it >= prm.max_iter || !std::isfinite(zr.real()) || !std::isfinite(zr.imag()) ||
-            zr.real() <= 0.0) {
+        if (!std::isfinite(zr.real()) || !std::isfinite(zr.imag())) reason = 1;
+        else if (zr.real() <= 0.0) reason = 2;
+        else if (it >= prm.max_iter) reason = 5;
+        if (reason) {
             fallback = true;
             break;
         }
@@ -261,6 +264,7 @@ ks_status_t fcg_core(ks_gauge_t g, NetCtx& net, double sigma, const double* b, d
         const std::complex<double> pr(hs[0], hs[1]);
         if (!(pap > 0.0) || !std::isfinite(pap)) {
             fallback = true;
+            reason = 3;
             break;
         }
         const std::complex<double> alpha = pr / pap;
@@ -290,6 +294,7 @@ ks_status_t fcg_core(ks_gauge_t g, NetCtx& net, double sigma, const double* b, d
         if (hist.size() > 51) hist.pop_front();
         if (hist.size() == 51 && hist.back() > 0.5 * hist.front()) {
             fallback = true;
+            reason = 4;
             break;
         }
         rho = rn;
@@ -318,7 +323,7 @@ ks_status_t fcg_core(ks_gauge_t g, NetCtx& net, double sigma, const double* b, d
     stats.iters = it + fb_iters;
     stats.reliable_updates = ru;
     stats.restarts = fb_iters;        // steps taken by the fallback CG
-    stats.fallback = fallback ? 1 : 0;
+    stats.fallback = fallback ? reason : 0;
     stats.true_rel_resid = std::sqrt(true_r2 / b2);
     stats.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return rc;

@@ -195,4 +195,6 @@ def test_fcg_fallback(ks, lat):
                        raise_on_error=False)
     torch.cuda.synchronize()
     tr = float(np.linalg.norm(b - oracle.apply_A(lat, 0.01, host(x))) / np.linalg.norm(b))
-    assert res.status == 0 and res.stats["fallback"] == 1 and tr <= 1e-10
+    # reason 2: Re<N(r), r> <= 0 before the first flexible step
+    assert res.status == 0 and res.stats["fallback"] == 2 and tr <= 1e-10
+    assert res.stats["restarts"] == res.stats["iters"]
