@@ -93,7 +93,7 @@ __device__ __forceinline__ bool lattice_busy(const BatchPair* pairs, int p0, int
     return false;
 }
 
-// out_r = D in_r for every RHS r of the site (XPAY: out_r = sigma_l x_r - D in_r, with
+// out_r = D in_r for every RHS r of the site (XPAY: out_r = sigma_r x_r - D in_r, with
 // per-tile partial sums of Re<x_r, out_r>).  RU selects the FP64 reliable-update form, which
 // works only on lattices with a pair whose update is due; otherwise lattices with a pair
 // still iterating.
@@ -155,11 +155,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void ba
             if (XPAY) {
                 cx<T> xs[3][R];
                 V::load(xv, L.vec_off, vh, h, xs);
-                const T sg = (T)L.sigma;
 #pragma unroll
                 for (int k = 0; k < 3; ++k)
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
+                        const T sg = (T)pairs[L.pair0 + r].sigma;
                         res[k][r].r = sg * xs[k][r].r - res[k][r].r;
                         res[k][r].i = sg * xs[k][r].i - res[k][r].i;
                         dot[r] += (double)xs[k][r].r * (double)res[k][r].r +
@@ -480,7 +480,8 @@ __global__ void batch_clock_kernel(unsigned long long* out) { *out = wall_clock6
 __global__ __launch_bounds__(kFin) void batch_init_pairs_kernel(const LatDesc* __restrict__ lats,
                                                                 int R, BatchPair* __restrict__ pairs,
                                                                 const char* __restrict__ b64,
-                                                                double tol, double delta,
+                                                                const double* __restrict__ param,
+                                                                int npairs, double delta,
                                                                 int max_iter,
                                                                 double* __restrict__ b2_out)
 {
@@ -497,6 +498,8 @@ __global__ __launch_bounds__(kFin) void batch_init_pairs_kernel(const LatDesc* _
     s = block_sum<kFin>(s);
     if (threadIdx.x != 0) return;
     BatchPair q{};
+    q.sigma = param[pi];
+    const double tol = param[npairs + pi];
     q.stop2 = tol * tol * s;
     q.delta = delta;
     q.max_iter = max_iter;
@@ -645,10 +648,11 @@ void batch_free(BatchCtx* c)
 {
     if (!c) return;
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
-    for (ks_gauge_t g : c->gauges) {
-        gauge_release(g);
-        delete g;
-    }
+    if (c->owns_gauges)
+        for (ks_gauge_t g : c->gauges) {
+            gauge_release(g);
+            delete g;
+        }
     device_free(c->lats_dev);
     for (int k = 0; k < 3; ++k) device_free(c->tiles[k]);
     device_free(c->partials);
@@ -656,6 +660,7 @@ void batch_free(BatchCtx* c)
     device_free(c->clock);
     device_free(c->census);
     device_free(c->b2);
+    device_free(c->pair_param);
     device_free(c->io_ptrs);
     for (char* v : {c->ps, c->qs, c->ts, c->rs, c->x64, c->b64, c->r64, c->t64, c->ax64})
         device_free(v);
@@ -666,22 +671,101 @@ void batch_free(BatchCtx* c)
     delete c;
 }
 
+// Lattice descriptors, tile tables, pair state and vector arenas for the gauges of c.
+static void batch_setup(BatchCtx* c, hipStream_t s)
+{
+    const int nlat = (int)c->gauges.size();
+    const int nrhs = c->nrhs;
+    const ks_prec_t inner = c->prec;
+    size_t vec_off = 0;
+    std::vector<LatDesc> lats(nlat);
+    for (int l = 0; l < nlat; ++l) {
+        ks_gauge_t g = c->gauges[l];
+        if (inner != KS_F64) gauge_prepare(g, inner, KS_RECON_18, s);
+        LatDesc& L = lats[l];
+        L.g = g->geom;
+        for (int par = 0; par < 2; ++par) {
+            L.fat64[par] = g->store[KS_F64][0].fat[par];
+            L.naik64[par] = g->store[KS_F64][0].naik[par];
+            L.fat32[par] = g->store[inner][0].fat[par];
+            L.naik32[par] = g->store[inner][0].naik[par];
+        }
+        L.vec_off = vec_off;
+        L.pair0 = l * nrhs;
+        vec_off += (size_t)g->geom.Vh;
+    }
+    c->total_vh = vec_off;
+    // tile tables for 64, 128 and 256 sites per tile
+    size_t max_tiles = 0;
+    for (int k = 0; k < 3; ++k) {
+        std::vector<int2> tt;
+        for (int l = 0; l < nlat; ++l) {
+            if (k == 0) lats[l].tile_begin = (int)tt.size();
+            for (int h0 = 0; h0 < lats[l].g.Vh; h0 += kTileSizes[k]) tt.push_back(make_int2(l, h0));
+        }
+        c->ntiles[k] = (int)tt.size();
+        c->tiles[k] = static_cast<int2*>(device_alloc(sizeof(int2) * tt.size()));
+        KS_HIP(hipMemcpyAsync(c->tiles[k], tt.data(), sizeof(int2) * tt.size(),
+                              hipMemcpyHostToDevice, s));
+        max_tiles = std::max(max_tiles, tt.size());
+        c->tile_tables[k] = tt;
+    }
+    c->lats_host = lats;
+    c->lats_dev = static_cast<LatDesc*>(device_alloc(sizeof(LatDesc) * nlat));
+    c->set_tiles(0, s);
+    c->partials = static_cast<double*>(device_alloc(sizeof(double) * max_tiles * nrhs));
+    c->pairs = static_cast<BatchPair*>(device_alloc(sizeof(BatchPair) * c->npairs));
+    KS_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->pairs_host), sizeof(BatchPair) * c->npairs));
+    c->clock = static_cast<unsigned long long*>(device_alloc(sizeof(unsigned long long)));
+    c->census = static_cast<int*>(device_alloc(sizeof(int)));
+    c->b2 = static_cast<double*>(device_alloc(sizeof(double) * c->npairs));
+    c->pair_param = static_cast<double*>(device_alloc(sizeof(double) * 2 * c->npairs));
+    c->io_ptrs = static_cast<void**>(device_alloc(sizeof(void*) * c->npairs));
+    KS_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->census_host), sizeof(int)));
+    const size_t cs = inner == KS_F64 ? 16 : 8;
+    const size_t nrec = vec_off * 3 * nrhs;
+    c->ps = static_cast<char*>(device_alloc(nrec * cs));
+    c->qs = static_cast<char*>(device_alloc(nrec * cs));
+    c->ts = static_cast<char*>(device_alloc(nrec * cs));
+    c->rs = static_cast<char*>(device_alloc(nrec * cs));
+    c->x64 = static_cast<char*>(device_alloc(nrec * 16));
+    c->b64 = static_cast<char*>(device_alloc(nrec * 16));
+    c->r64 = static_cast<char*>(device_alloc(nrec * 16));
+    c->t64 = static_cast<char*>(device_alloc(nrec * 16));
+    c->ax64 = static_cast<char*>(device_alloc(nrec * 16));
+    // finished pairs leave their slots of p, q, t untouched: start every arena finite
+    for (char* a : {c->ps, c->qs, c->ts, c->rs})
+        KS_HIP(hipMemsetAsync(a, 0, nrec * cs, s));
+    for (char* a : {c->x64, c->b64, c->r64, c->t64, c->ax64})
+        KS_HIP(hipMemsetAsync(a, 0, nrec * 16, s));
+    KS_HIP(hipStreamSynchronize(s));
+}
+
+static BatchCtx* batch_new(int nrhs, ks_prec_t inner)
+{
+    KS_REQUIRE(nrhs == 1 || nrhs == 2 || nrhs == 4, KS_ERR_ARG, "batch: nrhs must be 1, 2 or 4");
+    KS_REQUIRE(inner == KS_F64 || inner == KS_F32, KS_ERR_ARG, "batch: inner precision F64 or F32");
+    BatchCtx* c = new BatchCtx();
+    c->nrhs = nrhs;
+    c->prec = inner;
+    try {
+        KS_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+        KS_HIP(hipEventCreateWithFlags(&c->order, hipEventDisableTiming));
+    } catch (...) {
+        batch_free(c);
+        throw;
+    }
+    return c;
+}
+
 BatchCtx* batch_create(int nlat, const int* dims, const double* const* fat,
                        const double* const* naik, int on_device, int nrhs, ks_prec_t inner,
                        hipStream_t s)
 {
     KS_REQUIRE(nlat >= 1, KS_ERR_ARG, "batch: no lattices");
-    KS_REQUIRE(nrhs == 1 || nrhs == 2 || nrhs == 4, KS_ERR_ARG, "batch: nrhs must be 1, 2 or 4");
-    KS_REQUIRE(inner == KS_F64 || inner == KS_F32, KS_ERR_ARG, "batch: inner precision F64 or F32");
-    BatchCtx* c = new BatchCtx();
+    BatchCtx* c = batch_new(nrhs, inner);
     try {
-        KS_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
-        KS_HIP(hipEventCreateWithFlags(&c->order, hipEventDisableTiming));
-        c->nrhs = nrhs;
-        c->prec = inner;
         c->npairs = nlat * nrhs;
-        size_t vec_off = 0;
-        std::vector<LatDesc> lats(nlat);
         for (int l = 0; l < nlat; ++l) {
             const int* d = dims + 4 * l;
             long v = 1;
@@ -712,63 +796,23 @@ BatchCtx* batch_create(int nlat, const int* dims, const double* const* fat,
             gauge_build_f64(g, df, dn, s);
             device_free(tf);
             device_free(tn);
-            if (inner != KS_F64) gauge_prepare(g, inner, KS_RECON_18, s);
-            LatDesc& L = lats[l];
-            L.g = g->geom;
-            for (int par = 0; par < 2; ++par) {
-                L.fat64[par] = g->store[KS_F64][0].fat[par];
-                L.naik64[par] = g->store[KS_F64][0].naik[par];
-                L.fat32[par] = g->store[inner][0].fat[par];
-                L.naik32[par] = g->store[inner][0].naik[par];
-            }
-            L.vec_off = vec_off;
-            L.pair0 = l * nrhs;
-            vec_off += (size_t)g->geom.Vh;
         }
-        c->total_vh = vec_off;
-        // tile tables for 64, 128 and 256 sites per tile
-        size_t max_tiles = 0;
-        for (int k = 0; k < 3; ++k) {
-            std::vector<int2> tt;
-            for (int l = 0; l < nlat; ++l) {
-                if (k == 0) lats[l].tile_begin = (int)tt.size();
-                for (int h0 = 0; h0 < lats[l].g.Vh; h0 += kTileSizes[k]) tt.push_back(make_int2(l, h0));
-            }
-            c->ntiles[k] = (int)tt.size();
-            c->tiles[k] = static_cast<int2*>(device_alloc(sizeof(int2) * tt.size()));
-            KS_HIP(hipMemcpyAsync(c->tiles[k], tt.data(), sizeof(int2) * tt.size(),
-                                  hipMemcpyHostToDevice, s));
-            max_tiles = std::max(max_tiles, tt.size());
-            c->tile_tables[k] = tt;
-        }
-        c->lats_host = lats;
-        c->lats_dev = static_cast<LatDesc*>(device_alloc(sizeof(LatDesc) * nlat));
-        c->set_tiles(0, s);
-        c->partials = static_cast<double*>(device_alloc(sizeof(double) * max_tiles * nrhs));
-        c->pairs = static_cast<BatchPair*>(device_alloc(sizeof(BatchPair) * c->npairs));
-        KS_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->pairs_host), sizeof(BatchPair) * c->npairs));
-        c->clock = static_cast<unsigned long long*>(device_alloc(sizeof(unsigned long long)));
-        c->census = static_cast<int*>(device_alloc(sizeof(int)));
-        c->b2 = static_cast<double*>(device_alloc(sizeof(double) * c->npairs));
-        c->io_ptrs = static_cast<void**>(device_alloc(sizeof(void*) * c->npairs));
-        KS_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->census_host), sizeof(int)));
-        const size_t cs = inner == KS_F64 ? 16 : 8;
-        const size_t nrec = vec_off * 3 * nrhs;
-        c->ps = static_cast<char*>(device_alloc(nrec * cs));
-        c->qs = static_cast<char*>(device_alloc(nrec * cs));
-        c->ts = static_cast<char*>(device_alloc(nrec * cs));
-        c->rs = static_cast<char*>(device_alloc(nrec * cs));
-        c->x64 = static_cast<char*>(device_alloc(nrec * 16));
-        c->b64 = static_cast<char*>(device_alloc(nrec * 16));
-        c->r64 = static_cast<char*>(device_alloc(nrec * 16));
-        c->t64 = static_cast<char*>(device_alloc(nrec * 16));
-        c->ax64 = static_cast<char*>(device_alloc(nrec * 16));
-        // finished pairs leave their slots of p, q, t untouched: start every arena finite
-        for (char* a : {c->ps, c->qs, c->ts, c->rs})
-            KS_HIP(hipMemsetAsync(a, 0, nrec * cs, s));
-        for (char* a : {c->x64, c->b64, c->r64, c->t64, c->ax64})
-            KS_HIP(hipMemsetAsync(a, 0, nrec * 16, s));
-        KS_HIP(hipStreamSynchronize(s));
+        batch_setup(c, s);
+    } catch (...) {
+        batch_free(c);
+        throw;
+    }
+    return c;
+}
+
+BatchCtx* batch_create_on(ks_gauge_t g, int nrhs, ks_prec_t inner, hipStream_t s)
+{
+    BatchCtx* c = batch_new(nrhs, inner);
+    try {
+        c->owns_gauges = false;
+        c->npairs = nrhs;
+        c->gauges.push_back(g);
+        batch_setup(c, s);
     } catch (...) {
         batch_free(c);
         throw;
@@ -828,21 +872,37 @@ ks_status_t batch_solve(BatchCtx& c, const double* masses, const double* const* 
                         double* const* x, const ks_solver_params& prm, ks_batch_stats* stats,
                         hipStream_t caller)
 {
-    const auto t0 = std::chrono::steady_clock::now();
-    const hipStream_t s = enter_stream(c, caller);
     const int nlat = (int)c.lats_host.size();
+    std::vector<double> sigma(c.npairs), tol(c.npairs, prm.tol);
     for (int l = 0; l < nlat; ++l) {
         KS_REQUIRE(std::isfinite(masses[l]), KS_ERR_ARG, "batch: mass %d is not finite", l);
-        c.lats_host[l].sigma = 4.0 * masses[l] * masses[l];
+        for (int r = 0; r < c.nrhs; ++r) sigma[l * c.nrhs + r] = 4.0 * masses[l] * masses[l];
     }
-    for (int p = 0; p < c.npairs; ++p)
+    return batch_solve_pairs(c, sigma.data(), tol.data(), b, x, prm, stats, caller);
+}
+
+ks_status_t batch_solve_pairs(BatchCtx& c, const double* sigma, const double* tol,
+                              const double* const* b, double* const* x,
+                              const ks_solver_params& prm, ks_batch_stats* stats,
+                              hipStream_t caller)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    const hipStream_t s = enter_stream(c, caller);
+    std::vector<double> param(2 * (size_t)c.npairs);
+    for (int p = 0; p < c.npairs; ++p) {
         KS_REQUIRE(b[p] && x[p] && b[p] != x[p], KS_ERR_ARG, "batch: bad vectors for pair %d", p);
-    KS_HIP(hipMemcpyAsync(c.lats_dev, c.lats_host.data(), sizeof(LatDesc) * nlat,
+        KS_REQUIRE(std::isfinite(sigma[p]) && sigma[p] >= 0.0 && tol[p] > 0.0, KS_ERR_ARG,
+                   "batch: bad shift or tolerance for pair %d", p);
+        param[p] = sigma[p];
+        param[c.npairs + p] = tol[p];
+    }
+    KS_HIP(hipMemcpyAsync(c.pair_param, param.data(), sizeof(double) * param.size(),
                           hipMemcpyHostToDevice, s));
     batch_io(c, c.b64, reinterpret_cast<const void* const*>(b), 1, s);
     batch_io(c, c.x64, reinterpret_cast<const void* const*>(x), 1, s);
     batch_clock_kernel<<<1, 1, 0, s>>>(c.clock);
-    batch_init_pairs_kernel<<<c.npairs, kFin, 0, s>>>(c.lats_dev, c.nrhs, c.pairs, c.b64, prm.tol,
+    batch_init_pairs_kernel<<<c.npairs, kFin, 0, s>>>(c.lats_dev, c.nrhs, c.pairs, c.b64,
+                                                      c.pair_param, c.npairs,
                                                       c.prec == KS_F64 ? 0.0 : prm.delta,
                                                       prm.max_iter, c.b2);
     KS_HIP(hipGetLastError());

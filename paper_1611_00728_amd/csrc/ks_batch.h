@@ -15,13 +15,13 @@ struct LatDesc {
     const void* fat64[2];     // FP64 link planes (reliable updates)
     const void* naik64[2];
     size_t vec_off;           // site offset of this lattice in every vector arena
-    double sigma;             // 4 m^2 of this lattice
     int tile_begin, tile_end; // its range in the active tile table
     int pair0;                // first (lattice, RHS) pair index
 };
 
 // CG scalars of one (lattice, RHS) pair.
 struct BatchPair {
+    double sigma;                // shift of this pair's operator, sigma - D_eo D_oe
     double rho, alpha, beta, maxr, stop2, delta, true_r2;
     double rn;                   // |r|^2 of the step, applied to rho once the step's updates are known
     unsigned long long t_done;   // device wall clock at convergence
@@ -35,6 +35,7 @@ struct BatchCtx {
     ks_prec_t prec = KS_F32;
     size_t total_vh = 0;
     std::vector<ks_gauge_t> gauges;
+    bool owns_gauges = true;   // false: built on a caller's gauge handle, which keeps its stores
     std::vector<LatDesc> lats_host;
     LatDesc* lats_dev = nullptr;
     std::vector<int2> tile_tables[3];
@@ -54,6 +55,7 @@ struct BatchCtx {
     char *x64 = nullptr, *b64 = nullptr, *r64 = nullptr, *t64 = nullptr, *ax64 = nullptr;
     void** io_ptrs = nullptr;  // device table of the caller's per-pair vectors
     double* b2 = nullptr;      // |b|^2 per pair
+    double* pair_param = nullptr;     // device [2][npairs]: shift and tolerance of each pair
     hipStream_t stream = nullptr;     // the batch's own stream (default priority)
     hipEvent_t order = nullptr;       // orders it after the caller's stream
     hipGraphExec_t graph_exec = nullptr;
@@ -72,6 +74,12 @@ ks_status_t batch_solve(BatchCtx& c, const double* masses, const double* const* 
                         double* const* x, const ks_solver_params& prm, ks_batch_stats* stats,
                         hipStream_t s);
 void batch_tune(BatchCtx& c, hipStream_t s);
+// one lattice with nrhs right-hand sides on an existing gauge handle (its stores are shared)
+BatchCtx* batch_create_on(ks_gauge_t g, int nrhs, ks_prec_t inner, hipStream_t s);
+// solve with a shift and a tolerance per pair (host arrays of npairs); b, x as in batch_solve
+ks_status_t batch_solve_pairs(BatchCtx& c, const double* sigma, const double* tol,
+                              const double* const* b, double* const* x,
+                              const ks_solver_params& prm, ks_batch_stats* stats, hipStream_t s);
 
 }  // namespace ks
 

@@ -42,6 +42,10 @@ struct Workspace {
     double* full[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     // force: per term the even solution and its odd hopping image, FP64 planes
     std::vector<double*> force_psi;
+    // multi-shift refinement of several shifts at once: batched CG contexts on this gauge
+    // (1, 2 or 4 right-hand sides) and boundary-layout vectors for them
+    struct BatchCtx* ms_batch[3] = {nullptr, nullptr, nullptr};
+    std::vector<double*> ms_io;
 };
 
 Workspace& workspace(ks_gauge_t g);

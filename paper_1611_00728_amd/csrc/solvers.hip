@@ -9,6 +9,7 @@
 #include <cmath>
 #include <vector>
 
+#include "ks_batch.h"
 #include "ks_blas.h"
 #include "ks_device.h"
 #include "ks_solvers.h"
@@ -105,6 +106,8 @@ void workspace_free(Workspace* w)
     device_free(w->ms_st);
     for (double* v : w->full) device_free(v);
     for (double* v : w->force_psi) device_free(v);
+    for (BatchCtx* c : w->ms_batch) batch_free(c);
+    for (double* v : w->ms_io) device_free(v);
     if (w->ms_st_host) (void)hipHostFree(w->ms_st_host);
     delete w;
 }

@@ -116,7 +116,7 @@ def test_cg_ragged_lattices(ks, dims):
         assert res.ok and true_rel(g, 0.01, b, x) <= 1e-10
 
 
-@pytest.mark.parametrize("inner", ["f64", "f32"])
+@pytest.mark.parametrize("inner", ["f64", "f32", "f16"])
 def test_multishift(ks, cfg1, inner):
     announce("multishift 8^4", inner)
     g, G, b, _, _ = cfg1
@@ -127,9 +127,12 @@ def test_multishift(ks, cfg1, inner):
                                        ks.default_params(inner=ks.PREC[inner], check_every=4),
                                        raise_on_error=False)
     assert rc == 0
-    if inner == "f32":
+    if inner != "f64":
         # the base residual is recomputed in FP64 during the shared iteration
         assert stats[0]["reliable_updates"] >= 1
+        # several shifts need refinement after the reduced-precision phase: they are refined
+        # together by the batched CG (one right-hand side per shift)
+        assert sum(1 for st in stats if st["restarts"]) >= 2
     xo, _, _, st = oracle.multishift_cg(g, sig, b, 1e-11)
     for i, s in enumerate(sig):
         x = host(xs[i])
