@@ -454,7 +454,7 @@ def main():
     MS_DIMS = (32, 32, 32, 48)
     gm = make_gauge(MS_DIMS, 0.5, SEEDS["gauge"](3))
     GM = ks.Gauge(MS_DIMS, gm.fat, gm.naik)
-    for p_ in (ks.F64, ks.F32):
+    for p_ in (ks.F64, ks.F32, ks.F16):
         GM.prepare(p_, 18)
         GM.tune(p_, 18)
     mb_ = torch.from_numpy(gaussian_source(gm.volume // 2, SEEDS["source"](3))).cuda()
@@ -463,7 +463,7 @@ def main():
     ms_vh = gm.volume // 2
     del gm
     log("32^3x48 multi-shift field ready in %.1f s" % (time.time() - t1))
-    ms_runs = {"f64": [], "f32": []}
+    ms_runs = {"f64": [], "f32": [], "f16": []}
 
     # link derivative of sum_i r_i b^+ A_i^-1 b from the nine solutions (residues 1/(i+1))
     ms_res = [1.0 / (i + 1) for i in range(len(ms_sigma))]
@@ -473,7 +473,7 @@ def main():
     force_runs = []
 
     def multishift(record):
-        for name, p_ in (("f64", ks.F64), ("f32", ks.F32)):
+        for name, p_ in (("f64", ks.F64), ("f32", ks.F32), ("f16", ks.F16)):
             torch.cuda.synchronize()
             t = time.perf_counter()
             rc, st = ks.multishift_cg_solve(GM, ms_sigma, mb_, ms_x, 1e-9,
