@@ -454,16 +454,16 @@ def main():
     MS_DIMS = (32, 32, 32, 48)
     gm = make_gauge(MS_DIMS, 0.5, SEEDS["gauge"](3))
     GM = ks.Gauge(MS_DIMS, gm.fat, gm.naik)
-    for p_ in (ks.F64, ks.F32, ks.F16):
-        GM.prepare(p_, 18)
-        GM.tune(p_, 18)
+    for p_, rc_ in ((ks.F64, 18), (ks.F32, 18), (ks.F32, 12), (ks.F16, 18)):
+        GM.prepare(p_, rc_)
+        GM.tune(p_, rc_)
     mb_ = torch.from_numpy(gaussian_source(gm.volume // 2, SEEDS["source"](3))).cuda()
     ms_sigma = 4 * np.geomspace(0.002, 0.5, 9) ** 2
     ms_x = [torch.zeros_like(mb_) for _ in ms_sigma]
     ms_vh = gm.volume // 2
     del gm
     log("32^3x48 multi-shift field ready in %.1f s" % (time.time() - t1))
-    ms_runs = {"f64": [], "f32": [], "f16": []}
+    ms_runs = {"f64": [], "f32": [], "f32_r12": [], "f16": []}
 
     # link derivative of sum_i r_i b^+ A_i^-1 b from the nine solutions (residues 1/(i+1))
     ms_res = [1.0 / (i + 1) for i in range(len(ms_sigma))]
@@ -473,11 +473,13 @@ def main():
     force_runs = []
 
     def multishift(record):
-        for name, p_ in (("f64", ks.F64), ("f32", ks.F32), ("f16", ks.F16)):
+        for name, p_, rc_ in (("f64", ks.F64, 18), ("f32", ks.F32, 18), ("f32_r12", ks.F32, 12),
+                              ("f16", ks.F16, 18)):
             torch.cuda.synchronize()
             t = time.perf_counter()
             rc, st = ks.multishift_cg_solve(GM, ms_sigma, mb_, ms_x, 1e-9,
-                                            ks.default_params(inner=p_, check_every=16))
+                                            ks.default_params(inner=p_, recon=rc_,
+                                                              check_every=16))
             torch.cuda.synchronize()
             if record:
                 ms_runs[name].append((time.perf_counter() - t, st))

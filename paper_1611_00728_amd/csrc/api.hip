@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstdint>
 #include <cstring>
+#include <new>
 #include <vector>
 
 #include "ks_common.h"
@@ -72,6 +73,10 @@ using namespace ks;
     }                                                                                   \
     catch (const Failure& f) {                                                          \
         return f.code;                                                                  \
+    }                                                                                   \
+    catch (const std::bad_alloc&) {                                                     \
+        set_error("host memory exhausted");                                             \
+        return KS_ERR_NOMEM;                                                            \
     }                                                                                   \
     catch (...) {                                                                       \
         set_error("unexpected C++ exception");                                          \
