@@ -30,6 +30,7 @@ struct Workspace {
     // multi-shift
     std::vector<void*> ms_x;      // FP64 solutions
     std::vector<void*> ms_p;      // shifted directions, inner precision
+    std::vector<void*> ms_dx;     // FP32 increments of the shifted solutions (reduced precision)
     int ms_prec = -1;
     void* ms_r = nullptr;
     void* ms_pb = nullptr;

@@ -38,6 +38,8 @@ struct MSState {
 struct ShiftPtrs {
     double2* x[kMaxShift];
     void* p[kMaxShift];
+    void* dx[kMaxShift];   // FP32 increments of x_i since the last flush (reduced precision)
+    int sloppy;            // 1: the shared phase adds alpha_i p_i to dx_i instead of x_i
 };
 
 __device__ __forceinline__ double finish_sum(const double* in, int n)
@@ -145,7 +147,9 @@ __global__ __launch_bounds__(kFinish) void ms_beta_kernel(const double* __restri
 }
 
 // x_i += alpha_i p_i; p_i = zeta_i r + beta_i p_i for every shift updated this step, and the
-// base direction p = r + beta p.  r is read once per site for all shifts.
+// base direction p = r + beta p.  r is read once per site for all shifts.  In reduced
+// precision the x_i increments go to FP32 fields that are added into the FP64 x_i at every
+// reliable update of the base and at the end (half the bytes of an FP64 read-modify-write).
 template <int P>
 __global__ __launch_bounds__(kBlock) void ms_update_kernel(int vh, const void* __restrict__ r,
                                                            void* __restrict__ pb, ShiftPtrs sp,
@@ -163,13 +167,29 @@ __global__ __launch_bounds__(kBlock) void ms_update_kernel(int vh, const void* _
         const double ai = st->alpha_i[i];
         const R bi = (R)st->beta_i[i], zi = (R)st->zeta[i];
         Spinor<P>::load(sp.p[i], vh, h, pv);
-        double2* x = sp.x[i];
+        if (sp.sloppy) {
+            // x_i's increments accumulate in FP32 between flushes into the FP64 x_i
+            cx<float> d[3];
+            Spinor<KS_F32>::load(sp.dx[i], vh, h, d);
+            const float af = (float)ai;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                d[k].r = fmaf(af, (float)pv[k].r, d[k].r);
+                d[k].i = fmaf(af, (float)pv[k].i, d[k].i);
+            }
+            Spinor<KS_F32>::store(sp.dx[i], vh, h, d);
+        } else {
+            double2* x = sp.x[i];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                double2 t = x[k * vh + h];
+                t.x = fma(ai, (double)pv[k].r, t.x);
+                t.y = fma(ai, (double)pv[k].i, t.y);
+                x[k * vh + h] = t;
+            }
+        }
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            double2 t = x[k * vh + h];
-            t.x = fma(ai, (double)pv[k].r, t.x);
-            t.y = fma(ai, (double)pv[k].i, t.y);
-            x[k * vh + h] = t;
             pv[k].r = fma(bi, pv[k].r, zi * rv[k].r);
             pv[k].i = fma(bi, pv[k].i, zi * rv[k].i);
         }
@@ -183,6 +203,27 @@ __global__ __launch_bounds__(kBlock) void ms_update_kernel(int vh, const void* _
         pv[k].i = fma(b, pv[k].i, rv[k].i);
     }
     Spinor<P>::store(pb, vh, h, pv);
+}
+
+// x_i += dx_i (FP64), dx_i = 0, for every shift
+__global__ __launch_bounds__(kBlock) void ms_flush_kernel(int vh, int nshift, ShiftPtrs sp)
+{
+    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= vh) return;
+    const cx<float> zero[3] = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}};
+    for (int i = 0; i < nshift; ++i) {
+        cx<float> d[3];
+        Spinor<KS_F32>::load(sp.dx[i], vh, h, d);
+        double2* x = sp.x[i];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            double2 t = x[k * vh + h];
+            t.x += (double)d[k].r;
+            t.y += (double)d[k].i;
+            x[k * vh + h] = t;
+        }
+        Spinor<KS_F32>::store(sp.dx[i], vh, h, zero);
+    }
 }
 
 template <int P>
@@ -204,8 +245,10 @@ double multishift_iter_model_bytes(ks_prec_t p, ks_recon_t r, int nactive)
 {
     const double sb = p == KS_F64 ? 48 : p == KS_F32 ? 24 : 16;
     // A-apply (two hopping terms + xpay read), r update (q, r read, r write), fused update
-    // (r, p read, p write; per shift p_i read/write and x_i read/write in FP64)
-    return 2 * dslash_model_bytes(p, r) + sb + 3 * sb + 3 * sb + nactive * (2 * sb + 96);
+    // (r, p read, p write; per shift p_i read/write and x_i read/write: FP64, or its FP32
+    // increments in reduced precision)
+    const double xb = p == KS_F64 ? 96 : 48;
+    return 2 * dslash_model_bytes(p, r) + sb + 3 * sb + 3 * sb + nactive * (2 * sb + xb);
 }
 
 ks_status_t multishift_core(ks_gauge_t g, int nshift, const double* sigma, const double* b,
@@ -241,6 +284,9 @@ ks_status_t multishift_core(ks_gauge_t g, int nshift, const double* sigma, const
         w.ms_prec = (int)P;
     }
     while ((int)w.ms_p.size() < nshift) w.ms_p.push_back(device_alloc(fb));
+    const bool sloppy = P != KS_F64;
+    if (sloppy)
+        while ((int)w.ms_dx.size() < nshift) w.ms_dx.push_back(device_alloc(field_bytes(G, KS_F32)));
     if (!w.ms_st) {
         w.ms_st = device_alloc(sizeof(MSState));
         KS_HIP(hipHostMalloc(&w.ms_st_host, sizeof(MSState)));
@@ -265,7 +311,17 @@ ks_status_t multishift_core(ks_gauge_t g, int nshift, const double* sigma, const
         KS_HIP(hipMemsetAsync(x[i], 0, field_bytes(G, KS_F64), s));
         sp.x[i] = reinterpret_cast<double2*>(x[i]);
         sp.p[i] = w.ms_p[i];
+        if (sloppy) {
+            sp.dx[i] = w.ms_dx[i];
+            KS_HIP(hipMemsetAsync(w.ms_dx[i], 0, field_bytes(G, KS_F32), s));
+        }
     }
+    sp.sloppy = sloppy ? 1 : 0;
+    auto flush = [&]() {
+        if (!sloppy) return;
+        ms_flush_kernel<<<blocks_for(vh), kBlock, 0, s>>>(vh, nshift, sp);
+        KS_HIP(hipGetLastError());
+    };
     const double b2 = norm2_host(g, b, s);
     convert_field(vh, P, w.ms_r, KS_F64, w.r64, nullptr, s);
     const double r2 = norm2_host(g, static_cast<const double*>(w.r64), s);
@@ -337,6 +393,7 @@ ks_status_t multishift_core(ks_gauge_t g, int nshift, const double* sigma, const
         if (hs->ru_pending) {
             // r = b - A_0 x_0 in FP64 for the base (smallest) shift; the shifted systems keep
             // r_i = zeta_i r with the recomputed r
+            flush();
             apply_A64(g, s0, x[i0], w.ax64, s, nullptr);
             sub_norm_partials(vh, b, w.ax64, w.r64, w.partials, s);
             finish_to(w.partials, w.npart, w.scal, s);
@@ -355,6 +412,7 @@ ks_status_t multishift_core(ks_gauge_t g, int nshift, const double* sigma, const
         for (int k = 0; k < chunk; ++k) iteration();
     }
     const int ms_iters = hs->iter;
+    flush();
 
     // FP64 verdict per shift; refine the ones above target from x_i
     std::vector<int> need;

@@ -99,6 +99,7 @@ void workspace_free(Workspace* w)
     }
     for (void* v : w->ms_x) device_free(v);
     for (void* v : w->ms_p) device_free(v);
+    for (void* v : w->ms_dx) device_free(v);
     device_free(w->ms_r);
     device_free(w->ms_pb);
     device_free(w->ms_q);
