@@ -559,7 +559,8 @@ struct BatchLaunch {
     {
         const int nt = c.ntiles[c.tile_idx];
         const int2* tl = c.tiles[c.tile_idx];
-        const int grid = c.grid(nt);
+        const int grid = nt;   // streaming vector kernels: one block per tile (the tuned
+                                // persistent schedule is for the hopping terms)
         const int np = c.npairs;
         const int P = c.prec;
         // inner A-apply
@@ -585,7 +586,8 @@ struct BatchLaunch {
     {
         const int nt = c.ntiles[c.tile_idx];
         const int2* tl = c.tiles[c.tile_idx];
-        const int grid = c.grid(nt);
+        const int grid = nt;   // streaming vector kernels: one block per tile (the tuned
+                                // persistent schedule is for the hopping terms)
         dslash(c, KS_F64, false, true, 1, c.x64, c.t64, nullptr, s);
         dslash(c, KS_F64, true, true, 0, c.t64, c.ax64, c.x64, s);
         batch_resid_kernel<R, NT><<<grid, NT, 0, s>>>(c.lats_dev, tl, nt, c.b64, c.ax64, c.r64, c.pairs, c.partials);
@@ -600,7 +602,8 @@ struct BatchLaunch {
     {
         const int nt = c.ntiles[c.tile_idx];
         const int2* tl = c.tiles[c.tile_idx];
-        const int grid = c.grid(nt);
+        const int grid = nt;   // streaming vector kernels: one block per tile (the tuned
+                                // persistent schedule is for the hopping terms)
         reliable(c, 1, s);
         if (c.prec == KS_F64)
             batch_xpay_kernel<KS_F64, R, NT><<<grid, NT, 0, s>>>(c.lats_dev, tl, nt, c.rs, c.ps, c.pairs, 1);
