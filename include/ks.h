@@ -27,6 +27,9 @@
  * the library's internal layout; free them with the matching *_free call.
  * Streams: all device work is queued on the caller's stream.  ks_dslash_eo and ks_apply_A
  * return without waiting; the solvers wait for their stream before returning.
+ * Concurrency: calls on one gauge handle (or one batch or network handle) must not overlap in
+ * time, from several host threads or on several streams: they share the handle's solver
+ * workspace.  Different handles are independent.
  * Errors: every call returns a ks_status_t and never aborts; ks_last_error() gives a message
  * for the calling thread's last failure.
  */
@@ -52,7 +55,7 @@ typedef enum {
     KS_SUCCESS = 0,
     KS_ERR_ARG = -1,            /* invalid argument (dims, null pointer, parity, aliasing) */
     KS_ERR_HIP = -2,            /* a HIP runtime call failed */
-    KS_ERR_NOMEM = -3,          /* device allocation failed */
+    KS_ERR_NOMEM = -3,          /* device (or host) allocation failed */
     KS_ERR_NOT_SU3 = -4,        /* 12-real storage asked for links that are not c * SU(3) */
     KS_ERR_NOT_CONVERGED = -5,  /* max_iter reached; x holds the last iterate, stats filled */
     KS_ERR_BREAKDOWN = -6,      /* <p, A p> <= 0 */
