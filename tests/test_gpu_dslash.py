@@ -98,6 +98,11 @@ def test_dslash_f16(ks, dims, recon):
         if recon == 18:
             refq = oracle.dslash_eo(q, out_par, oracle.quantise_f16_sites(psi))
             assert rel_l2(got, refq) <= 2e-3
+            # per component: the stored output is binary16 relative to its site maximum n, so
+            # it is within 2 ulps (2 * 2^-10 * n) of the exact result on the same inputs
+            n = np.max(np.abs(np.stack([refq.real, refq.imag], -1).reshape(vh, 6)), axis=1)
+            assert np.all(np.abs(got.real - refq.real) <= 2 * 2.0 ** -10 * n[:, None])
+            assert np.all(np.abs(got.imag - refq.imag) <= 2 * 2.0 ** -10 * n[:, None])
         assert rel_l2(got, ref) <= 5e-3
 
 

@@ -116,6 +116,21 @@ def test_cg_ragged_lattices(ks, dims):
         assert res.ok and true_rel(g, 0.01, b, x) <= 1e-10
 
 
+@pytest.mark.parametrize("inner", ["f64", "f32"])
+def test_cg_16_agrees_with_oracle_solution(ks, inner):
+    """16^4, m = 0.01: the solution agrees with the oracle's own CG solution within
+    2 tol kappa (kappa from the oracle's Lanczos estimate)."""
+    announce("cg 16^4 vs oracle solution", inner)
+    g = make_gauge((16, 16, 16, 16), 0.5, 51)
+    G = ks.Gauge(g.dims, g.fat, g.naik)
+    b = gaussian_source(g.volume // 2, 52)
+    xo, info = oracle.cg(g, 4 * 0.01 ** 2, b, 1e-12)
+    lo, hi = oracle.lanczos_extremes(info.alpha, info.beta)
+    x, res = solve(ks, G, 0.01, b, tol=1e-10, inner=inner)
+    assert res.ok and true_rel(g, 4e-4, b, x) <= 1e-10
+    assert rel_l2(x, xo) <= 2 * (1e-10 + 1e-12) * hi / lo
+
+
 @pytest.mark.parametrize("inner", ["f64", "f32", "f16"])
 def test_multishift(ks, cfg1, inner):
     announce("multishift 8^4", inner)
