@@ -37,9 +37,9 @@ struct MSState {
 
 struct ShiftPtrs {
     double2* x[kMaxShift];
-    void* p[kMaxShift];
+    void* p[kMaxShift];    // p[base] is the base direction
     void* dx[kMaxShift];   // FP32 increments of x_i since the last flush (reduced precision)
-    int sloppy;            // 1: the shared phase adds alpha_i p_i to dx_i instead of x_i
+    int base;              // index of the smallest shift, whose system is the base system
 };
 
 __device__ __forceinline__ double finish_sum(const double* in, int n)
@@ -147,62 +147,73 @@ __global__ __launch_bounds__(kFinish) void ms_beta_kernel(const double* __restri
 }
 
 // x_i += alpha_i p_i; p_i = zeta_i r + beta_i p_i for every shift updated this step, and the
-// base direction p = r + beta p.  r is read once per site for all shifts.  In reduced
-// precision the x_i increments go to FP32 fields that are added into the FP64 x_i at every
-// reliable update of the base and at the end (half the bytes of an FP64 read-modify-write).
+// base direction p = r + beta p.  r and p are read once per site for all shifts.  The base
+// shift (delta = 0) keeps zeta = 1, alpha_i = alpha and beta_i = beta exactly, so its p_i is
+// the base p itself: it is neither loaded nor stored separately.  Loads of a group of shifts
+// are issued before any of the group's stores, so that a wave has several in flight.  In
+// reduced precision the x_i increments go to FP32 fields that are added into the FP64 x_i at
+// every reliable update of the base and at the end (half the bytes of an FP64
+// read-modify-write).
 template <int P>
 __global__ __launch_bounds__(kBlock) void ms_update_kernel(int vh, const void* __restrict__ r,
                                                            void* __restrict__ pb, ShiftPtrs sp,
                                                            const MSState* __restrict__ st)
 {
     using R = typename St<P>::R;
+    constexpr bool kSloppy = P != KS_F64;
+    constexpr int kX = kSloppy ? KS_F32 : KS_F64;
+    using XR = typename St<kX>::R;
+    constexpr int G = kSloppy ? 4 : 3;
     if (st->gate) return;
     const int h = blockIdx.x * blockDim.x + threadIdx.x;
     if (h >= vh) return;
-    cx<R> rv[3], pv[3];
+    cx<R> rv[3], bv[3];
     Spinor<P>::load(r, vh, h, rv);
+    Spinor<P>::load(pb, vh, h, bv);
     const int ns = st->nshift;
-    for (int i = 0; i < ns; ++i) {
-        if (!st->upd[i]) continue;
-        const double ai = st->alpha_i[i];
-        const R bi = (R)st->beta_i[i], zi = (R)st->zeta[i];
-        Spinor<P>::load(sp.p[i], vh, h, pv);
-        if (sp.sloppy) {
-            // x_i's increments accumulate in FP32 between flushes into the FP64 x_i
-            cx<float> d[3];
-            Spinor<KS_F32>::load(sp.dx[i], vh, h, d);
-            const float af = (float)ai;
+    for (int i0 = 0; i0 < ns; i0 += G) {
+        cx<R> pv[G][3];
+        cx<XR> xv[G][3];
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                d[k].r = fmaf(af, (float)pv[k].r, d[k].r);
-                d[k].i = fmaf(af, (float)pv[k].i, d[k].i);
-            }
-            Spinor<KS_F32>::store(sp.dx[i], vh, h, d);
-        } else {
-            double2* x = sp.x[i];
+        for (int j = 0; j < G; ++j) {
+            const int i = i0 + j;
+            if (i >= ns || !st->upd[i]) continue;
+            if (i == sp.base) {
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                double2 t = x[k * vh + h];
-                t.x = fma(ai, (double)pv[k].r, t.x);
-                t.y = fma(ai, (double)pv[k].i, t.y);
-                x[k * vh + h] = t;
+                for (int k = 0; k < 3; ++k) pv[j][k] = bv[k];
+            } else {
+                Spinor<P>::load(sp.p[i], vh, h, pv[j]);
             }
+            Spinor<kX>::load(kSloppy ? sp.dx[i] : sp.x[i], vh, h, xv[j]);
         }
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            pv[k].r = fma(bi, pv[k].r, zi * rv[k].r);
-            pv[k].i = fma(bi, pv[k].i, zi * rv[k].i);
+        for (int j = 0; j < G; ++j) {
+            const int i = i0 + j;
+            if (i >= ns || !st->upd[i]) continue;
+            const XR ai = (XR)st->alpha_i[i];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                xv[j][k].r = fma(ai, (XR)pv[j][k].r, xv[j][k].r);
+                xv[j][k].i = fma(ai, (XR)pv[j][k].i, xv[j][k].i);
+            }
+            Spinor<kX>::store(kSloppy ? sp.dx[i] : sp.x[i], vh, h, xv[j]);
+            if (i == sp.base) continue;
+            const R bi = (R)st->beta_i[i], zi = (R)st->zeta[i];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                pv[j][k].r = fma(bi, pv[j][k].r, zi * rv[k].r);
+                pv[j][k].i = fma(bi, pv[j][k].i, zi * rv[k].i);
+            }
+            Spinor<P>::store(sp.p[i], vh, h, pv[j]);
         }
-        Spinor<P>::store(sp.p[i], vh, h, pv);
     }
     const R b = (R)st->beta;
-    Spinor<P>::load(pb, vh, h, pv);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        pv[k].r = fma(b, pv[k].r, rv[k].r);
-        pv[k].i = fma(b, pv[k].i, rv[k].i);
+        bv[k].r = fma(b, bv[k].r, rv[k].r);
+        bv[k].i = fma(b, bv[k].i, rv[k].i);
     }
-    Spinor<P>::store(pb, vh, h, pv);
+    Spinor<P>::store(pb, vh, h, bv);
 }
 
 // x_i += dx_i (FP64), dx_i = 0, for every shift
@@ -241,14 +252,15 @@ void launch_upd(int vh, const void* r, void* pb, const ShiftPtrs& sp, const MSSt
 
 }  // namespace
 
-double multishift_iter_model_bytes(ks_prec_t p, ks_recon_t r, int nactive)
+double multishift_iter_model_bytes(ks_prec_t p, ks_recon_t r, int nactive, bool base_active)
 {
     const double sb = p == KS_F64 ? 48 : p == KS_F32 ? 24 : 16;
     // A-apply (two hopping terms + xpay read), r update (q, r read, r write), fused update
     // (r, p read, p write; per shift p_i read/write and x_i read/write: FP64, or its FP32
-    // increments in reduced precision)
+    // increments in reduced precision; the base shift's p_i is p)
     const double xb = p == KS_F64 ? 96 : 48;
-    return 2 * dslash_model_bytes(p, r) + sb + 3 * sb + 3 * sb + nactive * (2 * sb + xb);
+    const int np = nactive - (base_active ? 1 : 0);
+    return 2 * dslash_model_bytes(p, r) + sb + 3 * sb + 3 * sb + nactive * xb + np * 2 * sb;
 }
 
 ks_status_t multishift_core(ks_gauge_t g, int nshift, const double* sigma, const double* b,
@@ -306,17 +318,17 @@ ks_status_t multishift_core(ks_gauge_t g, int nshift, const double* sigma, const
     convert_field(vh, KS_F64, b, P, w.ms_r, nullptr, s);
     convert_field(vh, KS_F64, b, P, w.ms_pb, nullptr, s);
     ShiftPtrs sp{};
+    sp.base = i0;
     for (int i = 0; i < nshift; ++i) {
-        convert_field(vh, KS_F64, b, P, w.ms_p[i], nullptr, s);
+        if (i != i0) convert_field(vh, KS_F64, b, P, w.ms_p[i], nullptr, s);
         KS_HIP(hipMemsetAsync(x[i], 0, field_bytes(G, KS_F64), s));
         sp.x[i] = reinterpret_cast<double2*>(x[i]);
-        sp.p[i] = w.ms_p[i];
+        sp.p[i] = i == i0 ? w.ms_pb : w.ms_p[i];
         if (sloppy) {
             sp.dx[i] = w.ms_dx[i];
             KS_HIP(hipMemsetAsync(w.ms_dx[i], 0, field_bytes(G, KS_F32), s));
         }
     }
-    sp.sloppy = sloppy ? 1 : 0;
     auto flush = [&]() {
         if (!sloppy) return;
         ms_flush_kernel<<<blocks_for(vh), kBlock, 0, s>>>(vh, nshift, sp);
@@ -381,7 +393,7 @@ ks_status_t multishift_core(ks_gauge_t g, int nshift, const double* sigma, const
     for (;;) {
         KS_HIP(hipMemcpyAsync(hs, st, sizeof(MSState), hipMemcpyDeviceToHost, s));
         KS_HIP(hipStreamSynchronize(s));
-        model_bytes += (hs->iter - last_iter) * multishift_iter_model_bytes(P, RC, hs->nactive) * vh;
+        model_bytes += (hs->iter - last_iter) * multishift_iter_model_bytes(P, RC, hs->nactive, hs->active[i0] != 0) * vh;
         last_iter = hs->iter;
         if (hs->status != 0) {
             result = static_cast<ks_status_t>(hs->status);
