@@ -113,9 +113,11 @@ __global__ __launch_bounds__(kBlock) void sub_norm_kernel(int vh, const double2*
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
-// x (FP64) += alpha p; r -= alpha q (precision P); partial sums of |r|^2 as stored
+// x (FP64) += alpha p, or in reduced precision x's FP32 increment dx += alpha p (added into
+// the FP64 x at every reliable update); r -= alpha q (precision P); partial sums of |r|^2 as
+// stored
 template <int P>
-__global__ __launch_bounds__(kBlock) void update_xr_kernel(int vh, double2* __restrict__ x,
+__global__ __launch_bounds__(kBlock) void update_xr_kernel(int vh, void* __restrict__ x,
                                                            const void* __restrict__ p,
                                                            const void* __restrict__ q,
                                                            void* __restrict__ r,
@@ -123,22 +125,26 @@ __global__ __launch_bounds__(kBlock) void update_xr_kernel(int vh, double2* __re
                                                            double* __restrict__ partials)
 {
     using R = typename St<P>::R;
+    constexpr int kX = P == KS_F64 ? KS_F64 : KS_F32;
+    using XR = typename St<kX>::R;
     if (st->gate) return;
     const double alpha = st->alpha;
     const int h = blockIdx.x * blockDim.x + threadIdx.x;
     double s = 0.0;
     if (h < vh) {
         cx<R> pv[3], qv[3], rv[3];
+        cx<XR> xv[3];
         Spinor<P>::load(p, vh, h, pv);
         Spinor<P>::load(q, vh, h, qv);
         Spinor<P>::load(r, vh, h, rv);
+        Spinor<kX>::load(x, vh, h, xv);
+        const XR ax = (XR)alpha;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            double2 t = x[k * vh + h];
-            t.x = fma(alpha, (double)pv[k].r, t.x);
-            t.y = fma(alpha, (double)pv[k].i, t.y);
-            x[k * vh + h] = t;
+            xv[k].r = fma(ax, (XR)pv[k].r, xv[k].r);
+            xv[k].i = fma(ax, (XR)pv[k].i, xv[k].i);
         }
+        Spinor<kX>::store(x, vh, h, xv);
         const R a = (R)alpha;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
@@ -153,6 +159,25 @@ __global__ __launch_bounds__(kBlock) void update_xr_kernel(int vh, double2* __re
     }
     s = block_sum<kBlock>(s);
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// x (FP64 planes) += dx (FP32 field), dx = 0
+__global__ __launch_bounds__(kBlock) void flush_dx_kernel(int vh, void* __restrict__ dx,
+                                                          double2* __restrict__ x)
+{
+    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= vh) return;
+    cx<float> d[3];
+    Spinor<KS_F32>::load(dx, vh, h, d);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double2 t = x[k * vh + h];
+        t.x += (double)d[k].r;
+        t.y += (double)d[k].i;
+        x[k * vh + h] = t;
+    }
+    const cx<float> zero[3] = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}};
+    Spinor<KS_F32>::store(dx, vh, h, zero);
 }
 
 // p = r + beta p
@@ -330,14 +355,19 @@ void sub_norm_partials(int vh, const double* b, const double* ax, double* r, dou
     KS_HIP(hipGetLastError());
 }
 
-void update_xr(int vh, ks_prec_t prec, double* x, const void* p, const void* q, void* r,
+void update_xr(int vh, ks_prec_t prec, void* x, const void* p, const void* q, void* r,
                const CGState* st, double* partials, hipStream_t s)
 {
     const int nb = blocks_for(vh);
-    double2* xp = reinterpret_cast<double2*>(x);
-    if (prec == KS_F64) update_xr_kernel<KS_F64><<<nb, kBlock, 0, s>>>(vh, xp, p, q, r, st, partials);
-    else if (prec == KS_F32) update_xr_kernel<KS_F32><<<nb, kBlock, 0, s>>>(vh, xp, p, q, r, st, partials);
-    else update_xr_kernel<KS_F16><<<nb, kBlock, 0, s>>>(vh, xp, p, q, r, st, partials);
+    if (prec == KS_F64) update_xr_kernel<KS_F64><<<nb, kBlock, 0, s>>>(vh, x, p, q, r, st, partials);
+    else if (prec == KS_F32) update_xr_kernel<KS_F32><<<nb, kBlock, 0, s>>>(vh, x, p, q, r, st, partials);
+    else update_xr_kernel<KS_F16><<<nb, kBlock, 0, s>>>(vh, x, p, q, r, st, partials);
+    KS_HIP(hipGetLastError());
+}
+
+void flush_dx(int vh, void* dx, double* x, hipStream_t s)
+{
+    flush_dx_kernel<<<blocks_for(vh), kBlock, 0, s>>>(vh, dx, reinterpret_cast<double2*>(x));
     KS_HIP(hipGetLastError());
 }
 

@@ -29,8 +29,11 @@ void convert_field(int vh, ks_prec_t pin, const void* in, ks_prec_t pout, void* 
 void norm2_partials(int vh, const double* v, double* partials, hipStream_t s);
 void sub_norm_partials(int vh, const double* b, const double* ax, double* r, double* partials,
                        hipStream_t s);
-void update_xr(int vh, ks_prec_t prec, double* x, const void* p, const void* q, void* r,
+// x: FP64 planes when prec is KS_F64, else the FP32 increment field of x (see flush_dx)
+void update_xr(int vh, ks_prec_t prec, void* x, const void* p, const void* q, void* r,
                const CGState* st, double* partials, hipStream_t s);
+// x (FP64 planes) += dx (FP32 field); dx = 0
+void flush_dx(int vh, void* dx, double* x, hipStream_t s);
 void xpay(int vh, ks_prec_t prec, const void* r, void* p, const CGState* st, hipStream_t s);
 void cg_alpha(const double* part, int n, CGState* st, hipStream_t s);
 void cg_beta(const double* part, int n, CGState* st, hipStream_t s);

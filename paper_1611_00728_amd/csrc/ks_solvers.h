@@ -27,6 +27,7 @@ struct Workspace {
     void* ps[3] = {nullptr, nullptr, nullptr};
     void* qs[3] = {nullptr, nullptr, nullptr};
     void* ts[3] = {nullptr, nullptr, nullptr};
+    void* dx32 = nullptr;         // FP32 increments of x between reliable updates (reduced precision)
     // multi-shift
     std::vector<void*> ms_x;      // FP64 solutions
     std::vector<void*> ms_p;      // shifted directions, inner precision

@@ -41,9 +41,10 @@ double dslash_model_bytes(ks_prec_t p, ks_recon_t r)
 
 double cg_iter_model_bytes(ks_prec_t p, ks_recon_t r)
 {
-    // two hopping terms, the xpay read of p, x (FP64) read+write, r/p/q reads and the r
-    // write of the update, r/p reads and the p write of p = r + beta p
-    return 2 * dslash_model_bytes(p, r) + 8 * (double)spinor_bytes(p) + 96;
+    // two hopping terms, the xpay read of p, x read+write (FP64, or its FP32 increment in
+    // reduced precision), r/p/q reads and the r write of the update, r/p reads and the p
+    // write of p = r + beta p
+    return 2 * dslash_model_bytes(p, r) + 8 * (double)spinor_bytes(p) + (p == KS_F64 ? 96 : 48);
 }
 
 Workspace& workspace(ks_gauge_t g)
@@ -77,6 +78,7 @@ static void sloppy_vectors(ks_gauge_t g, Workspace& w, ks_prec_t p)
     ws_vec(w, w.ps[p], b);
     ws_vec(w, w.qs[p], b);
     ws_vec(w, w.ts[p], b);
+    if (p != KS_F64) ws_vec(w, w.dx32, field_bytes(g->geom, KS_F32));
 }
 
 void workspace_free(Workspace* w)
@@ -97,6 +99,7 @@ void workspace_free(Workspace* w)
         device_free(w->qs[p]);
         device_free(w->ts[p]);
     }
+    device_free(w->dx32);
     for (void* v : w->ms_x) device_free(v);
     for (void* v : w->ms_p) device_free(v);
     for (void* v : w->ms_dx) device_free(v);
@@ -201,7 +204,16 @@ ks_status_t cg_core(ks_gauge_t g, double sigma, const double* b, double* x,
     *w.st_host = init;
     KS_HIP(hipMemcpyAsync(w.st, w.st_host, sizeof(CGState), hipMemcpyHostToDevice, s));
 
+    // reduced precision: x's increments accumulate in FP32 and are added into the FP64 x
+    // before every reliable update and at the end
+    const bool sloppy = P != KS_F64;
+    if (sloppy) KS_HIP(hipMemsetAsync(w.dx32, 0, field_bytes(G, KS_F32), s));
+    void* xu = sloppy ? w.dx32 : static_cast<void*>(x);
+    auto flush = [&]() {
+        if (sloppy) flush_dx(vh, w.dx32, x, s);
+    };
     auto reliable = [&](int initial) {
+        flush();
         apply_A64(g, sigma, x, w.ax64, s, nullptr);
         sub_norm_partials(vh, b, w.ax64, w.r64, w.partials, s);
         cg_reliable(w.partials, w.npart, w.st, initial, s);
@@ -224,7 +236,7 @@ ks_status_t cg_core(ks_gauge_t g, double sigma, const double* b, double* x,
         a2.gate = &w.st->gate;
         dslash(g, P, RC, a2, s);
         cg_alpha(w.partials, dslash_blocks(g, P, RC), w.st, s);
-        update_xr(vh, P, x, ps, qs, rs, w.st, w.partials, s);
+        update_xr(vh, P, xu, ps, qs, rs, w.st, w.partials, s);
         cg_beta(w.partials, w.npart, w.st, s);
         xpay(vh, P, rs, ps, w.st, s);
     };
@@ -275,6 +287,7 @@ ks_status_t cg_core(ks_gauge_t g, double sigma, const double* b, double* x,
         }
         for (int k = 0; k < chunk; ++k) iteration();
     }
+    flush();   // x = the last iterate also when the loop ended on an error
     read_state(w, s);
     const CGState& h = *w.st_host;
     stats.iters = h.iter;
