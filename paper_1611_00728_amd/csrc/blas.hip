@@ -113,54 +113,6 @@ __global__ __launch_bounds__(kBlock) void sub_norm_kernel(int vh, const double2*
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
-// x (FP64) += alpha p, or in reduced precision x's FP32 increment dx += alpha p (added into
-// the FP64 x at every reliable update); r -= alpha q (precision P); partial sums of |r|^2 as
-// stored
-template <int P>
-__global__ __launch_bounds__(kBlock) void update_xr_kernel(int vh, void* __restrict__ x,
-                                                           const void* __restrict__ p,
-                                                           const void* __restrict__ q,
-                                                           void* __restrict__ r,
-                                                           const CGState* __restrict__ st,
-                                                           double* __restrict__ partials)
-{
-    using R = typename St<P>::R;
-    constexpr int kX = P == KS_F64 ? KS_F64 : KS_F32;
-    using XR = typename St<kX>::R;
-    if (st->gate) return;
-    const double alpha = st->alpha;
-    const int h = blockIdx.x * blockDim.x + threadIdx.x;
-    double s = 0.0;
-    if (h < vh) {
-        cx<R> pv[3], qv[3], rv[3];
-        cx<XR> xv[3];
-        Spinor<P>::load(p, vh, h, pv);
-        Spinor<P>::load(q, vh, h, qv);
-        Spinor<P>::load(r, vh, h, rv);
-        Spinor<kX>::load(x, vh, h, xv);
-        const XR ax = (XR)alpha;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            xv[k].r = fma(ax, (XR)pv[k].r, xv[k].r);
-            xv[k].i = fma(ax, (XR)pv[k].i, xv[k].i);
-        }
-        Spinor<kX>::store(x, vh, h, xv);
-        const R a = (R)alpha;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            rv[k].r = fma(-a, qv[k].r, rv[k].r);
-            rv[k].i = fma(-a, qv[k].i, rv[k].i);
-        }
-        Spinor<P>::store(r, vh, h, rv);
-        Spinor<P>::round(rv);
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-            s += (double)rv[k].r * (double)rv[k].r + (double)rv[k].i * (double)rv[k].i;
-    }
-    s = block_sum<kBlock>(s);
-    if (threadIdx.x == 0) partials[blockIdx.x] = s;
-}
-
 // x (FP64 planes) += dx (FP32 field), dx = 0
 __global__ __launch_bounds__(kBlock) void flush_dx_kernel(int vh, void* __restrict__ dx,
                                                           double2* __restrict__ x)
@@ -202,6 +154,152 @@ __global__ __launch_bounds__(kBlock) void xpay_kernel(int vh, const void* __rest
     Spinor<P>::store(p, vh, h, pv);
 }
 
+// ---------------------------------------------------------------- fused CG step
+
+// Every block reduces the previous kernel's partial sums itself: thread t adds partials t,
+// t + kCgFuse, ... then the fixed block tree, so all blocks hold the same value bit for bit.
+__device__ __forceinline__ double fused_sum(const double* __restrict__ in, int n)
+{
+    __shared__ double total;
+    double t = 0.0;
+    for (int k = threadIdx.x; k < n; k += kCgFuse) t += in[k];
+    t = block_sum<kCgFuse>(t);
+    if (threadIdx.x == 0) total = t;
+    __syncthreads();
+    return total;
+}
+
+template <int P>
+__global__ __launch_bounds__(kCgFuse) void cg_update_kernel(int vh, void* __restrict__ x,
+                                                            const void* __restrict__ p,
+                                                            const void* __restrict__ q,
+                                                            void* __restrict__ r,
+                                                            CGState* __restrict__ st,
+                                                            const double* __restrict__ pap_part,
+                                                            int npap, double* __restrict__ rr_part)
+{
+    using R = typename St<P>::R;
+    constexpr int kX = P == KS_F64 ? KS_F64 : KS_F32;
+    using XR = typename St<kX>::R;
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    // one read of the gate per block: only this kernel's lead thread can change it (to 1,
+    // on breakdown), and a block that sees that skips the step as the breakdown test would
+    __shared__ int gated;
+    if (threadIdx.x == 0) gated = st->gate;
+    __syncthreads();
+    if (gated) {
+        if (lead) st->s_gate = 1;
+        return;
+    }
+    const double pap = fused_sum(pap_part, npap);
+    const double rho = st->rho;
+    const bool ok = isfinite(pap) && pap > 0.0;
+    if (lead) {
+        st->pAp = pap;
+        st->s_rho = rho;
+        st->s_maxr = st->maxr;
+        st->s_iter = st->iter;
+        st->s_gate = ok ? 0 : 1;
+        if (ok) {
+            st->alpha = rho / pap;
+        } else {
+            st->status = isfinite(pap) ? KS_ERR_BREAKDOWN : KS_ERR_NONFINITE;
+            st->gate = 1;
+        }
+    }
+    if (!ok) return;
+    const double alpha = rho / pap;
+    const int h = blockIdx.x * kCgFuse + threadIdx.x;
+    double s = 0.0;
+    if (h < vh) {
+        cx<R> pv[3], qv[3], rv[3];
+        cx<XR> xv[3];
+        Spinor<P>::load(p, vh, h, pv);
+        Spinor<P>::load(q, vh, h, qv);
+        Spinor<P>::load(r, vh, h, rv);
+        Spinor<kX>::load(x, vh, h, xv);
+        const XR ax = (XR)alpha;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            xv[k].r = fma(ax, (XR)pv[k].r, xv[k].r);
+            xv[k].i = fma(ax, (XR)pv[k].i, xv[k].i);
+        }
+        Spinor<kX>::store(x, vh, h, xv);
+        const R a = (R)alpha;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            rv[k].r = fma(-a, qv[k].r, rv[k].r);
+            rv[k].i = fma(-a, qv[k].i, rv[k].i);
+        }
+        Spinor<P>::store(r, vh, h, rv);
+        Spinor<P>::round(rv);
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            s += (double)rv[k].r * (double)rv[k].r + (double)rv[k].i * (double)rv[k].i;
+    }
+    s = block_sum<kCgFuse>(s);
+    if (threadIdx.x == 0) rr_part[blockIdx.x] = s;
+}
+
+// Decides from the copies the update kernel took (s_*) and from fields no block writes here
+// (stop2, delta, max_iter), so every block takes the same branch; the lead thread alone
+// writes the live state.
+template <int P>
+__global__ __launch_bounds__(kCgFuse) void cg_beta_xpay_kernel(int vh, const void* __restrict__ r,
+                                                               void* __restrict__ p,
+                                                               CGState* __restrict__ st,
+                                                               const double* __restrict__ rr_part,
+                                                               int nrr)
+{
+    using R = typename St<P>::R;
+    if (st->s_gate) return;
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    const double rho_new = fused_sum(rr_part, nrr);
+    const int iter = st->s_iter + 1;
+    const double maxr = st->s_maxr;
+    if (lead) {
+        st->iter = iter;
+        st->rho_new = rho_new;
+    }
+    if (!isfinite(rho_new)) {
+        if (lead) {
+            st->status = KS_ERR_NONFINITE;
+            st->gate = 1;
+        }
+        return;
+    }
+    const double rn = sqrt(rho_new);
+    if (rho_new <= st->stop2 || rn < st->delta * maxr) {
+        // FP64 recomputation of r = b - A x decides (reliable update or final check)
+        if (lead) {
+            st->ru_pending = 1;
+            st->gate = 1;
+        }
+        return;
+    }
+    const double beta = rho_new / st->s_rho;
+    const bool last = iter >= st->max_iter;
+    if (lead) {
+        st->beta = beta;
+        st->rho = rho_new;
+        st->maxr = fmax(maxr, rn);
+        if (last) st->gate = 1;
+    }
+    if (last) return;
+    const int h = blockIdx.x * kCgFuse + threadIdx.x;
+    if (h >= vh) return;
+    const R b = (R)beta;
+    cx<R> rv[3], pv[3];
+    Spinor<P>::load(r, vh, h, rv);
+    Spinor<P>::load(p, vh, h, pv);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        pv[k].r = fma(b, pv[k].r, rv[k].r);
+        pv[k].i = fma(b, pv[k].i, rv[k].i);
+    }
+    Spinor<P>::store(p, vh, h, pv);
+}
+
 // ---------------------------------------------------------------- CG scalar steps
 
 __device__ __forceinline__ double finish_sum(const double* in, int n)
@@ -209,50 +307,6 @@ __device__ __forceinline__ double finish_sum(const double* in, int n)
     double s = 0.0;
     for (int k = threadIdx.x; k < n; k += kFinish) s += in[k];
     return block_sum<kFinish>(s);
-}
-
-__global__ __launch_bounds__(kFinish) void cg_alpha_kernel(const double* __restrict__ part, int n,
-                                                           CGState* __restrict__ st)
-{
-    if (st->gate) return;
-    const double pap = finish_sum(part, n);
-    if (threadIdx.x != 0) return;
-    st->pAp = pap;
-    if (!isfinite(pap)) {
-        st->status = KS_ERR_NONFINITE;
-        st->gate = 1;
-    } else if (!(pap > 0.0)) {
-        st->status = KS_ERR_BREAKDOWN;
-        st->gate = 1;
-    } else {
-        st->alpha = st->rho / pap;
-    }
-}
-
-__global__ __launch_bounds__(kFinish) void cg_beta_kernel(const double* __restrict__ part, int n,
-                                                          CGState* __restrict__ st)
-{
-    if (st->gate) return;
-    const double rho_new = finish_sum(part, n);
-    if (threadIdx.x != 0) return;
-    st->iter += 1;
-    st->rho_new = rho_new;
-    if (!isfinite(rho_new)) {
-        st->status = KS_ERR_NONFINITE;
-        st->gate = 1;
-        return;
-    }
-    const double rn = sqrt(rho_new);
-    if (rho_new <= st->stop2 || rn < st->delta * st->maxr) {
-        // FP64 recomputation of r = b - A x decides (reliable update or final check)
-        st->ru_pending = 1;
-        st->gate = 1;
-        return;
-    }
-    st->beta = rho_new / st->rho;
-    st->rho = rho_new;
-    st->maxr = fmax(st->maxr, rn);
-    if (st->iter >= st->max_iter) st->gate = 1;
 }
 
 // After r = b - A x in FP64: either converged, or continue with beta = |r|^2 / rho.
@@ -355,13 +409,26 @@ void sub_norm_partials(int vh, const double* b, const double* ax, double* r, dou
     KS_HIP(hipGetLastError());
 }
 
-void update_xr(int vh, ks_prec_t prec, void* x, const void* p, const void* q, void* r,
-               const CGState* st, double* partials, hipStream_t s)
+void cg_update(int vh, ks_prec_t prec, void* x, const void* p, const void* q, void* r,
+               CGState* st, const double* pap_part, int npap, double* rr_part, hipStream_t s)
 {
-    const int nb = blocks_for(vh);
-    if (prec == KS_F64) update_xr_kernel<KS_F64><<<nb, kBlock, 0, s>>>(vh, x, p, q, r, st, partials);
-    else if (prec == KS_F32) update_xr_kernel<KS_F32><<<nb, kBlock, 0, s>>>(vh, x, p, q, r, st, partials);
-    else update_xr_kernel<KS_F16><<<nb, kBlock, 0, s>>>(vh, x, p, q, r, st, partials);
+    const int nb = blocks_for(vh, kCgFuse);
+    if (prec == KS_F64)
+        cg_update_kernel<KS_F64><<<nb, kCgFuse, 0, s>>>(vh, x, p, q, r, st, pap_part, npap, rr_part);
+    else if (prec == KS_F32)
+        cg_update_kernel<KS_F32><<<nb, kCgFuse, 0, s>>>(vh, x, p, q, r, st, pap_part, npap, rr_part);
+    else
+        cg_update_kernel<KS_F16><<<nb, kCgFuse, 0, s>>>(vh, x, p, q, r, st, pap_part, npap, rr_part);
+    KS_HIP(hipGetLastError());
+}
+
+void cg_beta_xpay(int vh, ks_prec_t prec, const void* r, void* p, CGState* st,
+                  const double* rr_part, hipStream_t s)
+{
+    const int nb = blocks_for(vh, kCgFuse);
+    if (prec == KS_F64) cg_beta_xpay_kernel<KS_F64><<<nb, kCgFuse, 0, s>>>(vh, r, p, st, rr_part, nb);
+    else if (prec == KS_F32) cg_beta_xpay_kernel<KS_F32><<<nb, kCgFuse, 0, s>>>(vh, r, p, st, rr_part, nb);
+    else cg_beta_xpay_kernel<KS_F16><<<nb, kCgFuse, 0, s>>>(vh, r, p, st, rr_part, nb);
     KS_HIP(hipGetLastError());
 }
 
@@ -377,18 +444,6 @@ void xpay(int vh, ks_prec_t prec, const void* r, void* p, const CGState* st, hip
     if (prec == KS_F64) xpay_kernel<KS_F64><<<nb, kBlock, 0, s>>>(vh, r, p, st);
     else if (prec == KS_F32) xpay_kernel<KS_F32><<<nb, kBlock, 0, s>>>(vh, r, p, st);
     else xpay_kernel<KS_F16><<<nb, kBlock, 0, s>>>(vh, r, p, st);
-    KS_HIP(hipGetLastError());
-}
-
-void cg_alpha(const double* part, int n, CGState* st, hipStream_t s)
-{
-    cg_alpha_kernel<<<1, kFinish, 0, s>>>(part, n, st);
-    KS_HIP(hipGetLastError());
-}
-
-void cg_beta(const double* part, int n, CGState* st, hipStream_t s)
-{
-    cg_beta_kernel<<<1, kFinish, 0, s>>>(part, n, st);
     KS_HIP(hipGetLastError());
 }
 

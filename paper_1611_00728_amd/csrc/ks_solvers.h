@@ -12,6 +12,7 @@ struct Workspace {
     size_t bytes = 0;
     int npart = 0;
     double* partials = nullptr;   // per-block partial sums
+    double* rr_part = nullptr;    // |r|^2 partials of the fused CG step (blocks_for(Vh, kCgFuse))
     double* scal = nullptr;       // device scalars (after the partials)
     double* host_scal = nullptr;  // pinned
     CGState* st = nullptr;

@@ -58,6 +58,9 @@ Workspace& workspace(ks_gauge_t g)
         w.partials = static_cast<double*>(device_alloc(sizeof(double) * (cap + 64)));
         w.scal = w.partials + cap;
         w.bytes += sizeof(double) * (cap + 64);
+        const int nrr = blocks_for(vh, kCgFuse);
+        w.rr_part = static_cast<double*>(device_alloc(sizeof(double) * nrr));
+        w.bytes += sizeof(double) * nrr;
         w.st = static_cast<CGState*>(device_alloc(sizeof(CGState)));
         KS_HIP(hipHostMalloc(reinterpret_cast<void**>(&w.st_host), sizeof(CGState)));
         KS_HIP(hipHostMalloc(reinterpret_cast<void**>(&w.host_scal), sizeof(double) * 64));
@@ -85,6 +88,7 @@ void workspace_free(Workspace* w)
 {
     if (!w) return;
     device_free(w->partials);
+    device_free(w->rr_part);
     device_free(w->st);
     if (w->st_host) (void)hipHostFree(w->st_host);
     if (w->host_scal) (void)hipHostFree(w->host_scal);
@@ -235,10 +239,8 @@ ks_status_t cg_core(ks_gauge_t g, double sigma, const double* b, double* x,
         a2.dot_partials = w.partials;
         a2.gate = &w.st->gate;
         dslash(g, P, RC, a2, s);
-        cg_alpha(w.partials, dslash_blocks(g, P, RC), w.st, s);
-        update_xr(vh, P, xu, ps, qs, rs, w.st, w.partials, s);
-        cg_beta(w.partials, w.npart, w.st, s);
-        xpay(vh, P, rs, ps, w.st, s);
+        cg_update(vh, P, xu, ps, qs, rs, w.st, w.partials, dslash_blocks(g, P, RC), w.rr_part, s);
+        cg_beta_xpay(vh, P, rs, ps, w.st, w.rr_part, s);
     };
 
     reliable(1);
