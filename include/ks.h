@@ -189,9 +189,10 @@ ks_status_t ks_apply_A(ks_gauge_t g, double sigma, const double* in_dev, double*
 /* Solves (4 m^2 - D_eo D_oe) x = b, b_dev and x_dev complex128 [Vh][3] device arrays.
  * x_dev holds the initial guess on entry (zero it for x0 = 0) and the solution on return.
  * With p->inner = KS_F64 this is plain FP64 CG; with KS_F32 / KS_F16 the Krylov vectors and
- * the inner operator are FP32 / FP16 while x is accumulated in FP64 and r = b - A x is
- * recomputed in FP64 (reliable update) whenever the inner residual falls below delta times
- * its maximum since the last update, and before returning.  Reductions are FP64 throughout.
+ * the inner operator are FP32 / FP16; x's increments are summed in FP32 and added into the
+ * FP64 x, and r = b - A x is recomputed in FP64 (reliable update), whenever the inner residual
+ * falls below delta times its maximum since the last update, and before returning.
+ * Reductions are FP64 throughout.
  * Success means the FP64 true relative residual is <= p->tol. */
 ks_status_t ks_cg_solve(ks_gauge_t g, double mass, const double* b_dev, double* x_dev,
                         const ks_solver_params* p, ks_solver_stats* st, hipStream_t stream);
@@ -200,8 +201,10 @@ ks_status_t ks_cg_solve(ks_gauge_t g, double mass, const double* b_dev, double* 
  * multi-mass CG of Sec. 3 and Sec. 4); sigma (host, length nshift) >= 0, x_dev a host array
  * of nshift device pointers (complex128 [Vh][3], overwritten; the initial guess is zero),
  * tol (host, length nshift) the per-shift targets.  The shared iteration runs in p->inner
- * precision with x_i accumulated in FP64; every shift whose FP64 true residual is then above
- * its target is refined by ks_cg_solve's method from x_i.  st: nshift entries. */
+ * precision with x_i accumulated in FP64 (in reduced precision through FP32 increments added
+ * in at every reliable update of the base system); every shift whose FP64 true residual is
+ * then above its target is refined from x_i by ks_cg_solve's method (several at once, one
+ * right-hand side each, when the inner precision is reduced).  st: nshift entries. */
 ks_status_t ks_multishift_cg_solve(ks_gauge_t g, int nshift, const double* sigma,
                                    const double* b_dev, double* const* x_dev,
                                    const double* tol, const ks_solver_params* p,
