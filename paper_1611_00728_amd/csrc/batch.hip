@@ -179,6 +179,114 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void ba
     }
 }
 
+// FP64 reliable-update form of the multi-RHS hopping term (out_r = D in_r, or with XPAY
+// out_r = sigma_r x_r - D in_r), for the few lattices whose update is due.  Such a launch has
+// little work, so the tile walk of the inner-precision kernel would leave most of the chip
+// idle and each site's chain of 16 dependent link and neighbour loads would set the time.
+// Here every block first finds, with one parallel scan, the lattices with an update due and
+// numbers their 64-site chunks; the chunks are spread over the whole grid; and four lanes
+// share a site, each taking the four matrices of one hop kind (forward one-link, backward
+// one-link, forward Naik, backward Naik): four times the waves and a quarter of the chain.
+// A two-step butterfly adds the four sums (every lane ends with the same total) and lanes 0-2
+// store one colour each.  No partial sums: the residual kernel that follows computes its own.
+constexpr int kRuLanes = 4;                // lanes per site (8 ties, 16 is slower)
+constexpr int kRuSites = 256 / kRuLanes;   // sites per chunk (one block's pass)
+constexpr int kRuGrid = 1024;              // blocks of a reliable-update launch
+
+template <int R, bool XPAY>
+__global__ __launch_bounds__(256) void batch_dslash_ru_kernel(
+    const LatDesc* __restrict__ lats, int nlat, int par, const char* __restrict__ in,
+    char* __restrict__ out, const char* __restrict__ xv, const BatchPair* __restrict__ pairs)
+{
+    using V = MVec<KS_F64, R>;
+    __shared__ int pref[257];   // pref[j]: chunks of the chunk-group's lattices before j
+    constexpr int kM = 16 / kRuLanes;   // matrices per lane, all of one hop kind
+    const int part = threadIdx.x & (kRuLanes - 1);
+    const int sl = threadIdx.x / kRuLanes;
+    const int kind = (part * kM) >> 2;  // 0: +1, 1: -1 (one-link), 2: +3, 3: -3 (Naik)
+    const int dist = (kind & 1) ? ((kind & 2) ? -3 : -1) : ((kind & 2) ? 3 : 1);
+    const int mu0 = (part * kM) & 3;
+    for (int l0 = 0; l0 < nlat; l0 += 256) {
+        const int l = l0 + threadIdx.x;
+        int n = 0;
+        if (l < nlat && lattice_busy(pairs, lats[l].pair0, R, true))
+            n = (lats[l].g.Vh + kRuSites - 1) / kRuSites;
+        if (threadIdx.x == 0) pref[0] = 0;
+        pref[threadIdx.x + 1] = n;
+        __syncthreads();
+        for (int off = 1; off < 256; off <<= 1) {   // inclusive scan of pref[1..256]
+            const int v = threadIdx.x >= off ? pref[threadIdx.x + 1 - off] : 0;
+            __syncthreads();
+            pref[threadIdx.x + 1] += v;
+            __syncthreads();
+        }
+        const int total = pref[256];
+        for (int u = blockIdx.x; u < total; u += gridDim.x) {
+            int lo = 0, hi = 256;   // the lattice j with pref[j] <= u < pref[j + 1]
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (pref[mid] <= u) lo = mid;
+                else hi = mid;
+            }
+            const LatDesc& L = lats[l0 + lo];
+            const Geom& g = L.g;
+            const int vh = g.Vh;
+            const int h = (u - pref[lo]) * kRuSites + sl;
+            const void* links = kind < 2 ? L.fat64[par] : L.naik64[par];
+            cx<double> res[3][R];
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int r = 0; r < R; ++r) res[k][r] = {0.0, 0.0};
+            if (h < vh) {
+                int c[4];
+                cb_coords(g, h, par, c);
+                const int i = site_index(g, c);
+#pragma unroll 1
+                for (int mu = mu0; mu < mu0 + kM; ++mu) {
+                    cx<double> m[9];
+                    load_link<KS_F64, 9>(links, (kind & 1) * 4 + mu, vh, h, m);
+                    cx<double> v[3][R];
+                    V::load(in, L.vec_off, vh, hop_cb(g, i, c, mu, dist), v);
+#pragma unroll
+                    for (int a = 0; a < 3; ++a)
+#pragma unroll
+                        for (int b = 0; b < 3; ++b)
+#pragma unroll
+                            for (int r = 0; r < R; ++r) cfma(res[a][r], m[a * 3 + b], v[b][r]);
+                }
+            }
+#pragma unroll
+            for (int off = 1; off < kRuLanes; off <<= 1)
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        res[k][r].r += __shfl_xor(res[k][r].r, off);
+                        res[k][r].i += __shfl_xor(res[k][r].i, off);
+                    }
+            if (h >= vh) continue;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                if (part != k) continue;
+                const size_t o = V::off(L.vec_off, vh, k, h);
+                double2* dst = reinterpret_cast<double2*>(out + o);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    double2 w = make_double2(res[k][r].r, res[k][r].i);
+                    if (XPAY) {
+                        const double2 x = reinterpret_cast<const double2*>(xv + o)[r];
+                        const double sg = pairs[L.pair0 + r].sigma;
+                        w = make_double2(sg * x.x - w.x, sg * x.y - w.y);
+                    }
+                    dst[r] = w;
+                }
+            }
+        }
+        __syncthreads();   // pref is rewritten by the next group of lattices
+    }
+}
+
 // x (FP64) += alpha p; r -= alpha q; partial sums of |r|^2 per RHS
 template <int P, int R, int NT>
 __global__ __launch_bounds__(NT) void batch_update_kernel(const LatDesc* __restrict__ lats,
@@ -382,45 +490,42 @@ __global__ __launch_bounds__(kFin) void batch_alpha_kernel(const LatDesc* __rest
     q.alpha = q.rho / pap;
 }
 
-// |r|^2 of the step and the pair's own decision; rho and beta are set by batch_sync_kernel
+// One block per lattice.  Each pair's |r|^2 of the step (its tile partials in tile order) and
+// the pair's own decision (update due: target met or step cap; or |r| fell by delta), then
+// the lattice's: a reliable update costs the lattice one FP64 multi-RHS A-apply whatever the
+// number of its pairs that take part, so when one pair's residual has fallen by delta every
+// unfinished pair takes the update with it (the right-hand sides then stay in step instead of
+// each paying its own).  Pairs without an update continue: beta = |r|^2 / rho, rho = |r|^2.
 __global__ __launch_bounds__(kFin) void batch_beta_kernel(const LatDesc* __restrict__ lats, int R,
                                                           BatchPair* __restrict__ pairs,
                                                           const double* __restrict__ part)
 {
-    const int pi = blockIdx.x;
-    BatchPair& q = pairs[pi];
-    if (q.done) return;
-    const LatDesc& L = lats[pi / R];
-    const double rn = pair_sum(L, part, R, pi % R);
-    if (threadIdx.x != 0) return;
-    q.iter += 1;
-    q.rn = rn;
-    if (!isfinite(rn)) {
-        q.status = KS_ERR_NONFINITE;
-        q.done = 1;
-        q.t_done = wall_clock64();
-        return;
+    const LatDesc& L = lats[blockIdx.x];
+    __shared__ double rn[4];
+    for (int r = 0; r < R; ++r) {
+        const double s = pair_sum(L, part, R, r);
+        if (threadIdx.x == 0) rn[r] = s;
+        __syncthreads();   // block_sum's scratch is reused by the next pair
     }
-    if (rn <= q.stop2 || q.iter >= q.max_iter) q.ru_now = 1;
-    else if (sqrt(rn) < q.delta * q.maxr) q.ru_now = 2;
-}
-
-// One thread per lattice.  A reliable update costs a lattice one FP64 multi-RHS A-apply
-// whatever the number of its pairs that take part, so when one pair's residual has fallen by
-// delta every unfinished pair of the lattice takes the update with it (the right-hand sides
-// then stay in step instead of each paying its own).  Pairs without an update continue:
-// beta = |r|^2 / rho, rho = |r|^2.
-__global__ void batch_sync_kernel(int nlat, int R, BatchPair* __restrict__ pairs)
-{
-    const int l = blockIdx.x * blockDim.x + threadIdx.x;
-    if (l >= nlat) return;
+    if (threadIdx.x != 0) return;
     bool drop = false;
     for (int r = 0; r < R; ++r) {
-        const BatchPair& q = pairs[l * R + r];
-        drop = drop || (!q.done && q.ru_now == 2);
+        BatchPair& q = pairs[L.pair0 + r];
+        if (q.done) continue;
+        q.iter += 1;
+        q.rn = rn[r];
+        if (!isfinite(q.rn)) {
+            q.status = KS_ERR_NONFINITE;
+            q.done = 1;
+            q.t_done = wall_clock64();
+            continue;
+        }
+        if (q.rn <= q.stop2 || q.iter >= q.max_iter) q.ru_now = 1;
+        else if (sqrt(q.rn) < q.delta * q.maxr) q.ru_now = 2;
+        drop = drop || q.ru_now == 2;
     }
     for (int r = 0; r < R; ++r) {
-        BatchPair& q = pairs[l * R + r];
+        BatchPair& q = pairs[L.pair0 + r];
         if (q.done) continue;
         if (drop && q.ru_now == 0) q.ru_now = 1;
         if (q.ru_now) continue;
@@ -571,9 +676,7 @@ struct BatchLaunch {
             batch_update_kernel<KS_F64, R, NT><<<grid, NT, 0, s>>>(c.lats_dev, tl, nt, c.x64, c.ps, c.qs, c.rs, c.pairs, c.partials);
         else
             batch_update_kernel<KS_F32, R, NT><<<grid, NT, 0, s>>>(c.lats_dev, tl, nt, c.x64, c.ps, c.qs, c.rs, c.pairs, c.partials);
-        batch_beta_kernel<<<np, kFin, 0, s>>>(c.lats_dev, R, c.pairs, c.partials);
-        const int nlat = (int)c.lats_host.size();
-        batch_sync_kernel<<<blocks_for(nlat, 64), 64, 0, s>>>(nlat, R, c.pairs);
+        batch_beta_kernel<<<(int)c.lats_host.size(), kFin, 0, s>>>(c.lats_dev, R, c.pairs, c.partials);
         reliable(c, 0, s);
         if (P == KS_F64)
             batch_xpay_kernel<KS_F64, R, NT><<<grid, NT, 0, s>>>(c.lats_dev, tl, nt, c.rs, c.ps, c.pairs, 0);
@@ -588,8 +691,11 @@ struct BatchLaunch {
         const int2* tl = c.tiles[c.tile_idx];
         const int grid = nt;   // streaming vector kernels: one block per tile (the tuned
                                 // persistent schedule is for the hopping terms)
-        dslash(c, KS_F64, false, true, 1, c.x64, c.t64, nullptr, s);
-        dslash(c, KS_F64, true, true, 0, c.t64, c.ax64, c.x64, s);
+        const int nlat = (int)c.lats_host.size();
+        batch_dslash_ru_kernel<R, false><<<kRuGrid, 256, 0, s>>>(c.lats_dev, nlat, 1, c.x64, c.t64,
+                                                                 nullptr, c.pairs);
+        batch_dslash_ru_kernel<R, true><<<kRuGrid, 256, 0, s>>>(c.lats_dev, nlat, 0, c.t64, c.ax64,
+                                                                c.x64, c.pairs);
         batch_resid_kernel<R, NT><<<grid, NT, 0, s>>>(c.lats_dev, tl, nt, c.b64, c.ax64, c.r64, c.pairs, c.partials);
         batch_reliable_kernel<<<c.npairs, kFin, 0, s>>>(c.lats_dev, R, c.pairs, c.partials, initial);
         if (c.prec == KS_F64)
