@@ -280,14 +280,16 @@ ks_status_t ks_batch_create(ks_batch_t* out, int nlat, const int* dims, const do
                             const double* const* naik, int on_device, int nrhs, ks_prec_t inner,
                             hipStream_t stream);
 
-/* Solves (4 m_l^2 - D_eo D_oe) x = b for every (lattice l, RHS r) pair, pair index
- * p = l * nrhs + r.  masses: host [nlat]; b_dev, x_dev: host arrays of nlat*nrhs device
- * pointers to complex128 [Vh_l][3] (x holds the initial guess, then the solution).  Every pair
- * has its own CG scalars and reliable updates on the device; the host replays a HIP graph of
- * p->check_every steps (captured on the first call, replayed by later ones) until every pair
- * has finished.  st: nlat*nrhs entries.  Returns KS_SUCCESS if every pair reached p->tol, else
- * the first failing pair's code (all stats filled).  p->inner and p->recon are ignored (the
- * batch's inner precision and 18-real links are used). */
+/* Solves (4 m_l^2 - D_eo D_oe) x = b for every (lattice l, RHS r) pair, pair index p = l *
+ * nrhs + r.  masses: host [nlat]; b_dev, x_dev: host arrays of nlat*nrhs device pointers to
+ * complex128 [Vh_l][3] (x holds the initial guess, then the solution).  Every pair has its own
+ * CG scalars on the device; FP64 reliable updates are taken per lattice (when one pair's
+ * residual has fallen by p->delta, the lattice's other unfinished pairs take the update with
+ * it, since it costs the lattice one multi-RHS A-apply either way); the host replays a HIP
+ * graph of p->check_every steps (captured on the first call, replayed by later ones) until
+ * every pair has finished.  st: nlat*nrhs entries.  Returns KS_SUCCESS if every pair reached
+ * p->tol, else the first failing pair's code (all stats filled).  p->inner and p->recon are
+ * ignored (the batch's inner precision and 18-real links are used). */
 ks_status_t ks_batch_solve(ks_batch_t b, const double* masses, const double* const* b_dev,
                            double* const* x_dev, const ks_solver_params* p, ks_batch_stats* st,
                            hipStream_t stream);
