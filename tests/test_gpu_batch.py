@@ -112,6 +112,23 @@ def test_batch_matches_single_solves(ks, fields):
     B.free()
 
 
+def test_batch_runs_are_bit_identical(ks, fields):
+    """Two solves of the same batch (FP32 inner, per-lattice reliable updates) return the same
+    x bit for bit and the same step counts: the reductions have a fixed order and the
+    reliable-update kernel's spread of work over the grid does not change any sum."""
+    announce("batch repeatability")
+    gs, masses = fields
+    B = ks.Batch([g.dims for g in gs], [g.fat for g in gs], [g.naik for g in gs], 4, ks.F32)
+    rc1, st1, _, x1 = run_batch(ks, B, gs, masses, 4, check_every=4)
+    rc2, st2, _, x2 = run_batch(ks, B, gs, masses, 4, check_every=4)
+    assert rc1 == 0 and rc2 == 0
+    assert [s["iters"] for s in st1] == [s["iters"] for s in st2]
+    assert [s["reliable_updates"] for s in st1] == [s["reliable_updates"] for s in st2]
+    for a, c in zip(x1, x2):
+        assert np.array_equal(a, c)
+    B.free()
+
+
 def test_batch_zero_rhs_and_max_iter(ks, fields):
     announce("batch edge cases")
     gs, masses = fields

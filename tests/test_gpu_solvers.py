@@ -136,6 +136,39 @@ def test_cg_16_agrees_with_oracle_solution(ks, inner):
     assert rel_l2(x, xo) <= 2 * (1e-10 + 1e-12) * hi / lo
 
 
+@pytest.mark.parametrize("inner,recon", [("f64", 18), ("f32", 18), ("f16", 12)])
+def test_cg_runs_are_bit_identical(ks, inner, recon):
+    """Every reduction has a fixed order (in the fused step kernels every block re-adds the
+    partials in the same order), so two runs return the same x bit for bit: a cheap check for
+    races.  12^4 spans several hundred blocks per launch."""
+    announce("cg repeatability", inner, recon)
+    g = make_gauge((12, 12, 12, 12), 0.5, 61)
+    G = ks.Gauge(g.dims, g.fat, g.naik)
+    b = gaussian_source(g.volume // 2, 62)
+    x1, r1 = solve(ks, G, 0.05, b, tol=1e-10, inner=inner, recon=recon, check_every=3)
+    x2, r2 = solve(ks, G, 0.05, b, tol=1e-10, inner=inner, recon=recon, check_every=7)
+    assert r1.ok and r2.ok
+    assert r1.stats["iters"] == r2.stats["iters"]
+    assert r1.stats["reliable_updates"] == r2.stats["reliable_updates"]
+    assert np.array_equal(x1, x2)
+
+
+def test_multishift_runs_are_bit_identical(ks, cfg1):
+    announce("multishift repeatability")
+    g, G, b, _, _ = cfg1
+    sig = 4 * np.geomspace(0.002, 0.5, 9) ** 2
+    out = []
+    for _ in range(2):
+        xs = [zeros_dev(b.shape) for _ in sig]
+        rc, stats = ks.multishift_cg_solve(G, sig, dev(b), xs, 1e-9,
+                                           ks.default_params(inner=ks.F32, check_every=4))
+        assert rc == 0
+        out.append(([host(x) for x in xs], [st["iters"] for st in stats]))
+    assert out[0][1] == out[1][1]
+    for a, c in zip(out[0][0], out[1][0]):
+        assert np.array_equal(a, c)
+
+
 @pytest.mark.parametrize("inner", ["f64", "f32", "f16"])
 def test_multishift(ks, cfg1, inner):
     announce("multishift 8^4", inner)
