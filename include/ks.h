@@ -369,6 +369,12 @@ ks_status_t ks_fcg_solve(ks_gauge_t g, ks_net_t n, double mass, const double* b_
  * Asynchronous on `stream`. */
 ks_status_t ks_stream_copy(void* dst_dev, const void* src_dev, size_t bytes, hipStream_t stream);
 
+/* Reads bytes of src_dev (one 16-byte non-temporal load per thread; nothing is written that
+ * the caller can see): the achievable read bandwidth, the reference of the hopping term,
+ * whose bytes are ~98 % reads.  bytes and the address must be multiples of 16, else
+ * KS_ERR_ARG.  Asynchronous on `stream`. */
+ks_status_t ks_stream_read(const void* src_dev, size_t bytes, hipStream_t stream);
+
 /* Message of the calling thread's last failure ("" if none). */
 const char* ks_last_error(void);
 

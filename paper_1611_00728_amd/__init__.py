@@ -99,6 +99,7 @@ def lib():
         L.ks_tune_dslash.argtypes = [_vp, C.c_int, C.c_int, _vp]
         L.ks_dslash_config.argtypes = [_vp, C.c_int, C.c_int, C.POINTER(DslashLaunch)]
         L.ks_stream_copy.argtypes = [_vp, _vp, C.c_size_t, _vp]
+        L.ks_stream_read.argtypes = [_vp, C.c_size_t, _vp]
         L.ks_dslash_set_config.argtypes = [_vp, C.c_int, C.c_int, C.POINTER(DslashLaunch)]
         L.ks_cg_solve.argtypes = [_vp, C.c_double, _vp, _vp, C.POINTER(SolverParams),
                                   C.POINTER(SolverStats), _vp]
@@ -257,6 +258,13 @@ def stream_copy(dst, src, stream=None):
         raise ValueError("stream_copy: contiguous tensors expected")
     _check(lib().ks_stream_copy(dst.data_ptr(), src.data_ptr(), n, _stream(stream)))
     return dst
+
+
+def stream_read(src, stream=None):
+    """Reads every byte of a contiguous device tensor by the library's streaming read kernel."""
+    if not (src.is_cuda and src.is_contiguous()):
+        raise ValueError("stream_read: a contiguous device tensor expected")
+    _check(lib().ks_stream_read(src.data_ptr(), src.numel() * src.element_size(), _stream(stream)))
 
 
 def apply_A(gauge: Gauge, sigma: float, x, out, stream=None):

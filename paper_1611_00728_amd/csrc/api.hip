@@ -649,6 +649,17 @@ ks_status_t ks_stream_copy(void* dst_dev, const void* src_dev, size_t bytes, hip
     KS_API_END
 }
 
+ks_status_t ks_stream_read(const void* src_dev, size_t bytes, hipStream_t stream)
+{
+    KS_API_BEGIN
+    KS_REQUIRE(bytes == 0 || src_dev, KS_ERR_ARG, "ks_stream_read: null pointer");
+    KS_REQUIRE(bytes % 16 == 0 && (uintptr_t)src_dev % 16 == 0, KS_ERR_ARG,
+               "ks_stream_read: bytes and the address must be multiples of 16");
+    stream_read(src_dev, bytes, stream);
+    return KS_SUCCESS;
+    KS_API_END
+}
+
 ks_status_t ks_batch_free(ks_batch_t b)
 {
     KS_API_BEGIN

@@ -54,5 +54,7 @@ void finish_to(const double* part, int n, double* out, hipStream_t s);
 // dst = src, bytes a multiple of 16, both 16-byte aligned (a streaming copy: the
 // achievable-bandwidth reference of the memory-bound kernels)
 void stream_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+// reads src (bytes a multiple of 16, 16-byte aligned): the achievable read bandwidth
+void stream_read(const void* src, size_t bytes, hipStream_t s);
 
 }  // namespace ks

@@ -76,3 +76,7 @@ def test_stream_copy_argument_checks(libks):
     for dst, src, n in ((4096, 8192, 20), (4100, 8192, 32), (4096, 8200, 32), (4096, 4112, 64)):
         assert libks.ks_stream_copy(dst, src, n, None) == -1
     assert libks.ks_stream_copy(None, None, 0, None) == 0
+    for src, n in ((4096, 20), (4100, 32)):
+        assert libks.ks_stream_read(src, n, None) == -1
+    assert libks.ks_stream_read(None, 16, None) == -1
+    assert libks.ks_stream_read(None, 0, None) == 0

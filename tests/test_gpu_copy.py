@@ -1,5 +1,6 @@
-"""The streaming copy kernel (the achievable-bandwidth reference of the benchmark) moves every
-byte: ragged sizes around the kernel's four-units-per-thread passes and grid strides."""
+"""The streaming copy and read kernels (the achievable-bandwidth references of the benchmark):
+the copy moves every byte (ragged sizes, nothing written past the end); the read leaves its
+input untouched; both refuse misaligned arguments."""
 import numpy as np
 import pytest
 
@@ -32,3 +33,27 @@ def test_stream_copy_errors():
         ks.stream_copy(a[:8], a[8:24])
     with pytest.raises(ks.KSError):
         ks.stream_copy(a[1:5], a[8:12])     # 4-byte offset: not 16-byte aligned
+
+
+@pytest.mark.parametrize("units", [1, 255, 4097, (1 << 23) + 5])
+def test_stream_read_leaves_input(units):
+    import torch
+    import paper_1611_00728_amd as ks
+    announce("stream read", units)
+    rng = np.random.default_rng(units)
+    src = torch.from_numpy(rng.integers(0, 2 ** 31, size=4 * units, dtype=np.int32)).cuda()
+    keep = src.clone()
+    ks.stream_read(src)
+    torch.cuda.synchronize()
+    assert torch.equal(src, keep)
+
+
+def test_stream_read_errors():
+    import torch
+    import paper_1611_00728_amd as ks
+    announce("stream read errors")
+    a = torch.zeros(64, dtype=torch.int32, device="cuda")
+    with pytest.raises(ks.KSError):
+        ks.stream_read(a[1:5])              # 4-byte offset
+    with pytest.raises(ks.KSError):
+        ks.stream_read(a[:3])               # 12 bytes
