@@ -535,14 +535,15 @@ def main():
             learned_runs.append((time.perf_counter() - t, res.stats))
 
     # link construction from the thin links of the same 32^4 field (two smearing levels, U(3)
-    # projection, Naik): algorithmic bytes of its passes over [V][3][3] FP64 fields (144 B per
-    # matrix): per direction 6 three-link staples (4 matrices each), the scaled copies (2 each),
-    # per transverse direction 4 nested staples over three summed fields (7 matrices) and the
-    # outer and Lepage staples (5 each); then the projection (2 per link), the Naik product (4)
-    # and the sign folding (4 per link pair)
+    # projection, Naik): bytes of the matrices its passes access in [V][3][3] FP64 fields (144 B
+    # per matrix; neighbouring sites share many of them through the caches): per direction 6
+    # three-link staples (4 matrices each) and 6 fused outer terms (per term 4 inner staples of
+    # 5 matrices, the middle U, the two outer links, F in or U, F out, and the Lepage field at
+    # level 2); then the projection (2 per link), the Naik product (4) and the sign folding (4
+    # per link pair)
     def smear_bytes(lepage):
-        per_a = 2 + 4 * 7 + 5 + (5 if lepage else 0)
-        return 4 * 144 * (6 * 4 + 2 + 6 * per_a)
+        per_a = 4 * 5 + 1 + 2 + 2 + (1 if lepage else 0)
+        return 4 * 144 * (6 * 4 + 6 * per_a)
     hisq_bytes = (smear_bytes(False) + smear_bytes(True) + 4 * 144 * (2 + 4 + 4)) * g.volume
     thin_d = torch.from_numpy(np.ascontiguousarray(g.thin).reshape(-1)).cuda()
     hisq_fat = torch.empty_like(thin_d)

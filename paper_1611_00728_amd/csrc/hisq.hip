@@ -9,8 +9,10 @@
 //     F_mu = c1 U + cL sum_a S_a[S_a[U]] + sum_a S_a[ c3 U + sum_b S_b[ c5 U + c7 sum_c S_c[U] ] ]
 // over signed transverse directions on distinct axes (6 three-link, 24 five-link, 48
 // seven-link staples, 6 double-width Lepage staples; the nesting follows from linearity of the
-// staple in M).  Every term is one pass of `staple_kernel` over the lattice, which forms its
-// middle field on the fly as a weighted sum of up to three fields.
+// staple in M).  Per mu: the six three-link staples S_c[U] by `staple_kernel`, then one
+// `fat_term_kernel` pass per outer direction a that builds the whole middle field of S_a at
+// x + s_a a in registers (its four five-link staples with their seven-link middles, and the
+// Lepage term, which shares the outer links).
 #include <algorithm>
 #include <vector>
 
@@ -164,14 +166,108 @@ __global__ __launch_bounds__(kBlock) void staple_kernel(Geom g, const double2* _
     store_mat(out, x, o);
 }
 
-// out = a * in over n matrices
-__global__ __launch_bounds__(kBlock) void scale_mat_kernel(long n, const double2* __restrict__ in,
-                                                           double a, double2* __restrict__ out)
+// One outer term of the smearing for every x, all its inner terms fused:
+//   F(x) (+)= S_a[ c3 U + cL S_a[U] + sum_b S_b[ c5 U + c7 sum_c S_c[U] ] ](x)
+// (F(x) = c1 U(x) + ... when `first`).  The outer staple reads its middle field at
+// y = x + s_a a only, so each x builds that field at y in registers: the inner sum is never
+// stored, and the Lepage term shares the outer staple's links.  b runs over the four signed
+// directions off mu and a's axis, c over the two on the remaining axis (precomputed
+// three-link staples S_c[U], in s1).
+struct FatTerm {
+    const double2* s1[6];   // S_d[U_mu] for the six signed directions off mu
+    int mu, anu, as, aidx;
+    int bnu[4], bs[4], cidx[4][2];
+    double c1, c3, c5, c7, cl;
+    int first;
+};
+
+__device__ __forceinline__ void axpy_mat(Mat& acc, double w, const Mat& m)
 {
-    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n * 9) return;
-    const double2 v = in[i];
-    out[i] = make_double2(a * v.x, a * v.y);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        acc.e[k].r = fma(w, m.e[k].r, acc.e[k].r);
+        acc.e[k].i = fma(w, m.e[k].i, acc.e[k].i);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void fat_term_kernel(Geom g, const double2* __restrict__ U,
+                                                          FatTerm t, double2* __restrict__ F)
+{
+    const long x = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= g.V) return;
+    const long vol = g.V;
+    const int mu = t.mu;
+    const double2* Umu = U + (long)mu * vol * 9;
+    int c[4];
+    site_coords(g, x, c);
+    // y = x + s_a a and its coordinates; y + mu
+    const long y = hop_lex(g, x, c, t.anu, t.as);
+    int cy[4] = {c[0], c[1], c[2], c[3]};
+    cy[t.anu] = (c[t.anu] + t.as + g.n[t.anu]) % g.n[t.anu];
+    const long ym = hop_lex(g, y, cy, mu, 1);
+    int cym[4] = {cy[0], cy[1], cy[2], cy[3]};
+    cym[mu] = (cy[mu] + 1) % g.n[mu];
+    Mat inner;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) inner.e[k] = {0.0, 0.0};
+    axpy_mat(inner, t.c3, load_mat(Umu, y));
+    if (t.cl != 0.0) axpy_mat(inner, t.cl, load_mat(t.s1[t.aidx], y));
+#pragma unroll 1
+    for (int k = 0; k < 4; ++k) {
+        const int bn = t.bnu[k], bsg = t.bs[k];
+        const double2* Ub = U + (long)bn * vol * 9;
+        const long z = hop_lex(g, y, cy, bn, bsg);   // y + s_b b
+        Mat M;
+#pragma unroll
+        for (int e = 0; e < 9; ++e) M.e[e] = {0.0, 0.0};
+        axpy_mat(M, t.c5, load_mat(Umu, z));
+        if (t.c7 != 0.0) {
+            axpy_mat(M, t.c7, load_mat(t.s1[t.cidx[k][0]], z));
+            axpy_mat(M, t.c7, load_mat(t.s1[t.cidx[k][1]], z));
+        }
+        Mat B0, B1;
+        if (bsg > 0) {
+            B0 = load_mat(Ub, y);
+            B1 = load_mat(Ub, ym);
+        } else {
+            B0 = adj(load_mat(Ub, z));
+            B1 = adj(load_mat(Ub, hop_lex(g, ym, cym, bn, -1)));
+        }
+        const Mat r = mul_adj(mul(B0, M), B1);
+#pragma unroll
+        for (int e = 0; e < 9; ++e) {
+            inner.e[e].r += r.e[e].r;
+            inner.e[e].i += r.e[e].i;
+        }
+    }
+    // outer staple at x in direction a
+    const double2* Ua = U + (long)t.anu * vol * 9;
+    const long xm = hop_lex(g, x, c, mu, 1);
+    Mat L0, L1;
+    if (t.as > 0) {
+        L0 = load_mat(Ua, x);
+        L1 = load_mat(Ua, xm);
+    } else {
+        int cm[4] = {c[0], c[1], c[2], c[3]};
+        cm[mu] = (c[mu] + 1) % g.n[mu];
+        L0 = adj(load_mat(Ua, y));
+        L1 = adj(load_mat(Ua, hop_lex(g, xm, cm, t.anu, -1)));
+    }
+    const Mat r = mul_adj(mul(L0, inner), L1);
+    Mat o;
+    if (t.first) {
+#pragma unroll
+        for (int e = 0; e < 9; ++e) o.e[e] = {0.0, 0.0};
+        axpy_mat(o, t.c1, load_mat(Umu, x));
+    } else {
+        o = load_mat(F, x);
+    }
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+        o.e[e].r += r.e[e].r;
+        o.e[e].i += r.e[e].i;
+    }
+    store_mat(F, x, o);
 }
 
 // W = V (V^+ V)^(-1/2) by the scaled Newton iteration for the polar factor,
@@ -302,9 +398,10 @@ Middle one(const double2* f, double w)
     return m;
 }
 
-// out[4][V] = F(U; c), with scratch: s1 six fields, inner, one more
+// out[4][V] = F(U; c): per mu, the six three-link staples S_d[U_mu] into s1, then one fused
+// launch per outer direction a (its inner five- and seven-link and Lepage terms included)
 void smear(const Geom& G, const double2* U, const double* c, double2* out, double2* const* s1,
-           double2* inner, hipStream_t st)
+           hipStream_t st)
 {
     const long vol = G.V;
     for (int mu = 0; mu < 4; ++mu) {
@@ -317,28 +414,31 @@ void smear(const Geom& G, const double2* U, const double* c, double2* out, doubl
                 dirs.push_back({nu, -1});
             }
         for (int a = 0; a < 6; ++a) staple(G, U, mu, dirs[a], one(Umu, 1.0), 1.0, false, s1[a], st);
-        scale_mat_kernel<<<blocks_for(vol * 9), kBlock, 0, st>>>(vol, Umu, c[0], F);
-        KS_HIP(hipGetLastError());
         for (int a = 0; a < 6; ++a) {
-            scale_mat_kernel<<<blocks_for(vol * 9), kBlock, 0, st>>>(vol, Umu, c[1], inner);
-            KS_HIP(hipGetLastError());
+            FatTerm t{};
+            for (int q = 0; q < 6; ++q) t.s1[q] = s1[q];
+            t.mu = mu;
+            t.anu = dirs[a].nu;
+            t.as = dirs[a].s;
+            t.aidx = a;
+            int k = 0;
             for (int b = 0; b < 6; ++b) {
                 if (dirs[b].nu == dirs[a].nu) continue;
-                Middle m{};
-                m.f[0] = Umu;
-                m.w[0] = c[2];
-                m.n = 1;
-                if (c[3] != 0.0)
-                    for (int q = 0; q < 6; ++q)
-                        if (dirs[q].nu != dirs[a].nu && dirs[q].nu != dirs[b].nu) {
-                            m.f[m.n] = s1[q];
-                            m.w[m.n] = c[3];
-                            ++m.n;
-                        }
-                staple(G, U, mu, dirs[b], m, 1.0, true, inner, st);
+                t.bnu[k] = dirs[b].nu;
+                t.bs[k] = dirs[b].s;
+                int n = 0;
+                for (int q = 0; q < 6; ++q)
+                    if (dirs[q].nu != dirs[a].nu && dirs[q].nu != dirs[b].nu) t.cidx[k][n++] = q;
+                ++k;
             }
-            staple(G, U, mu, dirs[a], one(inner, 1.0), 1.0, true, F, st);
-            if (c[4] != 0.0) staple(G, U, mu, dirs[a], one(s1[a], 1.0), c[4], true, F, st);
+            t.c1 = c[0];
+            t.c3 = c[1];
+            t.c5 = c[2];
+            t.c7 = c[3];
+            t.cl = c[4];
+            t.first = a == 0 ? 1 : 0;
+            fat_term_kernel<<<blocks_for(vol), kBlock, 0, st>>>(G, U, t, F);
+            KS_HIP(hipGetLastError());
         }
     }
 }
@@ -362,16 +462,15 @@ void hisq_links(const Geom& G, const double* thin, double* fat, double* naik,
     try {
         double2* s1[6];
         for (auto& p : s1) p = get(mat);
-        double2* inner = get(mat);
         double2* V1 = get(4 * mat);
         double2* W = get(4 * mat);
         int* bad = reinterpret_cast<int*>(get(sizeof(double2)));
         const double2* U = reinterpret_cast<const double2*>(thin);
-        smear(G, U, level1, V1, s1, inner, st);
+        smear(G, U, level1, V1, s1, st);
         KS_HIP(hipMemsetAsync(bad, 0, sizeof(int), st));
         u3_project_kernel<<<blocks_for(4 * vol), kBlock, 0, st>>>(4 * vol, V1, W, bad);
         KS_HIP(hipGetLastError());
-        smear(G, W, level2, reinterpret_cast<double2*>(fat), s1, inner, st);
+        smear(G, W, level2, reinterpret_cast<double2*>(fat), s1, st);
         naik_kernel<<<blocks_for(4 * vol), kBlock, 0, st>>>(G, W, c_naik,
                                                              reinterpret_cast<double2*>(naik));
         KS_HIP(hipGetLastError());
