@@ -669,11 +669,14 @@ def main():
                      "frac_of_8TBps": mbytes / med / 1e9 / HBM_PEAK_GBS}
     msr["lattice"] = list(MS_DIMS)
     fsec = float(np.median(force_runs))
-    # per term: import (48 B read + 48 written per even site) and the FP64 hopping term (2400 B
-    # per odd site); outer products: both forces written (2 x 4 x 144 B per site) and each
-    # term's vector read once per site (48 B)
+    # per term: import (48 B read + 48 written per even site) and its share of the multi-vector
+    # FP64 hopping term (links, 2304 B per odd site, read once per pass of up to five terms; the
+    # term's input and output, 96 B); outer products: both forces written (2 x 4 x 144 B per
+    # site) and each term's vector read once per site (48 B)
     nt_ = len(ms_sigma)
-    fbytes = nt_ * ms_vh * (96 + 2400) + fvol * (2 * 4 * 144 + nt_ * 48)
+    fpasses = -(-nt_ // 5)
+    fbytes = (nt_ * ms_vh * (96 + 96) + fpasses * ms_vh * 2304 +
+              fvol * (2 * 4 * 144 + nt_ * 48))
     msr["force"] = {"seconds": fsec, "terms": nt_, "model_GBps": fbytes / fsec / 1e9,
                     "frac_of_8TBps": fbytes / fsec / 1e9 / HBM_PEAK_GBS,
                     "note": "link derivative of the nine-term rational action from the "
