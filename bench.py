@@ -9,8 +9,8 @@ One step is one pass of the hot path:
      its solutions;
   4. network bursts and the learned flexible CG;
   5. the full-system solve M x = b and the link construction from thin links;
-  6. the plain FP64 GPU CG and the mixed-precision CG solves (FP32 inner, FP16 inner with
-     12-real Naik) to FP64 true relative residual 1e-10.
+  6. the plain FP64 GPU CG and the mixed-precision CG solves (FP32 inner with 18- and 12-real
+     Naik, FP16 inner with 12-real Naik) to FP64 true relative residual 1e-10.
 `value` is the FP64 Dslash_eo's algorithmic HBM bandwidth (least-data model: 2400 bytes per
 output site) averaged over every launch of the timed steps; the other rows report their own
 figures in the same JSON line.
@@ -571,9 +571,9 @@ def main():
         if record:
             full_runs.append((time.perf_counter() - t, res.stats))
 
-    solves = {"f64": [], "f32": [], "f16_r12": []}
+    solves = {"f64": [], "f32": [], "f32_r12": [], "f16_r12": []}
     solve_cfg = {"f64": dict(inner=ks.F64, recon=18), "f32": dict(inner=ks.F32, recon=18),
-                 "f16_r12": dict(inner=ks.F16, recon=12)}
+                 "f32_r12": dict(inner=ks.F32, recon=12), "f16_r12": dict(inner=ks.F16, recon=12)}
 
     def step(record):
         for v in variants:
