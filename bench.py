@@ -5,8 +5,8 @@ One step is one pass of the hot path:
   1. timed bursts of Dslash_eo launches of all six variants (FP64 / FP32 / FP16, 18- and
      12-real Naik; HIP events around every launch, on the stream the library launches on);
   2. the batched solve (64 lattices of 8^4, 12^4, 16^4 x 4 right-hand sides, FP32 + RU);
-  3. the multi-shift solve on 32^3 x 48 (9 shifts, FP64 and FP32 + RU) and the force from
-     its solutions;
+  3. the multi-shift solve on 32^3 x 48 (9 shifts; FP64, FP32 + RU and FP16 + RU, 18-real
+     Naik, and FP64 and FP32 with 12-real Naik) and the force from its solutions;
   4. network bursts and the learned flexible CG;
   5. the full-system solve M x = b and the link construction from thin links;
   6. the plain FP64 GPU CG and the mixed-precision CG solves (FP32 inner with 18- and 12-real
@@ -454,7 +454,7 @@ def main():
     MS_DIMS = (32, 32, 32, 48)
     gm = make_gauge(MS_DIMS, 0.5, SEEDS["gauge"](3))
     GM = ks.Gauge(MS_DIMS, gm.fat, gm.naik)
-    for p_, rc_ in ((ks.F64, 18), (ks.F32, 18), (ks.F32, 12), (ks.F16, 18)):
+    for p_, rc_ in ((ks.F64, 18), (ks.F64, 12), (ks.F32, 18), (ks.F32, 12), (ks.F16, 18)):
         GM.prepare(p_, rc_)
         GM.tune(p_, rc_)
     mb_ = torch.from_numpy(gaussian_source(gm.volume // 2, SEEDS["source"](3))).cuda()
@@ -463,7 +463,7 @@ def main():
     ms_vh = gm.volume // 2
     del gm
     log("32^3x48 multi-shift field ready in %.1f s" % (time.time() - t1))
-    ms_runs = {"f64": [], "f32": [], "f32_r12": [], "f16": []}
+    ms_runs = {"f64": [], "f64_r12": [], "f32": [], "f32_r12": [], "f16": []}
 
     # link derivative of sum_i r_i b^+ A_i^-1 b from the nine solutions (residues 1/(i+1))
     ms_res = [1.0 / (i + 1) for i in range(len(ms_sigma))]
@@ -473,8 +473,8 @@ def main():
     force_runs = []
 
     def multishift(record):
-        for name, p_, rc_ in (("f64", ks.F64, 18), ("f32", ks.F32, 18), ("f32_r12", ks.F32, 12),
-                              ("f16", ks.F16, 18)):
+        for name, p_, rc_ in (("f64", ks.F64, 18), ("f64_r12", ks.F64, 12), ("f32", ks.F32, 18),
+                              ("f32_r12", ks.F32, 12), ("f16", ks.F16, 18)):
             torch.cuda.synchronize()
             t = time.perf_counter()
             rc, st = ks.multishift_cg_solve(GM, ms_sigma, mb_, ms_x, 1e-9,
