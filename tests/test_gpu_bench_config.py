@@ -1,0 +1,98 @@
+"""The benchmark's own configurations at full size, in the launch forms the benchmark times
+(every variant autotuned on its lattice first, as bench.py does):
+
+* every Dslash_eo output site of the six variants at 32^4 against the FP64 oracle (tolerances
+  as in test_gpu_dslash: FP64 1e-12, FP32 5e-6, FP16 5e-3 relative L2);
+* the benchmark's CG solves at 32^4, m = 0.01 (FP64, FP32 with 18- and 12-real Naik, FP16 with
+  12-real Naik), each x judged by the oracle's FP64 residual |b - A x| / |b| <= 1e-10;
+* the benchmark's multi-shift solve at 32^3 x 48 (nine shifts, FP32 inner and FP64, per-shift
+  target 1e-9), each x_i judged by the oracle's residual of its own shifted system.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from ksinputs import make_gauge, gaussian_source, SEEDS
+from conftest import rel_l2
+from gpu_util import dev, host, zeros_dev, announce
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ks():
+    import torch
+    import paper_1611_00728_amd as ks
+    assert torch.cuda.is_available()
+    return ks
+
+
+@pytest.fixture(scope="module")
+def lat32(ks):
+    dims = (32, 32, 32, 32)
+    g = make_gauge(dims, 0.5, 1002)
+    return g, ks.Gauge(dims, g.fat, g.naik), gaussian_source(g.volume // 2, 2002)
+
+
+def true_rel(g, sigma, b, x):
+    return float(np.linalg.norm(b - oracle.apply_A(g, sigma, x)) / np.linalg.norm(b))
+
+
+def test_tuned_dslash_32(ks, lat32):
+    import torch
+    g, G, psi = lat32
+    vh = g.volume // 2
+    refs = [oracle.dslash_eo(g, p, psi) for p in (0, 1)]
+    for prec, recon, tol in ((ks.F64, 18, 1e-12), (ks.F64, 12, 1e-12), (ks.F32, 18, 5e-6),
+                             (ks.F32, 12, 5e-6), (ks.F16, 18, 5e-3), (ks.F16, 12, 5e-3)):
+        G.prepare(prec, recon)
+        cfg = G.tune(prec, recon)
+        announce("tuned dslash 32^4", prec, recon, cfg)
+        for out_par in (0, 1):
+            inp = ks.Field(G, 1 - out_par, prec).load(dev(psi))
+            out = ks.Field(G, out_par, prec)
+            ks.dslash_eo(G, out, inp, recon)
+            res = zeros_dev((vh, 3))
+            out.store(res)
+            torch.cuda.synchronize()
+            assert rel_l2(host(res), refs[out_par]) <= tol, (prec, recon, cfg)
+
+
+@pytest.mark.parametrize("inner,recon", [("f64", 18), ("f32", 18), ("f32", 12), ("f16", 12)])
+def test_bench_cg_32(ks, lat32, inner, recon):
+    import torch
+    g, G, b = lat32
+    announce("bench cg 32^4", inner, recon)
+    G.prepare(ks.PREC[inner], recon)
+    G.tune(ks.PREC[inner], recon)
+    x = zeros_dev(b.shape)
+    res = ks.cg_solve(G, 0.01, dev(b), x, ks.default_params(tol=1e-10, inner=inner, recon=recon),
+                      raise_on_error=False)
+    torch.cuda.synchronize()
+    assert res.ok, res
+    tr = true_rel(g, 4 * 0.01 ** 2, b, host(x))
+    assert tr <= 1e-10
+    assert abs(res.stats["true_rel_resid"] - tr) <= 1e-3 * tr
+
+
+@pytest.mark.parametrize("inner", ["f32", "f64"])
+def test_bench_multishift_32x48(ks, inner):
+    import torch
+    dims = (32, 32, 32, 48)
+    announce("bench multishift 32^3x48", inner)
+    g = make_gauge(dims, 0.5, SEEDS["gauge"](3))
+    G = ks.Gauge(dims, g.fat, g.naik)
+    G.prepare(ks.PREC[inner], 18)
+    G.tune(ks.PREC[inner], 18)
+    b = gaussian_source(g.volume // 2, SEEDS["source"](3))
+    sig = 4 * np.geomspace(0.002, 0.5, 9) ** 2
+    xs = [zeros_dev(b.shape) for _ in sig]
+    rc, stats = ks.multishift_cg_solve(G, sig, dev(b), xs, 1e-9,
+                                       ks.default_params(inner=ks.PREC[inner], check_every=16),
+                                       raise_on_error=False)
+    torch.cuda.synchronize()
+    assert rc == 0
+    for i, s in enumerate(sig):
+        tr = true_rel(g, s, b, host(xs[i]))
+        assert tr <= 1e-9, (i, tr)
+        assert abs(stats[i]["true_rel_resid"] - tr) <= 1e-3 * tr
