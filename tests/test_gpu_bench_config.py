@@ -6,7 +6,8 @@
 * the benchmark's CG solves at 32^4, m = 0.01 (FP64, FP32 with 18- and 12-real Naik, FP16 with
   12-real Naik), each x judged by the oracle's FP64 residual |b - A x| / |b| <= 1e-10;
 * the benchmark's multi-shift solve at 32^3 x 48 (nine shifts, FP32 inner and FP64, per-shift
-  target 1e-9), each x_i judged by the oracle's residual of its own shifted system.
+  target 1e-9), each x_i judged by the oracle's residual of its own shifted system;
+* the benchmark's batch (64 lattices x 4 right-hand sides, tuned), every pair judged likewise.
 """
 import numpy as np
 import pytest
@@ -96,3 +97,30 @@ def test_bench_multishift_32x48(ks, inner):
         tr = true_rel(g, s, b, host(xs[i]))
         assert tr <= 1e-9, (i, tr)
         assert abs(stats[i]["true_rel_resid"] - tr) <= 1e-3 * tr
+
+
+def test_bench_batch(ks):
+    """The benchmark's batch: 24 x 8^4 + 24 x 12^4 + 16 x 16^4 lattices x 4 right-hand sides,
+    FP32 inner iterations with per-lattice reliable updates, tuned schedule; every pair's x
+    judged by the oracle's residual (<= 1e-10)."""
+    import torch
+    from ksinputs import batch_masses
+    announce("bench batch 64 lattices x 4")
+    bdims = [(8, 8, 8, 8)] * 24 + [(12, 12, 12, 12)] * 24 + [(16, 16, 16, 16)] * 16
+    gs = [make_gauge(d, 0.4, SEEDS["batch_gauge"](j)) for j, d in enumerate(bdims)]
+    masses = batch_masses(len(bdims), 0.01, 0.2, SEEDS["batch_mass"])
+    B = ks.Batch(bdims, [x.fat for x in gs], [x.naik for x in gs], 4, ks.F32)
+    B.tune()
+    bh = [gaussian_source(x.volume // 2, SEEDS["batch_rhs"](j, r)) for j, x in enumerate(gs)
+          for r in range(4)]
+    bs = [dev(b) for b in bh]
+    xs = [zeros_dev(b.shape) for b in bh]
+    rc, st = B.solve(masses, bs, xs, ks.default_params(tol=1e-10, check_every=8),
+                     raise_on_error=False)
+    torch.cuda.synchronize()
+    assert rc == 0
+    for p, b in enumerate(bh):
+        j = p // 4
+        tr = true_rel(gs[j], 4 * masses[j] ** 2, b, host(xs[p]))
+        assert tr <= 1e-10, (p, tr)
+    B.free()
