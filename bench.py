@@ -71,6 +71,26 @@ def batch_model_bytes(stats, vhs, nrhs=4):
     return total
 
 
+def lanczos_spectrum(alpha, beta):
+    """(lambda_min, lambda_max, kappa) of the Lanczos tridiagonal of one unbroken CG run:
+    diagonal 1/alpha_k + beta_{k-1}/alpha_{k-1}, off-diagonal sqrt(beta_k)/alpha_k (the last
+    step's beta, NaN after the final check, is not used)."""
+    import numpy as np
+    k = len(alpha)
+    if k < 2:
+        return None
+    a = np.asarray(alpha, dtype=float)
+    bt = np.asarray(beta[:k - 1], dtype=float)
+    if not (np.all(np.isfinite(a)) and np.all(np.isfinite(bt))):
+        return None
+    diag = 1.0 / a
+    diag[1:] += bt / a[:-1]
+    off = np.sqrt(bt) / a[:-1]
+    w = np.linalg.eigvalsh(np.diag(diag) + np.diag(off, 1) + np.diag(off, -1))
+    return {"lambda_min": float(w[0]), "lambda_max": float(w[-1]), "kappa": float(w[-1] / w[0]),
+            "steps": k}
+
+
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "dslash_32x32x32x32_hbm_traffic.md")
 KERNEL_SOURCES = ["dslash.hip", "ks_device.h", "ks_common.h"]
 
@@ -189,11 +209,14 @@ def learned48(args):
                       "fallback_code": res.stats["fallback"],
                       "flexible_steps": res.stats["iters"] - res.stats["restarts"]
                       if res.stats["fallback"] else res.stats["iters"]}
+        if name == "fp64_cg":
+            spectrum = lanczos_spectrum(*G.cg_coefficients())
         log("%s: %s" % (name, json.dumps(rows[name])))
     tm, tl = rows["mixed_f32_cg"]["seconds"], rows["learned_fcg"]["seconds"]
     print(json.dumps({
         "workload": "learned preconditioner, 48^3x64, H scale 0.5, m=0.002, tol 1e-10",
         "solves": rows,
+        "spectrum_of_A": spectrum,
         "training": {"pairs": len(pairs), "block_pairs": len(pairs) - len(full),
                      "full_lattice_pairs": len(full), "pair_generation_s": t_gen,
                      "adam_steps": steps, "batch": 8, "training_s": t_train,
@@ -572,6 +595,7 @@ def main():
             full_runs.append((time.perf_counter() - t, res.stats))
 
     solves = {"f64": [], "f32": [], "f32_r12": [], "f16_r12": []}
+    spectrum = {}
     solve_cfg = {"f64": dict(inner=ks.F64, recon=18), "f32": dict(inner=ks.F32, recon=18),
                  "f32_r12": dict(inner=ks.F32, recon=12), "f16_r12": dict(inner=ks.F16, recon=12)}
 
@@ -593,6 +617,8 @@ def main():
             dt = time.perf_counter() - t
             if record:
                 solves[name].append((dt, res.stats))
+                if name == "f64":
+                    spectrum["f64"] = lanczos_spectrum(*G.cg_coefficients())
 
     for _ in range(args.warmup):
         step(False)
@@ -769,6 +795,7 @@ def main():
         "link_access_study": link_study,
         "link_construction": links,
         "time_to_solution": tts,
+        "spectrum_32x32x32x32_m0.01": spectrum.get("f64"),
         "batch": batch,
         "multishift": msr,
         "network": network,

@@ -197,6 +197,16 @@ ks_status_t ks_apply_A(ks_gauge_t g, double sigma, const double* in_dev, double*
 ks_status_t ks_cg_solve(ks_gauge_t g, double mass, const double* b_dev, double* x_dev,
                         const ks_solver_params* p, ks_solver_stats* st, hipStream_t stream);
 
+/* The CG coefficients alpha_k, beta_k of every step of the last CG run on this handle
+ * (ks_cg_solve, or the CG inside ks_full_solve and the flexible-CG fallback): up to n_max of
+ * them into the host arrays alpha and beta, *n = how many (at most the run's steps, and at most
+ * 2^20).  beta_k is NaN for a step that ended in a reliable update or the final check.  With
+ * p->inner = KS_F64 and no restart they belong to one unbroken CG run, so they define its
+ * Lanczos tridiagonal (diagonal 1/alpha_k + beta_{k-1}/alpha_{k-1}, off-diagonal
+ * sqrt(beta_k)/alpha_k), whose extreme eigenvalues estimate those of A (the solver's condition
+ * number).  Synchronous.  KS_ERR_ARG for a null handle or pointer or n_max < 0. */
+ks_status_t ks_cg_coefficients(ks_gauge_t g, int n_max, double* alpha, double* beta, int* n);
+
 /* Solves (sigma_i - D_eo D_oe) x_i = b for nshift (<= 32) shifts in one Krylov space (the
  * multi-mass CG of Sec. 3 and Sec. 4); sigma (host, length nshift) >= 0, x_dev a host array
  * of nshift device pointers (complex128 [Vh][3], overwritten; the initial guess is zero),

@@ -100,6 +100,7 @@ def lib():
         L.ks_dslash_config.argtypes = [_vp, C.c_int, C.c_int, C.POINTER(DslashLaunch)]
         L.ks_stream_copy.argtypes = [_vp, _vp, C.c_size_t, _vp]
         L.ks_stream_read.argtypes = [_vp, C.c_size_t, _vp]
+        L.ks_cg_coefficients.argtypes = [_vp, C.c_int, _vp, _vp, C.POINTER(C.c_int)]
         L.ks_dslash_set_config.argtypes = [_vp, C.c_int, C.c_int, C.POINTER(DslashLaunch)]
         L.ks_cg_solve.argtypes = [_vp, C.c_double, _vp, _vp, C.POINTER(SolverParams),
                                   C.POINTER(SolverStats), _vp]
@@ -201,6 +202,16 @@ class Gauge:
 
     def device_bytes(self) -> int:
         return int(lib().ks_gauge_device_bytes(self.handle))
+
+    def cg_coefficients(self, n_max: int = 1 << 20):
+        """(alpha, beta) numpy arrays of the last CG run on this handle (ks_cg_coefficients)."""
+        import numpy as np
+        alpha = np.zeros(n_max)
+        beta = np.zeros(n_max)
+        n = C.c_int(0)
+        _check(lib().ks_cg_coefficients(self.handle, n_max, alpha.ctypes.data, beta.ctypes.data,
+                                        C.byref(n)))
+        return alpha[:n.value].copy(), beta[:n.value].copy()
 
     def free(self):
         if self.handle:

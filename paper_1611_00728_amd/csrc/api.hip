@@ -649,6 +649,16 @@ ks_status_t ks_stream_copy(void* dst_dev, const void* src_dev, size_t bytes, hip
     KS_API_END
 }
 
+ks_status_t ks_cg_coefficients(ks_gauge_t g, int n_max, double* alpha, double* beta, int* n)
+{
+    KS_API_BEGIN
+    KS_REQUIRE(g && n && n_max >= 0 && (n_max == 0 || (alpha && beta)), KS_ERR_ARG,
+               "ks_cg_coefficients: null argument or n_max < 0");
+    cg_coefficients(g, n_max, alpha, beta, n);
+    return KS_SUCCESS;
+    KS_API_END
+}
+
 ks_status_t ks_stream_read(const void* src_dev, size_t bytes, hipStream_t stream)
 {
     KS_API_BEGIN

@@ -176,7 +176,8 @@ __global__ __launch_bounds__(kCgFuse) void cg_update_kernel(int vh, void* __rest
                                                             void* __restrict__ r,
                                                             CGState* __restrict__ st,
                                                             const double* __restrict__ pap_part,
-                                                            int npap, double* __restrict__ rr_part)
+                                                            int npap, double* __restrict__ rr_part,
+                                                            double* __restrict__ coef, int coef_cap)
 {
     using R = typename St<P>::R;
     constexpr int kX = P == KS_F64 ? KS_F64 : KS_F32;
@@ -202,6 +203,7 @@ __global__ __launch_bounds__(kCgFuse) void cg_update_kernel(int vh, void* __rest
         st->s_gate = ok ? 0 : 1;
         if (ok) {
             st->alpha = rho / pap;
+            if (st->iter < coef_cap) coef[2 * st->iter] = rho / pap;
         } else {
             st->status = isfinite(pap) ? KS_ERR_BREAKDOWN : KS_ERR_NONFINITE;
             st->gate = 1;
@@ -249,7 +251,8 @@ __global__ __launch_bounds__(kCgFuse) void cg_beta_xpay_kernel(int vh, const voi
                                                                void* __restrict__ p,
                                                                CGState* __restrict__ st,
                                                                const double* __restrict__ rr_part,
-                                                               int nrr)
+                                                               int nrr, double* __restrict__ coef,
+                                                               int coef_cap)
 {
     using R = typename St<P>::R;
     if (st->s_gate) return;
@@ -270,16 +273,19 @@ __global__ __launch_bounds__(kCgFuse) void cg_beta_xpay_kernel(int vh, const voi
     }
     const double rn = sqrt(rho_new);
     if (rho_new <= st->stop2 || rn < st->delta * maxr) {
-        // FP64 recomputation of r = b - A x decides (reliable update or final check)
+        // FP64 recomputation of r = b - A x decides (reliable update or final check); the
+        // step's beta is then not a CG coefficient
         if (lead) {
             st->ru_pending = 1;
             st->gate = 1;
+            if (st->s_iter < coef_cap) coef[2 * st->s_iter + 1] = __builtin_nan("");
         }
         return;
     }
     const double beta = rho_new / st->s_rho;
     const bool last = iter >= st->max_iter;
     if (lead) {
+        if (st->s_iter < coef_cap) coef[2 * st->s_iter + 1] = beta;
         st->beta = beta;
         st->rho = rho_new;
         st->maxr = fmax(maxr, rn);
@@ -410,25 +416,32 @@ void sub_norm_partials(int vh, const double* b, const double* ax, double* r, dou
 }
 
 void cg_update(int vh, ks_prec_t prec, void* x, const void* p, const void* q, void* r,
-               CGState* st, const double* pap_part, int npap, double* rr_part, hipStream_t s)
+               CGState* st, const double* pap_part, int npap, double* rr_part, double* coef,
+               int coef_cap, hipStream_t s)
 {
     const int nb = blocks_for(vh, kCgFuse);
     if (prec == KS_F64)
-        cg_update_kernel<KS_F64><<<nb, kCgFuse, 0, s>>>(vh, x, p, q, r, st, pap_part, npap, rr_part);
+        cg_update_kernel<KS_F64><<<nb, kCgFuse, 0, s>>>(vh, x, p, q, r, st, pap_part, npap, rr_part,
+                                                        coef, coef_cap);
     else if (prec == KS_F32)
-        cg_update_kernel<KS_F32><<<nb, kCgFuse, 0, s>>>(vh, x, p, q, r, st, pap_part, npap, rr_part);
+        cg_update_kernel<KS_F32><<<nb, kCgFuse, 0, s>>>(vh, x, p, q, r, st, pap_part, npap, rr_part,
+                                                        coef, coef_cap);
     else
-        cg_update_kernel<KS_F16><<<nb, kCgFuse, 0, s>>>(vh, x, p, q, r, st, pap_part, npap, rr_part);
+        cg_update_kernel<KS_F16><<<nb, kCgFuse, 0, s>>>(vh, x, p, q, r, st, pap_part, npap, rr_part,
+                                                        coef, coef_cap);
     KS_HIP(hipGetLastError());
 }
 
 void cg_beta_xpay(int vh, ks_prec_t prec, const void* r, void* p, CGState* st,
-                  const double* rr_part, hipStream_t s)
+                  const double* rr_part, double* coef, int coef_cap, hipStream_t s)
 {
     const int nb = blocks_for(vh, kCgFuse);
-    if (prec == KS_F64) cg_beta_xpay_kernel<KS_F64><<<nb, kCgFuse, 0, s>>>(vh, r, p, st, rr_part, nb);
-    else if (prec == KS_F32) cg_beta_xpay_kernel<KS_F32><<<nb, kCgFuse, 0, s>>>(vh, r, p, st, rr_part, nb);
-    else cg_beta_xpay_kernel<KS_F16><<<nb, kCgFuse, 0, s>>>(vh, r, p, st, rr_part, nb);
+    if (prec == KS_F64)
+        cg_beta_xpay_kernel<KS_F64><<<nb, kCgFuse, 0, s>>>(vh, r, p, st, rr_part, nb, coef, coef_cap);
+    else if (prec == KS_F32)
+        cg_beta_xpay_kernel<KS_F32><<<nb, kCgFuse, 0, s>>>(vh, r, p, st, rr_part, nb, coef, coef_cap);
+    else
+        cg_beta_xpay_kernel<KS_F16><<<nb, kCgFuse, 0, s>>>(vh, r, p, st, rr_part, nb, coef, coef_cap);
     KS_HIP(hipGetLastError());
 }
 

@@ -41,13 +41,16 @@ constexpr int kCgFuse = 1024;
 // sums the partials in the same order and takes alpha = rho / <p, q>; then x += alpha p (x:
 // FP64 planes, or in reduced precision x's FP32 increment field, see flush_dx),
 // r -= alpha q, and the |r|^2 partials to rr_part (blocks_for(vh, kCgFuse) of them).
-// Breakdown and a non-finite <p, q> gate the solver.
+// Breakdown and a non-finite <p, q> gate the solver.  Step k's alpha goes to coef[2k]
+// (k < coef_cap).
 void cg_update(int vh, ks_prec_t prec, void* x, const void* p, const void* q, void* r,
-               CGState* st, const double* pap_part, int npap, double* rr_part, hipStream_t s);
+               CGState* st, const double* pap_part, int npap, double* rr_part, double* coef,
+               int coef_cap, hipStream_t s);
 // The rest of the step: every block sums the |r|^2 partials; beta, the stopping and
-// reliable-update decisions, and p = r + beta p when the step goes on.
+// reliable-update decisions, and p = r + beta p when the step goes on.  Step k's beta goes to
+// coef[2k + 1] (NaN when the step ends in a reliable update or the final check).
 void cg_beta_xpay(int vh, ks_prec_t prec, const void* r, void* p, CGState* st,
-                  const double* rr_part, hipStream_t s);
+                  const double* rr_part, double* coef, int coef_cap, hipStream_t s);
 void xpay(int vh, ks_prec_t prec, const void* r, void* p, const CGState* st, hipStream_t s);
 void cg_reliable(const double* part, int n, CGState* st, int initial, hipStream_t s);
 void finish_to(const double* part, int n, double* out, hipStream_t s);

@@ -13,6 +13,9 @@ struct Workspace {
     int npart = 0;
     double* partials = nullptr;   // per-block partial sums
     double* rr_part = nullptr;    // |r|^2 partials of the fused CG step (blocks_for(Vh, kCgFuse))
+    double* cg_coef = nullptr;    // alpha_k, beta_k of the last CG run, interleaved
+    int cg_coef_cap = 0;          // steps it holds
+    int cg_coef_n = 0;            // steps recorded by the last run
     double* scal = nullptr;       // device scalars (after the partials)
     double* host_scal = nullptr;  // pinned
     CGState* st = nullptr;
@@ -61,6 +64,8 @@ void apply_A64(ks_gauge_t g, double sigma, const double* x, double* ax, hipStrea
                const int* gate);
 double true_resid2(ks_gauge_t g, double sigma, const double* b, const double* x, hipStream_t s);
 
+// alpha_k, beta_k (host arrays of n_max) of the last CG run on g; *n = steps copied
+void cg_coefficients(ks_gauge_t g, int n_max, double* alpha, double* beta, int* n);
 ks_status_t cg_core(ks_gauge_t g, double sigma, const double* b, double* x,
                     const ks_solver_params& prm, ks_solver_stats& stats, hipStream_t s);
 // M x = b with M = 2m + D on both parities (internal FP64 planes; x_e: initial guess in)

@@ -89,6 +89,7 @@ void workspace_free(Workspace* w)
     if (!w) return;
     device_free(w->partials);
     device_free(w->rr_part);
+    device_free(w->cg_coef);
     device_free(w->st);
     if (w->st_host) (void)hipHostFree(w->st_host);
     if (w->host_scal) (void)hipHostFree(w->host_scal);
@@ -175,6 +176,22 @@ void read_state(Workspace& w, hipStream_t s)
 }  // namespace
 
 // CG on internal FP64 planes: b (read), x (initial guess in, solution out).
+void cg_coefficients(ks_gauge_t g, int n_max, double* alpha, double* beta, int* n)
+{
+    *n = 0;
+    if (!g->ws || !g->ws->cg_coef) return;
+    Workspace& w = *g->ws;
+    const int k = std::min(n_max, w.cg_coef_n);
+    if (k <= 0) return;
+    std::vector<double> tmp(2 * (size_t)k);
+    KS_HIP(hipMemcpy(tmp.data(), w.cg_coef, sizeof(double) * 2 * (size_t)k, hipMemcpyDeviceToHost));
+    for (int j = 0; j < k; ++j) {
+        alpha[j] = tmp[2 * j];
+        beta[j] = tmp[2 * j + 1];
+    }
+    *n = k;
+}
+
 ks_status_t cg_core(ks_gauge_t g, double sigma, const double* b, double* x,
                     const ks_solver_params& prm, ks_solver_stats& stats, hipStream_t s)
 {
@@ -208,6 +225,17 @@ ks_status_t cg_core(ks_gauge_t g, double sigma, const double* b, double* x,
     *w.st_host = init;
     KS_HIP(hipMemcpyAsync(w.st, w.st_host, sizeof(CGState), hipMemcpyHostToDevice, s));
 
+    // alpha_k, beta_k of every step (up to 2^20 of them), for the Lanczos estimate of the
+    // spectrum from an unbroken FP64 run
+    const int want = std::min(prm.max_iter, 1 << 20);
+    if (w.cg_coef_cap < want) {
+        device_free(w.cg_coef);
+        w.cg_coef = nullptr;
+        w.cg_coef_cap = 0;
+        w.cg_coef = static_cast<double*>(device_alloc(sizeof(double) * 2 * (size_t)want));
+        w.cg_coef_cap = want;
+    }
+    w.cg_coef_n = 0;
     // reduced precision: x's increments accumulate in FP32 and are added into the FP64 x
     // before every reliable update and at the end
     const bool sloppy = P != KS_F64;
@@ -239,8 +267,9 @@ ks_status_t cg_core(ks_gauge_t g, double sigma, const double* b, double* x,
         a2.dot_partials = w.partials;
         a2.gate = &w.st->gate;
         dslash(g, P, RC, a2, s);
-        cg_update(vh, P, xu, ps, qs, rs, w.st, w.partials, dslash_blocks(g, P, RC), w.rr_part, s);
-        cg_beta_xpay(vh, P, rs, ps, w.st, w.rr_part, s);
+        cg_update(vh, P, xu, ps, qs, rs, w.st, w.partials, dslash_blocks(g, P, RC), w.rr_part,
+                  w.cg_coef, w.cg_coef_cap, s);
+        cg_beta_xpay(vh, P, rs, ps, w.st, w.rr_part, w.cg_coef, w.cg_coef_cap, s);
     };
 
     reliable(1);
@@ -292,6 +321,7 @@ ks_status_t cg_core(ks_gauge_t g, double sigma, const double* b, double* x,
     flush();   // x = the last iterate also when the loop ended on an error
     read_state(w, s);
     const CGState& h = *w.st_host;
+    w.cg_coef_n = std::min(h.iter, w.cg_coef_cap);
     stats.iters = h.iter;
     stats.reliable_updates = ru;
     stats.restarts = restarts;

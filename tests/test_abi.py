@@ -80,3 +80,11 @@ def test_stream_copy_argument_checks(libks):
         assert libks.ks_stream_read(src, n, None) == -1
     assert libks.ks_stream_read(None, 16, None) == -1
     assert libks.ks_stream_read(None, 0, None) == 0
+
+
+def test_cg_coefficients_argument_checks(libks):
+    import ctypes
+    n = ctypes.c_int(7)
+    assert libks.ks_cg_coefficients(None, 0, None, None, ctypes.byref(n)) == -1
+    assert libks.ks_cg_coefficients(ctypes.c_void_p(16), -1, None, None, ctypes.byref(n)) == -1
+    assert libks.ks_cg_coefficients(ctypes.c_void_p(16), 4, None, None, ctypes.byref(n)) == -1

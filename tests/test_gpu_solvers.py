@@ -71,6 +71,30 @@ def test_cg_f64_iterations_match_oracle(ks, cfg1):
     assert abs(res.stats["iters"] - info.iters) <= 1
 
 
+def test_cg_coefficients_match_oracle(ks, cfg1):
+    """The FP64 run's recorded alpha_k, beta_k are the oracle CG's (the two differ only in
+    summation order), so their Lanczos extremes agree; a reduced-precision run marks the
+    steps that ended in a reliable update with beta = NaN."""
+    g, G, b, _, _ = cfg1
+    announce("cg coefficients")
+    _, info = oracle.cg(g, 0.04, b, 1e-10)
+    x, res = solve(ks, G, 0.1, b, tol=1e-10, check_every=4)
+    alpha, beta = G.cg_coefficients()
+    assert len(alpha) == res.stats["iters"]
+    k = min(len(alpha), len(info.alpha)) - 1
+    assert np.allclose(alpha[:20], info.alpha[:20], rtol=1e-10, atol=0)
+    assert np.allclose(beta[:20], info.beta[:20], rtol=1e-10, atol=0)
+    lo, hi = oracle.lanczos_extremes(alpha[:k], beta[:k])
+    lo_o, hi_o = oracle.lanczos_extremes(info.alpha[:k], info.beta[:k])
+    assert abs(lo - lo_o) <= 1e-6 * lo_o and abs(hi - hi_o) <= 1e-6 * hi_o
+    assert 0.04 * (1 - 1e-9) <= lo < hi
+    x, res = solve(ks, G, 0.1, b, tol=1e-10, inner="f32", check_every=4)
+    alpha, beta = G.cg_coefficients()
+    assert len(alpha) == res.stats["iters"]
+    assert np.all(np.isfinite(alpha))
+    assert np.isnan(beta).sum() == res.stats["reliable_updates"] + res.stats["restarts"] + 1
+
+
 def test_cg_initial_guess(ks, cfg1):
     g, G, b, xo, _ = cfg1
     announce("cg initial guess")
