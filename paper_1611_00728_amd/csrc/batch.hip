@@ -94,10 +94,8 @@ __device__ __forceinline__ bool lattice_busy(const BatchPair* pairs, int p0, int
 }
 
 // out_r = D in_r for every RHS r of the site (XPAY: out_r = sigma_r x_r - D in_r, with
-// per-tile partial sums of Re<x_r, out_r>).  RU selects the FP64 reliable-update form, which
-// works only on lattices with a pair whose update is due; otherwise lattices with a pair
-// still iterating.
-template <int P, int R, bool XPAY, bool RU, int NT>
+// per-tile partial sums of Re<x_r, out_r>), on lattices with a pair still iterating.
+template <int P, int R, bool XPAY, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void batch_dslash_kernel(
     const LatDesc* __restrict__ lats, const int2* __restrict__ tiles, int ntiles, int par,
     const char* __restrict__ in, char* __restrict__ out, const char* __restrict__ xv,
@@ -108,7 +106,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void ba
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int2 tl = tiles[t];
         const LatDesc& L = lats[tl.x];
-        const bool busy = lattice_busy(pairs, L.pair0, R, RU);
+        const bool busy = lattice_busy(pairs, L.pair0, R, false);
         if (!busy) {
             if (XPAY && threadIdx.x < R) partials[(size_t)t * R + threadIdx.x] = 0.0;
             continue;
@@ -640,22 +638,22 @@ __global__ void batch_io_kernel(const LatDesc* __restrict__ lats, char* __restri
 
 template <int R, int NT>
 struct BatchLaunch {
-    static void dslash(BatchCtx& c, int prec, bool xpay, bool ru, int par, const char* in, char* out,
+    static void dslash(BatchCtx& c, int prec, bool xpay, int par, const char* in, char* out,
                        const char* x, hipStream_t s)
     {
         const int nt = c.ntiles[c.tile_idx];
         const int2* tl = c.tiles[c.tile_idx];
         const int grid = c.grid(nt);
         double* part = c.partials;
-#define KS_BD(P, X, U)                                                                         \
-    batch_dslash_kernel<P, R, X, U, NT><<<grid, NT, 0, s>>>(c.lats_dev, tl, nt, par, in, out, x, \
-                                                          c.pairs, part)
+#define KS_BD(P, X)                                                                            \
+    batch_dslash_kernel<P, R, X, NT><<<grid, NT, 0, s>>>(c.lats_dev, tl, nt, par, in, out, x,   \
+                                                       c.pairs, part)
         if (prec == KS_F64) {
-            if (xpay) { if (ru) KS_BD(KS_F64, true, true); else KS_BD(KS_F64, true, false); }
-            else { if (ru) KS_BD(KS_F64, false, true); else KS_BD(KS_F64, false, false); }
+            if (xpay) KS_BD(KS_F64, true);
+            else KS_BD(KS_F64, false);
         } else {
-            if (xpay) { if (ru) KS_BD(KS_F32, true, true); else KS_BD(KS_F32, true, false); }
-            else { if (ru) KS_BD(KS_F32, false, true); else KS_BD(KS_F32, false, false); }
+            if (xpay) KS_BD(KS_F32, true);
+            else KS_BD(KS_F32, false);
         }
 #undef KS_BD
         KS_HIP(hipGetLastError());
@@ -669,8 +667,8 @@ struct BatchLaunch {
         const int np = c.npairs;
         const int P = c.prec;
         // inner A-apply
-        dslash(c, P, false, false, 1, c.ps, c.ts, nullptr, s);
-        dslash(c, P, true, false, 0, c.ts, c.qs, c.ps, s);
+        dslash(c, P, false, 1, c.ps, c.ts, nullptr, s);
+        dslash(c, P, true, 0, c.ts, c.qs, c.ps, s);
         batch_alpha_kernel<<<np, kFin, 0, s>>>(c.lats_dev, R, c.pairs, c.partials);
         if (P == KS_F64)
             batch_update_kernel<KS_F64, R, NT><<<grid, NT, 0, s>>>(c.lats_dev, tl, nt, c.x64, c.ps, c.qs, c.rs, c.pairs, c.partials);
@@ -729,7 +727,7 @@ static void dispatch(BatchCtx& c, int what, hipStream_t s, int xpay_or_init = 0)
     if (nt == NTV) {                                                                    \
         if (what == 0) BatchLaunch<R, NTV>::step(c, s);                                 \
         else if (what == 1) BatchLaunch<R, NTV>::start(c, s);                           \
-        else BatchLaunch<R, NTV>::dslash(c, c.prec, xpay_or_init != 0, false, 1, c.ps, c.ts, nullptr, s); \
+        else BatchLaunch<R, NTV>::dslash(c, c.prec, xpay_or_init != 0, 1, c.ps, c.ts, nullptr, s); \
         return;                                                                         \
     }
     KS_DISP(64)
