@@ -467,16 +467,37 @@ __device__ __forceinline__ double pair_sum(const LatDesc& L, const double* part,
     return block_sum<kFin>(s);
 }
 
-__global__ __launch_bounds__(kFin) void batch_alpha_kernel(const LatDesc* __restrict__ lats, int R,
+// The scalar steps run one block of kLat threads per lattice: one pass over the lattice's tile
+// partials gives the sums of all its R pairs (thread j adds tiles j, j + kLat, ... in order,
+// then a fixed tree per pair), so a lattice with many tiles is summed as fast as a small one.
+constexpr int kLat = 1024;
+
+__device__ __forceinline__ void lattice_sums(const LatDesc& L, const double* __restrict__ part,
+                                             int R, double* tot)
+{
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int t = L.tile_begin + threadIdx.x; t < L.tile_end; t += kLat)
+        for (int r = 0; r < R; ++r) s[r] += part[(size_t)t * R + r];
+    for (int r = 0; r < R; ++r) {
+        const double v = block_sum<kLat>(s[r]);
+        if (threadIdx.x == 0) tot[r] = v;
+        __syncthreads();   // block_sum's scratch is reused by the next pair; tot is read next
+    }
+}
+
+// alpha = rho / <p, A p> per pair (thread r of the lattice's block takes pair r)
+__global__ __launch_bounds__(kLat) void batch_alpha_kernel(const LatDesc* __restrict__ lats, int R,
                                                            BatchPair* __restrict__ pairs,
                                                            const double* __restrict__ part)
 {
-    const int pi = blockIdx.x;
-    BatchPair& q = pairs[pi];
+    const LatDesc& L = lats[blockIdx.x];
+    if (!lattice_busy(pairs, L.pair0, R, false)) return;
+    __shared__ double tot[4];
+    lattice_sums(L, part, R, tot);
+    if (threadIdx.x >= R) return;
+    BatchPair& q = pairs[L.pair0 + threadIdx.x];
     if (q.done) return;
-    const LatDesc& L = lats[pi / R];
-    const double pap = pair_sum(L, part, R, pi % R);
-    if (threadIdx.x != 0) return;
+    const double pap = tot[threadIdx.x];
     q.ru_now = 0;
     if (!isfinite(pap) || !(pap > 0.0)) {
         q.status = isfinite(pap) ? KS_ERR_BREAKDOWN : KS_ERR_NONFINITE;
@@ -494,17 +515,14 @@ __global__ __launch_bounds__(kFin) void batch_alpha_kernel(const LatDesc* __rest
 // number of its pairs that take part, so when one pair's residual has fallen by delta every
 // unfinished pair takes the update with it (the right-hand sides then stay in step instead of
 // each paying its own).  Pairs without an update continue: beta = |r|^2 / rho, rho = |r|^2.
-__global__ __launch_bounds__(kFin) void batch_beta_kernel(const LatDesc* __restrict__ lats, int R,
+__global__ __launch_bounds__(kLat) void batch_beta_kernel(const LatDesc* __restrict__ lats, int R,
                                                           BatchPair* __restrict__ pairs,
                                                           const double* __restrict__ part)
 {
     const LatDesc& L = lats[blockIdx.x];
+    if (!lattice_busy(pairs, L.pair0, R, false)) return;
     __shared__ double rn[4];
-    for (int r = 0; r < R; ++r) {
-        const double s = pair_sum(L, part, R, r);
-        if (threadIdx.x == 0) rn[r] = s;
-        __syncthreads();   // block_sum's scratch is reused by the next pair
-    }
+    lattice_sums(L, part, R, rn);
     if (threadIdx.x != 0) return;
     bool drop = false;
     for (int r = 0; r < R; ++r) {
@@ -533,17 +551,21 @@ __global__ __launch_bounds__(kFin) void batch_beta_kernel(const LatDesc* __restr
     }
 }
 
-__global__ __launch_bounds__(kFin) void batch_reliable_kernel(const LatDesc* __restrict__ lats, int R,
+// After r = b - A x in FP64 for the lattices with an update due: each such pair either
+// finishes or continues with beta = |r|^2 / rho (thread r of the lattice's block, pair r)
+__global__ __launch_bounds__(kLat) void batch_reliable_kernel(const LatDesc* __restrict__ lats, int R,
                                                               BatchPair* __restrict__ pairs,
                                                               const double* __restrict__ part,
                                                               int initial)
 {
-    const int pi = blockIdx.x;
-    BatchPair& q = pairs[pi];
+    const LatDesc& L = lats[blockIdx.x];
+    if (!lattice_busy(pairs, L.pair0, R, true)) return;
+    __shared__ double tot[4];
+    lattice_sums(L, part, R, tot);
+    if (threadIdx.x >= R) return;
+    BatchPair& q = pairs[L.pair0 + threadIdx.x];
     if (!q.ru_now || q.done) return;
-    const LatDesc& L = lats[pi / R];
-    const double r2 = pair_sum(L, part, R, pi % R);
-    if (threadIdx.x != 0) return;
+    const double r2 = tot[threadIdx.x];
     q.true_r2 = r2;
     if (!initial) q.ru += 1;
     if (!isfinite(r2)) {
@@ -579,10 +601,41 @@ __global__ void batch_census_kernel(const BatchPair* __restrict__ pairs, int n, 
 
 __global__ void batch_clock_kernel(unsigned long long* out) { *out = wall_clock64(); }
 
-// Per pair: |b|^2 from the FP64 arena, and the initial scalars (one block per pair).
+// Per tile: partial sums of |b_r|^2 over its sites, for every RHS r (FP64 arena).
+template <int R, int NT>
+__global__ __launch_bounds__(NT) void batch_b2_kernel(const LatDesc* __restrict__ lats,
+                                                     const int2* __restrict__ tiles,
+                                                     const char* __restrict__ b64,
+                                                     double* __restrict__ partials)
+{
+    const int t = blockIdx.x;
+    const int2 tl = tiles[t];
+    const LatDesc& L = lats[tl.x];
+    const int vh = L.g.Vh;
+    const int h = tl.y + threadIdx.x;
+    double nrm[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) nrm[k] = 0.0;
+    if (h < vh) {
+        cx<double> v[3][R];
+        MVec<KS_F64, R>::load(b64, L.vec_off, vh, h, v);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int k = 0; k < R; ++k) nrm[k] += v[c][k].r * v[c][k].r + v[c][k].i * v[c][k].i;
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const double s = block_sum<NT>(nrm[k]);
+        if (threadIdx.x == 0) partials[(size_t)t * R + k] = s;
+        __syncthreads();
+    }
+}
+
+// Per pair: |b|^2 (the tile partials in tile order) and the initial scalars (one block per pair).
 __global__ __launch_bounds__(kFin) void batch_init_pairs_kernel(const LatDesc* __restrict__ lats,
                                                                 int R, BatchPair* __restrict__ pairs,
-                                                                const char* __restrict__ b64,
+                                                                const double* __restrict__ part,
                                                                 const double* __restrict__ param,
                                                                 int npairs, double delta,
                                                                 int max_iter,
@@ -590,15 +643,7 @@ __global__ __launch_bounds__(kFin) void batch_init_pairs_kernel(const LatDesc* _
 {
     const int pi = blockIdx.x;
     const LatDesc& L = lats[pi / R];
-    const int r = pi % R;
-    const int vh = L.g.Vh;
-    double s = 0.0;
-    for (int j = threadIdx.x; j < 3 * vh; j += kFin) {
-        const int k = j / vh, h = j - k * vh;
-        const double2 v = reinterpret_cast<const double2*>(b64)[(L.vec_off * 3 + (size_t)k * vh + h) * R + r];
-        s += v.x * v.x + v.y * v.y;
-    }
-    s = block_sum<kFin>(s);
+    const double s = pair_sum(L, part, R, pi % R);
     if (threadIdx.x != 0) return;
     BatchPair q{};
     q.sigma = param[pi];
@@ -664,17 +709,17 @@ struct BatchLaunch {
         const int2* tl = c.tiles[c.tile_idx];
         const int grid = nt;   // streaming vector kernels: one block per tile (the tuned
                                 // persistent schedule is for the hopping terms)
-        const int np = c.npairs;
         const int P = c.prec;
         // inner A-apply
         dslash(c, P, false, 1, c.ps, c.ts, nullptr, s);
         dslash(c, P, true, 0, c.ts, c.qs, c.ps, s);
-        batch_alpha_kernel<<<np, kFin, 0, s>>>(c.lats_dev, R, c.pairs, c.partials);
+        const int nlat = (int)c.lats_host.size();
+        batch_alpha_kernel<<<nlat, kLat, 0, s>>>(c.lats_dev, R, c.pairs, c.partials);
         if (P == KS_F64)
             batch_update_kernel<KS_F64, R, NT><<<grid, NT, 0, s>>>(c.lats_dev, tl, nt, c.x64, c.ps, c.qs, c.rs, c.pairs, c.partials);
         else
             batch_update_kernel<KS_F32, R, NT><<<grid, NT, 0, s>>>(c.lats_dev, tl, nt, c.x64, c.ps, c.qs, c.rs, c.pairs, c.partials);
-        batch_beta_kernel<<<(int)c.lats_host.size(), kFin, 0, s>>>(c.lats_dev, R, c.pairs, c.partials);
+        batch_beta_kernel<<<nlat, kLat, 0, s>>>(c.lats_dev, R, c.pairs, c.partials);
         reliable(c, 0, s);
         if (P == KS_F64)
             batch_xpay_kernel<KS_F64, R, NT><<<grid, NT, 0, s>>>(c.lats_dev, tl, nt, c.rs, c.ps, c.pairs, 0);
@@ -695,11 +740,18 @@ struct BatchLaunch {
         batch_dslash_ru_kernel<R, true><<<kRuGrid, 256, 0, s>>>(c.lats_dev, nlat, 0, c.t64, c.ax64,
                                                                 c.x64, c.pairs);
         batch_resid_kernel<R, NT><<<grid, NT, 0, s>>>(c.lats_dev, tl, nt, c.b64, c.ax64, c.r64, c.pairs, c.partials);
-        batch_reliable_kernel<<<c.npairs, kFin, 0, s>>>(c.lats_dev, R, c.pairs, c.partials, initial);
+        batch_reliable_kernel<<<(int)c.lats_host.size(), kLat, 0, s>>>(c.lats_dev, R, c.pairs, c.partials,
+                                                                      initial);
         if (c.prec == KS_F64)
             batch_load_r_kernel<KS_F64, R, NT><<<grid, NT, 0, s>>>(c.lats_dev, tl, nt, c.r64, c.rs, c.pairs);
         else
             batch_load_r_kernel<KS_F32, R, NT><<<grid, NT, 0, s>>>(c.lats_dev, tl, nt, c.r64, c.rs, c.pairs);
+        KS_HIP(hipGetLastError());
+    }
+    static void b2(BatchCtx& c, hipStream_t s)
+    {
+        const int nt = c.ntiles[c.tile_idx];
+        batch_b2_kernel<R, NT><<<nt, NT, 0, s>>>(c.lats_dev, c.tiles[c.tile_idx], c.b64, c.partials);
         KS_HIP(hipGetLastError());
     }
     static void start(BatchCtx& c, hipStream_t s)
@@ -727,6 +779,7 @@ static void dispatch(BatchCtx& c, int what, hipStream_t s, int xpay_or_init = 0)
     if (nt == NTV) {                                                                    \
         if (what == 0) BatchLaunch<R, NTV>::step(c, s);                                 \
         else if (what == 1) BatchLaunch<R, NTV>::start(c, s);                           \
+        else if (what == 3) BatchLaunch<R, NTV>::b2(c, s);                              \
         else BatchLaunch<R, NTV>::dslash(c, c.prec, xpay_or_init != 0, 1, c.ps, c.ts, nullptr, s); \
         return;                                                                         \
     }
@@ -1008,7 +1061,8 @@ ks_status_t batch_solve_pairs(BatchCtx& c, const double* sigma, const double* to
     batch_io(c, c.b64, reinterpret_cast<const void* const*>(b), 1, s);
     batch_io(c, c.x64, reinterpret_cast<const void* const*>(x), 1, s);
     batch_clock_kernel<<<1, 1, 0, s>>>(c.clock);
-    batch_init_pairs_kernel<<<c.npairs, kFin, 0, s>>>(c.lats_dev, c.nrhs, c.pairs, c.b64,
+    run(c, 3, s);   // |b|^2 tile partials
+    batch_init_pairs_kernel<<<c.npairs, kFin, 0, s>>>(c.lats_dev, c.nrhs, c.pairs, c.partials,
                                                       c.pair_param, c.npairs,
                                                       c.prec == KS_F64 ? 0.0 : prm.delta,
                                                       prm.max_iter, c.b2);
