@@ -136,7 +136,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void ba
             for (int k = 0; k < 3; ++k)
 #pragma unroll
                 for (int r = 0; r < R; ++r) res[k][r] = {0, 0};
-#pragma unroll 1
+            // FP32: four hops per pass keep four link and neighbour loads in flight
+            // (measured best; a full unroll is slower); FP64 at four hops would spill
+            constexpr int kHopUnroll = P == KS_F64 ? 1 : 4;
+#pragma unroll kHopUnroll
             for (int s = 0; s < 16; ++s) {
                 cx<T> m[9];
                 if (s < 8) load_link<P, 9>(fat, s, vh, h, m);
