@@ -55,7 +55,8 @@ __global__ __launch_bounds__(kBlock) void dslash_multi_kernel(Geom g, int par,
                                                               float naik_scale)
 {
     const int vh = g.Vh;
-    const int h = blockIdx.x * kBlock + threadIdx.x;
+    // each XCD takes one contiguous range of sites, so its L2 holds most neighbour vectors
+    const int h = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (h >= vh) return;
     int c[4];
     cb_coords(g, h, par, c);
@@ -115,15 +116,24 @@ void launch_multi(int k, unsigned nb, const Geom& G, const LinkStore& st, const 
     launch_multi_k<kMultiMax>(k, nb, G, st, mv, s);
 }
 
-// thread per (direction mu, lexicographic site x): t = mu V + x
-__global__ __launch_bounds__(kBlock) void force_outer_kernel(Geom g, Terms terms,
-                                                             double2* __restrict__ fv,
-                                                             double2* __restrict__ fw)
+// One block: kOuterSites consecutive lexicographic sites x the four directions (wave w takes
+// mu = w), so the four waves that read a site's vectors share them through one CU's L1; blocks
+// are remapped so that each XCD walks one contiguous range of sites.  Thread (mu, x) writes
+// link t = mu V + x.
+constexpr int kOuterSites = 64;
+
+__global__ __launch_bounds__(4 * kOuterSites) void force_outer_kernel(Geom g, Terms terms,
+                                                                      double2* __restrict__ fv,
+                                                                      double2* __restrict__ fw)
 {
-    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= 4L * g.V) return;
-    const int mu = (int)(t / g.V);
-    const int x = (int)(t - (long)mu * g.V);
+    const int mu = threadIdx.x / kOuterSites;
+    const int lane = threadIdx.x % kOuterSites;
+    const long x0 = (long)xcd_tile(blockIdx.x, gridDim.x) * kOuterSites;
+    const bool full = x0 + kOuterSites <= g.V;   // uniform over the block
+    const long xl = x0 + lane;
+    if (!full && xl >= g.V) return;               // only in a ragged last block
+    const int x = (int)(xl < g.V ? xl : g.V - 1);
+    const long t = (long)mu * g.V + x;
     int c[4];
     int r = x;
 #pragma unroll
@@ -164,6 +174,29 @@ __global__ __launch_bounds__(kBlock) void force_outer_kernel(Geom g, Terms terms
         }
     }
     const double eps = par ? -1.0 : 1.0;
+    if (full) {
+        // stage each wave's 64 consecutive links in LDS, then store them as one contiguous,
+        // streamed run (a lane's own 144 bytes at a 144-byte lane stride, stored directly,
+        // measured slower; streamed without staging, far slower)
+        __shared__ dvec2 stage[4][kOuterSites * 9];
+        dvec2* sw = stage[mu];
+        dvec2* o1 = reinterpret_cast<dvec2*>(fv + ((size_t)mu * g.V + x0) * 9);
+        dvec2* o3 = reinterpret_cast<dvec2*>(fw + ((size_t)mu * g.V + x0) * 9);
+#pragma unroll
+        for (int e = 0; e < 9; ++e) sw[lane * 9 + e] = dvec2{eps * a1[e].r, eps * a1[e].i};
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 9; ++k)
+            __builtin_nontemporal_store(sw[k * kOuterSites + lane], o1 + k * kOuterSites + lane);
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < 9; ++e) sw[lane * 9 + e] = dvec2{eps * a3[e].r, eps * a3[e].i};
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 9; ++k)
+            __builtin_nontemporal_store(sw[k * kOuterSites + lane], o3 + k * kOuterSites + lane);
+        return;
+    }
     double2* o1 = fv + (size_t)t * 9;
     double2* o3 = fw + (size_t)t * 9;
 #pragma unroll
@@ -209,8 +242,7 @@ void force_core(ks_gauge_t g, int nterm, const double* residues, const double* c
         launch_multi(k, nb, G, st, mv, s);
         KS_HIP(hipGetLastError());
     }
-    const long n = 4L * G.V;
-    force_outer_kernel<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(
+    force_outer_kernel<<<(unsigned)((G.V + kOuterSites - 1) / kOuterSites), 4 * kOuterSites, 0, s>>>(
         G, terms, reinterpret_cast<double2*>(force_fat), reinterpret_cast<double2*>(force_naik));
     KS_HIP(hipGetLastError());
 }

@@ -39,7 +39,8 @@ __global__ __launch_bounds__(kNT) void net_layer_kernel(Geom g, const float2* __
                                                         const float2* __restrict__ w)
 {
     const int vh = g.Vh;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    // each XCD takes one contiguous range of sites, so its L2 holds most neighbour activations
+    const int t = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (t >= 2 * vh) return;
     const int par = t >= vh ? 1 : 0;
     const int h = t - par * vh;

@@ -21,7 +21,9 @@ def ks():
     return ks
 
 
-@pytest.mark.parametrize("dims,nterm", [((4, 4, 4, 6), 3), ((8, 6, 10, 12), 9), ((4, 4, 4, 4), 1)])
+# 6x6x6x4 has 864 sites: its last block of 64 sites is ragged (the other lattices fill theirs)
+@pytest.mark.parametrize("dims,nterm", [((4, 4, 4, 6), 3), ((8, 6, 10, 12), 9), ((4, 4, 4, 4), 1),
+                                        ((6, 6, 6, 4), 2)])
 def test_force_matches_oracle(ks, dims, nterm):
     announce("force", dims, nterm)
     import torch
