@@ -84,13 +84,18 @@ struct MVec {
     }
 };
 
+// R <= 4: the flags of all pairs are loaded together, not one after another
 __device__ __forceinline__ bool lattice_busy(const BatchPair* pairs, int p0, int R, bool ru)
 {
-    for (int r = 0; r < R; ++r) {
-        const BatchPair& q = pairs[p0 + r];
-        if (ru ? (q.ru_now && !q.done) : !q.done) return true;
+    bool busy = false;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        if (r < R) {
+            const BatchPair& q = pairs[p0 + r];
+            busy = busy || (ru ? (q.ru_now && !q.done) : !q.done);
+        }
     }
-    return false;
+    return busy;
 }
 
 // out_r = D in_r for every RHS r of the site (XPAY: out_r = sigma_r x_r - D in_r, with
@@ -478,14 +483,24 @@ constexpr int kLat = 1024;
 __device__ __forceinline__ void lattice_sums(const LatDesc& L, const double* __restrict__ part,
                                              int R, double* tot)
 {
+    __shared__ double red[kLat / 64][4];
     double s[4] = {0.0, 0.0, 0.0, 0.0};
     for (int t = L.tile_begin + threadIdx.x; t < L.tile_end; t += kLat)
         for (int r = 0; r < R; ++r) s[r] += part[(size_t)t * R + r];
-    for (int r = 0; r < R; ++r) {
-        const double v = block_sum<kLat>(s[r]);
-        if (threadIdx.x == 0) tot[r] = v;
-        __syncthreads();   // block_sum's scratch is reused by the next pair; tot is read next
+    // every pair's wave sums in one LDS round; thread r then adds pair r's waves in order
+#pragma unroll
+    for (int r = 0; r < 4; ++r) s[r] = wave_sum(s[r]);
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) red[threadIdx.x >> 6][r] = s[r];
+    __syncthreads();
+    if (threadIdx.x < R) {
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < kLat / 64; ++k) v += red[k][threadIdx.x];
+        tot[threadIdx.x] = v;
     }
+    __syncthreads();
 }
 
 // alpha = rho / <p, A p> per pair (thread r of the lattice's block takes pair r)
@@ -526,32 +541,31 @@ __global__ __launch_bounds__(kLat) void batch_beta_kernel(const LatDesc* __restr
     if (!lattice_busy(pairs, L.pair0, R, false)) return;
     __shared__ double rn[4];
     lattice_sums(L, part, R, rn);
-    if (threadIdx.x != 0) return;
-    bool drop = false;
-    for (int r = 0; r < R; ++r) {
-        BatchPair& q = pairs[L.pair0 + r];
-        if (q.done) continue;
-        q.iter += 1;
-        q.rn = rn[r];
-        if (!isfinite(q.rn)) {
-            q.status = KS_ERR_NONFINITE;
-            q.done = 1;
-            q.t_done = wall_clock64();
-            continue;
+    if (threadIdx.x >= 64) return;   // lane r of the first wave takes pair r
+    const int r = threadIdx.x;
+    BatchPair* q = r < R ? &pairs[L.pair0 + r] : nullptr;
+    bool live = q && !q->done;
+    if (live) {
+        q->iter += 1;
+        q->rn = rn[r];
+        if (!isfinite(q->rn)) {
+            q->status = KS_ERR_NONFINITE;
+            q->done = 1;
+            q->t_done = wall_clock64();
+            live = false;
+        } else if (q->rn <= q->stop2 || q->iter >= q->max_iter) {
+            q->ru_now = 1;
+        } else if (sqrt(q->rn) < q->delta * q->maxr) {
+            q->ru_now = 2;
         }
-        if (q.rn <= q.stop2 || q.iter >= q.max_iter) q.ru_now = 1;
-        else if (sqrt(q.rn) < q.delta * q.maxr) q.ru_now = 2;
-        drop = drop || q.ru_now == 2;
     }
-    for (int r = 0; r < R; ++r) {
-        BatchPair& q = pairs[L.pair0 + r];
-        if (q.done) continue;
-        if (drop && q.ru_now == 0) q.ru_now = 1;
-        if (q.ru_now) continue;
-        q.beta = q.rn / q.rho;
-        q.rho = q.rn;
-        q.maxr = fmax(q.maxr, sqrt(q.rn));
-    }
+    const bool drop = __any(live && q->ru_now == 2);
+    if (!live) return;
+    if (drop && q->ru_now == 0) q->ru_now = 1;
+    if (q->ru_now) return;
+    q->beta = q->rn / q->rho;
+    q->rho = q->rn;
+    q->maxr = fmax(q->maxr, sqrt(q->rn));
 }
 
 // After r = b - A x in FP64 for the lattices with an update due: each such pair either
