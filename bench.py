@@ -48,12 +48,15 @@ def model_bytes_per_site(prec: str, recon: int) -> int:
 
 # one batched CG step for 4 right-hand sides, FP32 vectors and links, FP64 x, per even site:
 # two multi-RHS hopping terms (links 1152 + 4 x 24 in + 4 x 24 out, the second also reading
-# 4 x 24 of p), the x/r update (p, q, r read, r written: 4 x 4 x 24; x read and written:
-# 2 x 4 x 48) and p = r + beta p (3 x 4 x 24)
-BATCH_STEP_BYTES = 1344 + 1440 + 768 + 288
-# one FP64 reliable update for 4 right-hand sides: two FP64 multi-RHS hopping terms, r = b - Ax
-# (2 reads, 1 write of 4 x 48) and the conversion to FP32 (4 x 48 read, 4 x 24 read/written)
-BATCH_RU_BYTES = (2304 + 2 * 4 * 48) * 2 + 4 * 48 + 3 * 4 * 48 + 4 * 48 + 2 * 4 * 24
+# 4 x 24 of p), the x/r update (p, q, r read, r written: 4 x 4 x 24; x's FP32 increments read
+# and written: 2 x 4 x 24) and p = r + beta p (3 x 4 x 24)
+BATCH_STEP_BYTES = 1344 + 1440 + 576 + 288
+# one FP64 reliable update for 4 right-hand sides: the increments added into the FP64 x
+# (x read and written 2 x 4 x 48, increments read and cleared 2 x 4 x 24), two FP64 multi-RHS
+# hopping terms, r = b - Ax (2 reads, 1 write of 4 x 48) and the conversion to FP32 (4 x 48
+# read, 4 x 24 read/written)
+BATCH_RU_BYTES = (2 * 4 * 48 + 2 * 4 * 24 + (2304 + 2 * 4 * 48) * 2 + 4 * 48 + 3 * 4 * 48 +
+                  4 * 48 + 2 * 4 * 24)
 # network (per site of the full lattice): four layers, each reading its site's 8 stored FP32
 # fat links (4 forward, 4 backward: 8 x 72 bytes) and its input channels and writing its
 # output channels (FP32 complex colour vectors, 24 bytes each): 1->8, 8->8, 8->8, 8->1

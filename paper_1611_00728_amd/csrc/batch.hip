@@ -316,12 +316,12 @@ __global__ __launch_bounds__(NT) void batch_update_kernel(const LatDesc* __restr
 #pragma unroll
         for (int k = 0; k < R; ++k) nrm[k] = 0.0;
         if (h < vh) {
-            cx<T> pv[3][R], qv[3][R], rv[3][R];
-            cx<double> xv[3][R];
+            // xv: x itself (FP64), or x's FP32 increments since the last reliable update
+            cx<T> pv[3][R], qv[3][R], rv[3][R], xv[3][R];
             MVec<P, R>::load(p, L.vec_off, vh, h, pv);
             MVec<P, R>::load(q, L.vec_off, vh, h, qv);
             MVec<P, R>::load(r, L.vec_off, vh, h, rv);
-            MVec<KS_F64, R>::load(x, L.vec_off, vh, h, xv);
+            MVec<P, R>::load(x, L.vec_off, vh, h, xv);
 #pragma unroll
             for (int k = 0; k < R; ++k) {
                 const BatchPair& pp = pairs[L.pair0 + k];
@@ -329,18 +329,17 @@ __global__ __launch_bounds__(NT) void batch_update_kernel(const LatDesc* __restr
                 // maintained (never written for a pair that starts finished), so it must not
                 // enter even with a zero step
                 if (pp.done) continue;
-                const double a = pp.alpha;
-                const T af = (T)a;
+                const T af = (T)pp.alpha;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    xv[c][k].r = fma(a, (double)pv[c][k].r, xv[c][k].r);
-                    xv[c][k].i = fma(a, (double)pv[c][k].i, xv[c][k].i);
+                    xv[c][k].r = fma(af, pv[c][k].r, xv[c][k].r);
+                    xv[c][k].i = fma(af, pv[c][k].i, xv[c][k].i);
                     rv[c][k].r = fma(-af, qv[c][k].r, rv[c][k].r);
                     rv[c][k].i = fma(-af, qv[c][k].i, rv[c][k].i);
                     nrm[k] += (double)rv[c][k].r * rv[c][k].r + (double)rv[c][k].i * rv[c][k].i;
                 }
             }
-            MVec<KS_F64, R>::store(x, L.vec_off, vh, h, xv);
+            MVec<P, R>::store(x, L.vec_off, vh, h, xv);
             MVec<P, R>::store(r, L.vec_off, vh, h, rv);
         }
 #pragma unroll
@@ -349,6 +348,38 @@ __global__ __launch_bounds__(NT) void batch_update_kernel(const LatDesc* __restr
             if (threadIdx.x == 0) partials[(size_t)t * R + k] = s;
             __syncthreads();
         }
+    }
+}
+
+// FP32 inner: x += dx, dx = 0 on the lattices with a reliable update due (all = 1: every
+// lattice, at the end of a solve)
+template <int R, int NT>
+__global__ __launch_bounds__(NT) void batch_flush_kernel(const LatDesc* __restrict__ lats,
+                                                        const int2* __restrict__ tiles, int ntiles,
+                                                        char* __restrict__ x, char* __restrict__ dx,
+                                                        const BatchPair* __restrict__ pairs, int all)
+{
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int2 tl = tiles[t];
+        const LatDesc& L = lats[tl.x];
+        if (!all && !lattice_busy(pairs, L.pair0, R, true)) continue;
+        const int vh = L.g.Vh;
+        const int h = tl.y + threadIdx.x;
+        if (h >= vh) continue;
+        cx<double> xv[3][R];
+        cx<float> dv[3][R], zero[3][R];
+        MVec<KS_F64, R>::load(x, L.vec_off, vh, h, xv);
+        MVec<KS_F32, R>::load(dx, L.vec_off, vh, h, dv);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                xv[c][k].r += (double)dv[c][k].r;
+                xv[c][k].i += (double)dv[c][k].i;
+                zero[c][k] = {0.f, 0.f};
+            }
+        MVec<KS_F64, R>::store(x, L.vec_off, vh, h, xv);
+        MVec<KS_F32, R>::store(dx, L.vec_off, vh, h, zero);
     }
 }
 
@@ -735,7 +766,7 @@ struct BatchLaunch {
         if (P == KS_F64)
             batch_update_kernel<KS_F64, R, NT><<<grid, NT, 0, s>>>(c.lats_dev, tl, nt, c.x64, c.ps, c.qs, c.rs, c.pairs, c.partials);
         else
-            batch_update_kernel<KS_F32, R, NT><<<grid, NT, 0, s>>>(c.lats_dev, tl, nt, c.x64, c.ps, c.qs, c.rs, c.pairs, c.partials);
+            batch_update_kernel<KS_F32, R, NT><<<grid, NT, 0, s>>>(c.lats_dev, tl, nt, c.dx32, c.ps, c.qs, c.rs, c.pairs, c.partials);
         batch_beta_kernel<<<nlat, kLat, 0, s>>>(c.lats_dev, R, c.pairs, c.partials);
         reliable(c, 0, s);
         if (P == KS_F64)
@@ -752,6 +783,7 @@ struct BatchLaunch {
         const int grid = nt;   // streaming vector kernels: one block per tile (the tuned
                                 // persistent schedule is for the hopping terms)
         const int nlat = (int)c.lats_host.size();
+        if (c.prec == KS_F32) flush(c, 0, s);
         batch_dslash_ru_kernel<R, false><<<kRuGrid, 256, 0, s>>>(c.lats_dev, nlat, 1, c.x64, c.t64,
                                                                  nullptr, c.pairs);
         batch_dslash_ru_kernel<R, true><<<kRuGrid, 256, 0, s>>>(c.lats_dev, nlat, 0, c.t64, c.ax64,
@@ -763,6 +795,13 @@ struct BatchLaunch {
             batch_load_r_kernel<KS_F64, R, NT><<<grid, NT, 0, s>>>(c.lats_dev, tl, nt, c.r64, c.rs, c.pairs);
         else
             batch_load_r_kernel<KS_F32, R, NT><<<grid, NT, 0, s>>>(c.lats_dev, tl, nt, c.r64, c.rs, c.pairs);
+        KS_HIP(hipGetLastError());
+    }
+    static void flush(BatchCtx& c, int all, hipStream_t s)
+    {
+        const int nt = c.ntiles[c.tile_idx];
+        batch_flush_kernel<R, NT><<<nt, NT, 0, s>>>(c.lats_dev, c.tiles[c.tile_idx], nt, c.x64,
+                                                    c.dx32, c.pairs, all);
         KS_HIP(hipGetLastError());
     }
     static void b2(BatchCtx& c, hipStream_t s)
@@ -797,6 +836,7 @@ static void dispatch(BatchCtx& c, int what, hipStream_t s, int xpay_or_init = 0)
         if (what == 0) BatchLaunch<R, NTV>::step(c, s);                                 \
         else if (what == 1) BatchLaunch<R, NTV>::start(c, s);                           \
         else if (what == 3) BatchLaunch<R, NTV>::b2(c, s);                              \
+        else if (what == 4) BatchLaunch<R, NTV>::flush(c, 1, s);                        \
         else BatchLaunch<R, NTV>::dslash(c, c.prec, xpay_or_init != 0, 1, c.ps, c.ts, nullptr, s); \
         return;                                                                         \
     }
@@ -839,7 +879,7 @@ void batch_free(BatchCtx* c)
     device_free(c->b2);
     device_free(c->pair_param);
     device_free(c->io_ptrs);
-    for (char* v : {c->ps, c->qs, c->ts, c->rs, c->x64, c->b64, c->r64, c->t64, c->ax64})
+    for (char* v : {c->ps, c->qs, c->ts, c->rs, c->x64, c->b64, c->r64, c->t64, c->ax64, c->dx32})
         device_free(v);
     if (c->pairs_host) (void)hipHostFree(c->pairs_host);
     if (c->census_host) (void)hipHostFree(c->census_host);
@@ -910,6 +950,10 @@ static void batch_setup(BatchCtx* c, hipStream_t s)
     c->r64 = static_cast<char*>(device_alloc(nrec * 16));
     c->t64 = static_cast<char*>(device_alloc(nrec * 16));
     c->ax64 = static_cast<char*>(device_alloc(nrec * 16));
+    if (inner == KS_F32) {
+        c->dx32_bytes = nrec * 8;
+        c->dx32 = static_cast<char*>(device_alloc(c->dx32_bytes));
+    }
     // finished pairs leave their slots of p, q, t untouched: start every arena finite
     for (char* a : {c->ps, c->qs, c->ts, c->rs})
         KS_HIP(hipMemsetAsync(a, 0, nrec * cs, s));
@@ -1077,6 +1121,7 @@ ks_status_t batch_solve_pairs(BatchCtx& c, const double* sigma, const double* to
                           hipMemcpyHostToDevice, s));
     batch_io(c, c.b64, reinterpret_cast<const void* const*>(b), 1, s);
     batch_io(c, c.x64, reinterpret_cast<const void* const*>(x), 1, s);
+    if (c.dx32) KS_HIP(hipMemsetAsync(c.dx32, 0, c.dx32_bytes, s));   // outside any graph
     batch_clock_kernel<<<1, 1, 0, s>>>(c.clock);
     run(c, 3, s);   // |b|^2 tile partials
     batch_init_pairs_kernel<<<c.npairs, kFin, 0, s>>>(c.lats_dev, c.nrhs, c.pairs, c.partials,
@@ -1119,6 +1164,7 @@ ks_status_t batch_solve_pairs(BatchCtx& c, const double* sigma, const double* to
     KS_HIP(hipMemcpyAsync(&start, c.clock, sizeof(start), hipMemcpyDeviceToHost, s));
     std::vector<double> b2(c.npairs);
     KS_HIP(hipMemcpyAsync(b2.data(), c.b2, sizeof(double) * c.npairs, hipMemcpyDeviceToHost, s));
+    if (c.dx32) run(c, 4, s);   // every pair's remaining FP32 increments into x
     batch_io(c, c.x64, reinterpret_cast<const void* const*>(x), 0, s);
     int dev = 0, khz = 100000;
     KS_HIP(hipGetDevice(&dev));

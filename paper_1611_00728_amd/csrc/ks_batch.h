@@ -53,6 +53,9 @@ struct BatchCtx {
     // vector arenas: inner precision p, q, t (odd), r; FP64 x, b, r, t (odd), A x
     char *ps = nullptr, *qs = nullptr, *ts = nullptr, *rs = nullptr;
     char *x64 = nullptr, *b64 = nullptr, *r64 = nullptr, *t64 = nullptr, *ax64 = nullptr;
+    // FP32 inner: x's FP32 increments since the pair's last reliable update (zero otherwise)
+    char* dx32 = nullptr;
+    size_t dx32_bytes = 0;
     void** io_ptrs = nullptr;  // device table of the caller's per-pair vectors
     double* b2 = nullptr;      // |b|^2 per pair
     double* pair_param = nullptr;     // device [2][npairs]: shift and tolerance of each pair

@@ -492,10 +492,10 @@ ks_status_t multishift_core(ks_gauge_t g, int nshift, const double* sigma, const
                 o.true_rel_resid = bs[k].true_rel_resid;
                 // per step: two multi-RHS FP32 hopping terms (links once for the group, the
                 // 96 bytes of spinor in/out per right-hand side) and the per-RHS vector
-                // traffic of a mixed CG step with an FP64 x (read + write)
+                // traffic of a mixed CG step with x's FP32 increments (read + write)
                 o.model_bytes += (double)bs[k].iters * vh *
                                  ((2 * dslash_model_bytes(KS_F32, KS_RECON_18) - 96) / R + 96 +
-                                  8.0 * 24 + 96);
+                                  8.0 * 24 + 48);
                 if (bs[k].status != KS_SUCCESS && result == KS_SUCCESS)
                     result = static_cast<ks_status_t>(bs[k].status);
             }
