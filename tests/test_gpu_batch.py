@@ -48,7 +48,7 @@ def run_batch(ks, B, gs, masses, nrhs, tol=1e-10, **kw):
     return rc, st, bh, [host(x) for x in xs]
 
 
-@pytest.mark.parametrize("nrhs,inner", [(4, "f32"), (2, "f32"), (1, "f64"), (4, "f64")])
+@pytest.mark.parametrize("nrhs,inner", [(4, "f32"), (2, "f32"), (1, "f32"), (1, "f64"), (4, "f64")])
 def test_batch_pairs_converge(ks, fields, nrhs, inner):
     announce("batch", nrhs, inner)
     gs, masses = fields
@@ -145,4 +145,9 @@ def test_batch_zero_rhs_and_max_iter(ks, fields):
                      raise_on_error=False)
     torch.cuda.synchronize()
     assert rc == -5 and all(s["status"] == -5 for s in st)
+    # the step cap forces a reliable update: the reported residual is that of the returned x
+    # (its FP32 increments added in before the update and again at the end)
+    for k in range(2):
+        tr = true_rel(gs[0], 4 * masses[0] ** 2, b, host(xs[k]))
+        assert 1e-6 < tr < 1.0 and abs(st[k]["true_rel_resid"] - tr) <= 1e-6 * tr
     B.free()
