@@ -214,7 +214,8 @@ ks_status_t ks_cg_coefficients(ks_gauge_t g, int n_max, double* alpha, double* b
  * precision with x_i accumulated in FP64 (in reduced precision through FP32 increments added
  * in at every reliable update of the base system); every shift whose FP64 true residual is
  * then above its target is refined from x_i by ks_cg_solve's method (several at once, one
- * right-hand side each, when the inner precision is reduced).  st: nshift entries. */
+ * right-hand side each, FP32 inner, reliable updates at p->delta / 10, when the inner precision
+ * is reduced).  st: nshift entries. */
 ks_status_t ks_multishift_cg_solve(ks_gauge_t g, int nshift, const double* sigma,
                                    const double* b_dev, double* const* x_dev,
                                    const double* tol, const ks_solver_params* p,

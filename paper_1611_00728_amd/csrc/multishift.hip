@@ -479,6 +479,9 @@ ks_status_t multishift_core(ks_gauge_t g, int nshift, const double* sigma, const
             }
             ks_solver_params q = prm;
             q.inner = KS_F32;
+            // the group's FP64 updates are synchronous (the fastest shift sets their rate):
+            // take them at a ten times deeper drop; FP32 keeps the same step counts there
+            q.delta = prm.delta * 0.1;
             std::vector<ks_batch_stats> bs(R);
             const ks_status_t rc = batch_solve_pairs(*w.ms_batch[ri], sg.data(), tl.data(),
                                                      bp.data(), xp.data(), q, bs.data(), s);
