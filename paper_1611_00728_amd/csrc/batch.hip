@@ -2,7 +2,8 @@
 // together.  One launch of each step covers every (lattice, site tile) of the batch through a
 // tile table; the multi-RHS Dslash loads each link once and applies it to all R vectors of
 // the site.  Every (lattice, RHS) pair keeps its own CG scalars on the device, with FP32 (or
-// FP64) inner iterations, FP64 solution accumulation and per-pair FP64 reliable updates
+// FP64) inner iterations, FP64 solution accumulation (through FP32 increments added in at
+// each reliable update when the inner iterations are FP32) and per-pair FP64 reliable updates
 // decided on the device, so a fixed sequence of kernels makes up one step and a run of steps
 // is captured once into a HIP graph and replayed until every pair has converged.
 #include <algorithm>
@@ -293,7 +294,8 @@ __global__ __launch_bounds__(256) void batch_dslash_ru_kernel(
     }
 }
 
-// x (FP64) += alpha p; r -= alpha q; partial sums of |r|^2 per RHS
+// x += alpha p (FP64 x, or with FP32 inner iterations its FP32 increments); r -= alpha q;
+// partial sums of |r|^2 per RHS
 template <int P, int R, int NT>
 __global__ __launch_bounds__(NT) void batch_update_kernel(const LatDesc* __restrict__ lats,
                                                          const int2* __restrict__ tiles, int ntiles,
@@ -508,7 +510,8 @@ __device__ __forceinline__ double pair_sum(const LatDesc& L, const double* part,
 
 // The scalar steps run one block of kLat threads per lattice: one pass over the lattice's tile
 // partials gives the sums of all its R pairs (thread j adds tiles j, j + kLat, ... in order,
-// then a fixed tree per pair), so a lattice with many tiles is summed as fast as a small one.
+// then wave sums and the waves in order, for all pairs in one LDS round), so a lattice with
+// many tiles is summed as fast as a small one.
 constexpr int kLat = 1024;
 
 __device__ __forceinline__ void lattice_sums(const LatDesc& L, const double* __restrict__ part,
