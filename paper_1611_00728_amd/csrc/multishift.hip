@@ -17,6 +17,7 @@
 #include "ks_blas.h"
 #include "ks_device.h"
 #include "ks_solvers.h"
+#include "ks_stream.h"
 
 namespace ks {
 
@@ -153,49 +154,9 @@ __global__ __launch_bounds__(kFinish) void ms_beta_kernel(const double* __restri
 // are issued before any of the group's stores, so that a wave has several in flight.  In
 // reduced precision the x_i increments go to FP32 fields that are added into the FP64 x_i at
 // every reliable update of the base and at the end (half the bytes of an FP64
-// read-modify-write).
-// The shifts' own vectors (x_i or its increments, p_i) are read and written streamed
-// (non-temporal): they are touched once per step, and through the caches they would push out
-// the base direction p that the next hopping term gathers from its 16 neighbours.  FP64 and
-// FP32 layouts as in Spinor; FP16 records go through Spinor's encoding.
-template <int P>
-struct Streamed {
-    using R = typename St<P>::R;
-    __device__ static __forceinline__ void load(const void* b, int vh, int h, cx<R> v[3])
-    {
-        if constexpr (P == KS_F64) {
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const dvec2 t = __builtin_nontemporal_load(static_cast<const dvec2*>(b) + (size_t)k * vh + h);
-                v[k] = {t.x, t.y};
-            }
-        } else if constexpr (P == KS_F32) {
-            const fvec4 a = __builtin_nontemporal_load(static_cast<const fvec4*>(b) + h);
-            const fvec2 c = __builtin_nontemporal_load(
-                reinterpret_cast<const fvec2*>(static_cast<const fvec4*>(b) + vh) + h);
-            v[0] = {a.x, a.y};
-            v[1] = {a.z, a.w};
-            v[2] = {c.x, c.y};
-        } else {
-            Spinor<P>::load(b, vh, h, v);
-        }
-    }
-    __device__ static __forceinline__ void store(void* b, int vh, int h, const cx<R> v[3])
-    {
-        if constexpr (P == KS_F64) {
-#pragma unroll
-            for (int k = 0; k < 3; ++k)
-                __builtin_nontemporal_store(dvec2{v[k].r, v[k].i}, static_cast<dvec2*>(b) + (size_t)k * vh + h);
-        } else if constexpr (P == KS_F32) {
-            __builtin_nontemporal_store(fvec4{v[0].r, v[0].i, v[1].r, v[1].i}, static_cast<fvec4*>(b) + h);
-            __builtin_nontemporal_store(fvec2{v[2].r, v[2].i},
-                                        reinterpret_cast<fvec2*>(static_cast<fvec4*>(b) + vh) + h);
-        } else {
-            Spinor<P>::store(b, vh, h, v);
-        }
-    }
-};
-
+// read-modify-write).  The shifts' own vectors (x_i or its increments, p_i) are touched once
+// per step: read and written streamed, they do not push the base direction p, which the next
+// hopping term gathers from its 16 neighbours, out of the caches.
 template <int P>
 __global__ __launch_bounds__(kBlock) void ms_update_kernel(int vh, const void* __restrict__ r,
                                                            void* __restrict__ pb, ShiftPtrs sp,
