@@ -8,6 +8,8 @@
 // bytes); the 16 neighbour vectors are gathers that the XCD-aware tile order keeps inside
 // one XCD's L2 for most hops.
 #include <algorithm>
+#include <utility>
+#include <vector>
 
 #include "ks_device.h"
 #include "ks_naik.h"
@@ -316,12 +318,28 @@ void dslash(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, const DslashArgs& a,
     launch(g, prec, ri, a, g->tune[prec][ri], s);
 }
 
+// mean time of one launch over `reps` launches of one candidate (HIP events)
+static float time_launches(ks_gauge_t g, ks_prec_t prec, int ri, const DslashArgs& a,
+                           const TuneEntry& t, int reps, hipEvent_t e0, hipEvent_t e1,
+                           hipStream_t s)
+{
+    KS_HIP(hipEventRecord(e0, s));
+    for (int k = 0; k < reps; ++k) launch(g, prec, ri, a, t, s);
+    KS_HIP(hipEventRecord(e1, s));
+    KS_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    KS_HIP(hipEventElapsedTime(&ms, e0, e1));
+    return ms * 1e3f / reps;
+}
+
 // Candidates: neighbours through the caches or x/y neighbours staged in LDS, 8-way or 4-way
 // link access, 1, 2 or 4 matrices loaded per pass (2 at most in
 // FP64), 64, 128 or 256 threads per block, each with the number of resident blocks per CU capped through the dynamic LDS
 // request (how many waves share a SIMD also decides how
 // evenly the last round of waves fills the chip).  Each candidate is timed over a few
-// launches with HIP events on this lattice; the fastest is kept for the handle.
+// launches with HIP events on this lattice; the four fastest are then timed again over 20
+// launches each, twice in alternation, and the one with the best mean is kept for the handle
+// (a single short timing picks a lucky candidate too often).
 void dslash_tune(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, hipStream_t s)
 {
     const int ri = recon_index(recon);
@@ -341,6 +359,7 @@ void dslash_tune(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, hipStream_t s)
     hipEvent_t e0 = nullptr, e1 = nullptr;
     TuneEntry best;
     float best_us = 1e30f;
+    std::vector<std::pair<float, TuneEntry>> timed;
     try {
         out = device_alloc(fb);
         KS_HIP(hipMemsetAsync(in, 0x3f, fb, s));
@@ -369,23 +388,27 @@ void dslash_tune(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, hipStream_t s)
                     t.lds = (int)l;
                 }
                 for (int k = 0; k < 2; ++k) launch(g, prec, ri, a, t, s);
-                const int reps = 5;
-                KS_HIP(hipEventRecord(e0, s));
-                for (int k = 0; k < reps; ++k) launch(g, prec, ri, a, t, s);
-                KS_HIP(hipEventRecord(e1, s));
-                KS_HIP(hipEventSynchronize(e1));
-                float ms = 0.f;
-                KS_HIP(hipEventElapsedTime(&ms, e0, e1));
-                const float us = ms * 1e3f / reps;
-                if (us < best_us) {
-                    best_us = us;
-                    best = t;
-                }
+                timed.push_back({time_launches(g, prec, ri, a, t, 5, e0, e1, s), t});
             }
         }
         }
         }
         }
+        std::stable_sort(timed.begin(), timed.end(),
+                         [](const std::pair<float, TuneEntry>& x,
+                            const std::pair<float, TuneEntry>& y) { return x.first < y.first; });
+        const size_t nfin = std::min<size_t>(4, timed.size());
+        std::vector<float> sum(nfin, 0.f);
+        for (int round = 0; round < 2; ++round)
+            for (size_t i = 0; i < nfin; ++i) {
+                launch(g, prec, ri, a, timed[i].second, s);
+                sum[i] += time_launches(g, prec, ri, a, timed[i].second, 20, e0, e1, s);
+            }
+        for (size_t i = 0; i < nfin; ++i)
+            if (sum[i] / 2 < best_us) {
+                best_us = sum[i] / 2;
+                best = timed[i].second;
+            }
     } catch (...) {
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
