@@ -47,6 +47,9 @@ struct MultiVec {
     double2* out[kMultiMax];
 };
 
+// Two lanes per output site: lane 0 of the pair takes the eight one-link matrices, lane 1 the
+// eight Naik matrices (twice the waves, half of each lane's chain of dependent loads); one
+// shuffle adds the halves and lane 0 stores.
 template <int K>
 __global__ __launch_bounds__(kBlock) void dslash_multi_kernel(Geom g, int par,
                                                               const void* __restrict__ fat,
@@ -55,41 +58,50 @@ __global__ __launch_bounds__(kBlock) void dslash_multi_kernel(Geom g, int par,
                                                               float naik_scale)
 {
     const int vh = g.Vh;
-    // each XCD takes one contiguous range of sites, so its L2 holds most neighbour vectors
-    const int h = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    if (h >= vh) return;
+    const int t = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const int h = t >> 1;
+    const int kind = t & 1;                 // 0: one-link, 1: Naik
+    const bool live = h < vh;
+    const int hs = live ? h : vh - 1;       // a dead lane shadows a live site (no store)
     int c[4];
-    cb_coords(g, h, par, c);
+    cb_coords(g, hs, par, c);
     const int i = site_index(g, c);
     cx<double> res[K][3];
 #pragma unroll
     for (int q = 0; q < K; ++q)
 #pragma unroll
         for (int a = 0; a < 3; ++a) res[q][a] = {0.0, 0.0};
+    const void* links = kind ? naik : fat;
+    const double sc = kind ? (double)naik_scale : (double)fat_scale;
 #pragma unroll 1
-    for (int s = 0; s < 16; ++s) {
-        // slots 0-3: +mu, 4-7: -mu (one-link); 8-15 the same for the three-link (Naik) hops;
-        // backward slots hold the negated adjoint of the link
-        const int dist = (s & 4) ? ((s & 8) ? -3 : -1) : ((s & 8) ? 3 : 1);
+    for (int s = 0; s < 8; ++s) {
+        // slots 0-3: +mu, 4-7: -mu; backward slots hold the negated adjoint of the link
+        const int dist = (s & 4) ? (kind ? -3 : -1) : (kind ? 3 : 1);
         const int nb = hop_cb(g, i, c, s & 3, dist);
         cx<double> m[9];
-        if (s < 8) load_link<KS_F64, 9>(fat, s, vh, h, m);
-        else load_link<KS_F64, 9>(naik, s - 8, vh, h, m);
-        const double sc = s < 8 ? (double)fat_scale : (double)naik_scale;
+        load_link<KS_F64, 9>(links, s, vh, hs, m);
 #pragma unroll
         for (int q = 0; q < K; ++q) {
             cx<double> v[3];
             load_psi(mv.in[q], vh, nb, v);
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                cx<double> t = {0.0, 0.0};
+                cx<double> u = {0.0, 0.0};
 #pragma unroll
-                for (int b = 0; b < 3; ++b) cfma(t, m[a * 3 + b], v[b]);
-                res[q][a].r = fma(sc, t.r, res[q][a].r);
-                res[q][a].i = fma(sc, t.i, res[q][a].i);
+                for (int b = 0; b < 3; ++b) cfma(u, m[a * 3 + b], v[b]);
+                res[q][a].r = fma(sc, u.r, res[q][a].r);
+                res[q][a].i = fma(sc, u.i, res[q][a].i);
             }
         }
     }
+#pragma unroll
+    for (int q = 0; q < K; ++q)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            res[q][a].r += __shfl_xor(res[q][a].r, 1, 64);
+            res[q][a].i += __shfl_xor(res[q][a].i, 1, 64);
+        }
+    if (!live || kind) return;
 #pragma unroll
     for (int q = 0; q < K; ++q)
 #pragma unroll
@@ -238,7 +250,7 @@ void force_core(ks_gauge_t g, int nterm, const double* residues, const double* c
             mv.in[q] = terms.psi[0][i0 + q];
             mv.out[q] = reinterpret_cast<double2*>(w.force_psi[2 * (i0 + q) + 1]);
         }
-        const unsigned nb = (unsigned)blocks_for(G.Vh);
+        const unsigned nb = (unsigned)blocks_for(2L * G.Vh);   // two lanes per site
         launch_multi(k, nb, G, st, mv, s);
         KS_HIP(hipGetLastError());
     }
