@@ -13,12 +13,16 @@ and never imports it; the two meet only in the seeded inputs of `ksinputs`.
   derivative (force) of the multi-shift pseudofermion action from the shifted solutions.
 * `hisq.py`: two-level smeared fat links (fat7, U(3) projection, fat7 + Lepage) and the
   Naik link built from thin links.
-* `quant.py`: the quantise-then-FP64 references of the reduced-precision storage formats.
+* `quant.py`: the quantise-then-FP64 references of the reduced-precision storage formats
+  (vectors, links, 12-real Naik storage), the Dslash with separately stored forward and
+  backward links, and the per-component modulus sums that bound its rounding error.
 """
 from .core import (lib, set_threads, max_threads, dslash_full, dslash_eo, apply_A, cg, multishift_cg, embed, restrict,
                    CGInfo, dense_A, lanczos_extremes, OracleError)
 from . import hisq
-from .quant import quantise_f32, quantise_f16_sites, quantise_f16_links, f16_link_exponent
+from .quant import (quantise_f32, quantise_f16_sites, quantise_f16_links, f16_link_exponent,
+                    rebuild_su3, naik_phase, naik12_scale, link_store_values, dslash_eo_fb,
+                    dslash_eo_abs)
 from .network import (Network, PATHS, transport, transport_adj, layer_forward,
                       network_forward, loss_and_grad, adam_step, neighbour_tables)
 from .solvers import (fcg, apply_M, full_solve, FullInfo, force_outer, rational_action,
@@ -26,7 +30,8 @@ from .solvers import (fcg, apply_M, full_solve, FullInfo, force_outer, rational_
 
 __all__ = ["hisq", "lib", "set_threads", "max_threads", "dslash_full", "dslash_eo", "apply_A", "cg", "multishift_cg", "embed",
            "restrict", "CGInfo", "dense_A", "lanczos_extremes", "OracleError", "quantise_f32",
-           "quantise_f16_sites", "quantise_f16_links", "f16_link_exponent", "Network", "PATHS",
+           "quantise_f16_sites", "quantise_f16_links", "f16_link_exponent", "rebuild_su3",
+           "naik_phase", "naik12_scale", "link_store_values", "dslash_eo_fb", "dslash_eo_abs", "Network", "PATHS",
            "transport", "transport_adj", "layer_forward", "network_forward", "loss_and_grad",
            "adam_step", "neighbour_tables", "fcg", "apply_M", "full_solve", "FullInfo", "force_outer",
            "rational_action", "parity_sign"]

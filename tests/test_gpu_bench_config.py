@@ -1,8 +1,11 @@
 """The benchmark's own configurations at full size, in the launch forms the benchmark times
 (every variant autotuned on its lattice first, as bench.py does):
 
-* every Dslash_eo output site of the six variants at 32^4 against the FP64 oracle (tolerances
-  as in test_gpu_dslash: FP64 1e-12, FP32 5e-6, FP16 5e-3 relative L2);
+* every Dslash_eo output component of the six variants at 32^4, in the tuned launch form,
+  against the oracle applied to the links and input as the device stores them (the 12-real
+  Naik copies of the tuned link access), within the device's rounding bound
+  (`dslash_check`), and the relative L2 distance to the plain FP64 oracle (FP64 1e-12, FP32
+  5e-6, FP16 5e-3);
 * the benchmark's CG solves at 32^4, m = 0.01 (FP64, FP32 with 18- and 12-real Naik, FP16 with
   12-real Naik), each x judged by the oracle's FP64 residual |b - A x| / |b| <= 1e-10;
 * the benchmark's multi-shift solve at 32^3 x 48 (nine shifts, FP32 inner and FP64, per-shift
@@ -17,6 +20,7 @@ import oracle
 from ksinputs import make_gauge, gaussian_source, SEEDS
 from conftest import rel_l2
 from gpu_util import dev, host, zeros_dev, announce
+import dslash_check as dc
 
 pytestmark = pytest.mark.gpu
 
@@ -40,24 +44,29 @@ def true_rel(g, sigma, b, x):
     return float(np.linalg.norm(b - oracle.apply_A(g, sigma, x)) / np.linalg.norm(b))
 
 
-def test_tuned_dslash_32(ks, lat32):
+@pytest.mark.parametrize("prec,recon", [("f64", 18), ("f64", 12), ("f32", 18), ("f32", 12),
+                                         ("f16", 18), ("f16", 12)])
+def test_tuned_dslash_32(ks, lat32, prec, recon):
     import torch
     g, G, psi = lat32
     vh = g.volume // 2
-    refs = [oracle.dslash_eo(g, p, psi) for p in (0, 1)]
-    for prec, recon, tol in ((ks.F64, 18, 1e-12), (ks.F64, 12, 1e-12), (ks.F32, 18, 5e-6),
-                             (ks.F32, 12, 5e-6), (ks.F16, 18, 5e-3), (ks.F16, 12, 5e-3)):
-        G.prepare(prec, recon)
-        cfg = G.tune(prec, recon)
-        announce("tuned dslash 32^4", prec, recon, cfg)
-        for out_par in (0, 1):
-            inp = ks.Field(G, 1 - out_par, prec).load(dev(psi))
-            out = ks.Field(G, out_par, prec)
-            ks.dslash_eo(G, out, inp, recon)
-            res = zeros_dev((vh, 3))
-            out.store(res)
-            torch.cuda.synchronize()
-            assert rel_l2(host(res), refs[out_par]) <= tol, (prec, recon, cfg)
+    P = ks.PREC[prec]
+    tol = {"f64": 1e-12, "f32": 5e-6, "f16": 5e-3}[prec]
+    G.prepare(P, recon)
+    cfg = G.tune(P, recon)
+    announce("tuned dslash 32^4", prec, recon, cfg)
+    for out_par in (0, 1):
+        inp = ks.Field(G, 1 - out_par, P).load(dev(psi))
+        out = ks.Field(G, out_par, P)
+        ks.dslash_eo(G, out, inp, recon)
+        res = zeros_dev((vh, 3))
+        out.store(res)
+        torch.cuda.synchronize()
+        got = host(res)
+        assert rel_l2(got, oracle.dslash_eo(g, out_par, psi)) <= tol, (prec, recon, cfg)
+        r, S = dc.reference(g, prec, recon, cfg["link_access"], out_par, psi)
+        assert dc.worst(got, r, S, prec) <= 1.0, (prec, recon, cfg)
+        del r, S
 
 
 @pytest.mark.parametrize("inner,recon", [("f64", 18), ("f32", 18), ("f32", 12), ("f16", 12)])

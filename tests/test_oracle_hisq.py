@@ -125,3 +125,47 @@ def test_level1_abelian_form_factor(mu):
         resp = (V[mu, :, 0, 0] - 1.0) / (1j * eps)
         f = np.prod([(1 + np.cos(ks[nu])) / 2 for nu in range(4) if nu != mu])
         assert np.max(np.abs(resp - f * np.cos(phase))) <= 1e-6
+
+
+@pytest.mark.parametrize("n", [(0, 0, 0, 0), (1, 0, 2, 1), (3, 1, 0, 4)])
+def test_signs_of_unit_links_give_the_free_operator(n):
+    """fold_signs, pinned through the closed-form free field: unit thin links give the
+    unsigned X = 9/8 and N = -1/24; with the staggered phases and the antiperiodic time signs
+    folded in, D on an antiperiodic plane wave psi = e^{ip.x} chi must be
+    2i sum_mu eta_mu(x) s_mu(p) psi(x), s_mu = (9/8) sin p_mu - (1/24) sin 3p_mu (the free
+    operator's closed form).  A wrong eta, a one-link boundary sign on the wrong slice or a
+    three-link sign on the wrong slices breaks it."""
+    import oracle
+    from ksinputs import GaugeField, lattice_coords, staggered_phase
+    dims = (4, 6, 4, 8)
+    vol = int(np.prod(dims))
+    U = np.zeros((4, vol, 3, 3), dtype=complex)
+    U[..., [0, 1, 2], [0, 1, 2]] = 1.0
+    X, N = hisq.hisq_links(U, dims, signs=True)
+    g = GaugeField(dims, X, N)
+    x, y, z, t = lattice_coords(dims)
+    p = [2 * np.pi * n[0] / dims[0], 2 * np.pi * n[1] / dims[1], 2 * np.pi * n[2] / dims[2],
+         2 * np.pi * (n[3] + 0.5) / dims[3]]
+    chi = np.array([0.3 + 0.1j, -0.7j, 1.1])
+    psi = np.exp(1j * (p[0] * x + p[1] * y + p[2] * z + p[3] * t))[:, None] * chi[None, :]
+    s = [9.0 / 8.0 * np.sin(pm) - np.sin(3 * pm) / 24.0 for pm in p]
+    expect = (2j * sum(staggered_phase(mu, x, y, z, t) * s[mu] for mu in range(4)))[:, None] * psi
+    got = oracle.dslash_full(g, psi)
+    assert np.max(np.abs(got - expect)) <= 1e-13 * max(np.max(np.abs(expect)), 1.0)
+
+
+def test_signs_count_boundary_crossings():
+    """Every folded sign is eta_mu(x) times (-1)^(number of times the hop from x crosses the
+    time boundary), with the crossings counted as floor((t + hops) / Nt)."""
+    dims = (4, 4, 4, 6)
+    vol = int(np.prod(dims))
+    U = np.zeros((4, vol, 3, 3), dtype=complex)
+    U[..., [0, 1, 2], [0, 1, 2]] = 1.0
+    X, N = hisq.fold_signs(U, 2.0 * U, dims)
+    for i in range(vol):
+        c = coords(dims, i)
+        for mu in range(4):
+            eta = (-1.0) ** (sum(c[:mu]))
+            for L, hops, f in ((X, 1, 1.0), (N, 3, 2.0)):
+                cross = (c[3] + hops) // dims[3] if mu == 3 else 0
+                assert L[mu, i, 1, 1] == f * eta * (-1.0) ** cross
