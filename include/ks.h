@@ -184,6 +184,17 @@ ks_status_t ks_dslash_set_config(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon,
 ks_status_t ks_apply_A(ks_gauge_t g, double sigma, const double* in_dev, double* out_dev,
                        hipStream_t stream);
 
+/* ks_apply_A without any device allocation, for callers that cannot allocate (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same arguments and
+ * result as ks_apply_A (the same kernels run); out_dev also stages the input's internal
+ * planes.  Its temporaries live in a fixed 48 MiB device array of the library, one per GPU,
+ * held until the process ends: lattices of up to 524288 even sites (32^4) are accepted, larger
+ * ones return KS_ERR_ARG before any device work.  The FP64 link store is built by
+ * ks_gauge_load, so nothing is allocated on the way.  Calls that overlap in time on one GPU
+ * (several host threads or streams) share that array and race.  Asynchronous on `stream`. */
+ks_status_t ks_apply_A_noalloc(ks_gauge_t g, double sigma, const double* in_dev, double* out_dev,
+                               hipStream_t stream);
+
 /* ------------------------------------------------------------------ solvers */
 
 /* Solves (4 m^2 - D_eo D_oe) x = b, b_dev and x_dev complex128 [Vh][3] device arrays.

@@ -86,6 +86,7 @@ def lib():
         L.ks_field_export.argtypes = [_vp, _vp, _vp]
         L.ks_dslash_eo.argtypes = [_vp, _vp, _vp, C.c_int, _vp]
         L.ks_apply_A.argtypes = [_vp, C.c_double, _vp, _vp, _vp]
+        L.ks_apply_A_noalloc.argtypes = [_vp, C.c_double, _vp, _vp, _vp]
         L.ks_batch_create.argtypes = [C.POINTER(_vp), C.c_int, C.POINTER(C.c_int),
                                       C.POINTER(_vp), C.POINTER(_vp), C.c_int, C.c_int,
                                       C.c_int, _vp]
@@ -282,6 +283,14 @@ def apply_A(gauge: Gauge, sigma: float, x, out, stream=None):
     _check(lib().ks_apply_A(gauge.handle, float(sigma), _dev_vec(x, gauge.vh, "x"),
                             _dev_vec(out, gauge.vh, "out"),
                             _stream(stream)))
+    return out
+
+
+def apply_A_noalloc(gauge: Gauge, sigma: float, x, out, stream=None):
+    """apply_A through the entry point that allocates no device memory (its temporaries sit in
+    the library's fixed scratch array)."""
+    _check(lib().ks_apply_A_noalloc(gauge.handle, float(sigma), _dev_vec(x, gauge.vh, "x"),
+                                    _dev_vec(out, gauge.vh, "out"), _stream(stream)))
     return out
 
 

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libks.so")
 SOURCES = ["api.hip", "gauge.hip", "dslash.hip", "blas.hip", "solvers.hip", "multishift.hip",
-           "batch.hip", "network.hip", "network_mfma.hip", "fcg.hip", "fullsolve.hip", "force.hip", "hisq.hip"]
+           "batch.hip", "network.hip", "network_mfma.hip", "fcg.hip", "fullsolve.hip", "force.hip", "hisq.hip", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall",
          "-Wno-unused-function", "-Wno-unused-parameter",
