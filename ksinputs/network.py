@@ -1,12 +1,13 @@
 """Initial weights of the preconditioner network (random draws only).
 
-Layer l has weights w[c_out][c_in][9] (complex): nine parallel-transport paths, channels
-1 -> 8 -> 8 -> 8 -> 1.  Entries are CN(0, 1/(9 c_in)) draws (default_rng(seed), layer by layer,
-row-major, re before im) plus 1 on the identity path of the channel diagonal.
+The free layers of the network's half L have weights w[c_out][c_in][9] (complex): nine
+parallel-transport paths, channels 1 -> 8 -> 8.  Entries are CN(0, 1/(9 c_in)) draws
+(default_rng(seed), layer by layer, row-major, re before im) plus 1 on the identity path of the
+channel diagonal.
 """
 import numpy as np
 
-CHANNELS = (1, 8, 8, 8, 1)
+CHANNELS = (1, 8, 8)
 NPATH = 9
 
 

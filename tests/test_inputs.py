@@ -59,9 +59,9 @@ def test_block_origins_tile_the_lattice():
 
 def test_network_initial_weights():
     ws = net_init_weights(5000)
-    assert [w.shape for w in ws] == [(8, 1, 9), (8, 8, 9), (8, 8, 9), (1, 8, 9)]
+    assert [w.shape for w in ws] == [(8, 1, 9), (8, 8, 9)]
     flat = flatten_weights(ws)
-    assert flat.shape == (1296,)
+    assert flat.shape == (648,)
     back = unflatten_weights(flat)
     assert all(np.array_equal(a, b) for a, b in zip(ws, back))
     # identity diagonal on the 0-path of the square layers, CN(0, 1/(9 c_in)) noise

@@ -1,7 +1,9 @@
 """Pins of the oracle's preconditioner network and flexible CG: gauge equivariance, linearity,
-the adjoint identity of every transport, the path conventions on a point source, central
-finite differences (exact up to rounding: the loss is quadratic in each single weight), the
-closed-form first Adam step, and flexible CG's two limits (identity and exact inverse)."""
+the adjoint identity of every transport and of whole layers, N Hermitian with
+<v, N v> = |L v|^2 for the half network computed on its own, the path conventions on a point
+source, central finite differences of the loss (an even quartic polynomial in each single
+weight, so the differences agree to O(h^2)), the closed-form first Adam step, and flexible CG's
+two limits (identity and exact inverse)."""
 import numpy as np
 import pytest
 
@@ -81,28 +83,79 @@ def test_gauge_equivariance(g6):
     assert rel_l2(outp, np.einsum("vab,vb->va", Gev, out)) <= 1e-13
 
 
+def test_layer_adjoint_identity(g6):
+    """<g, layer(w) phi> = <layer(w')(g), phi> with w' = adjoint_weights(w), channel by channel
+    summed, for the 1 -> 8 and 8 -> 8 layers."""
+    nb = N.neighbour_tables(g6.dims)
+    V = g6.volume
+    for w in N.Network.init(5000).weights:
+        cout, cin, _ = w.shape
+        phi = np.stack([gaussian_full(V, 60 + d) for d in range(cin)])
+        gg = np.stack([gaussian_full(V, 70 + c) for c in range(cout)])
+        y, _ = N.layer_forward(g6.fat, nb, w, phi)
+        ya, _ = N.layer_forward(g6.fat, nb, N.adjoint_weights(w), gg)
+        lhs = cvdot(gg, y)
+        rhs = cvdot(ya, phi)
+        assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+
+
+def test_hermitian_positive(g6):
+    """N is Hermitian, and <v, N v> equals |L v|^2 with L v computed by the two free layers
+    alone (so Re<N(r), r> > 0 unless L r = 0)."""
+    net = N.Network.init(5000)
+    vh = g6.volume // 2
+    u, v = gaussian_source(vh, 80), gaussian_source(vh, 81)
+    Nu, _ = N.network_forward(net, g6, u)
+    Nv, _ = N.network_forward(net, g6, v)
+    assert abs(cvdot(u, Nv) - np.conj(cvdot(v, Nu))) <= 1e-13 * abs(cvdot(u, Nv))
+    Lv = N.half_forward(net, g6, v)
+    vNv = cvdot(v, Nv)
+    assert abs(vNv.imag) <= 1e-13 * abs(vNv)
+    assert abs(vNv.real - np.vdot(Lv.ravel(), Lv.ravel()).real) <= 1e-13 * vNv.real
+    assert vNv.real > 0
+
+
 def test_gradient_central_differences(g6):
     net = N.Network.init(5000)
     vh = g6.volume // 2
+    sig = [4 * 0.05 ** 2, 0.3]
     bs = [gaussian_source(vh, 10 + j) for j in range(2)]
-    xs = [gaussian_source(vh, 20 + j) for j in range(2)]
-    loss, grads = N.loss_and_grad(net, g6, bs, xs)
+    xs = [oracle.cg(g6, s, b, 1e-12)[0] for s, b in zip(sig, bs)]
+    loss, grads = N.loss_and_grad(net, g6, sig, bs, xs)
     rng = np.random.default_rng(3)
-    h = 1e-3
-    for layer in range(4):
+    h = 1e-4
+    for layer in range(2):
         w = net.weights[layer]
-        for _ in range(3):
+        for _ in range(4):
             k = tuple(rng.integers(0, s) for s in w.shape)
             for part, unit in (("re", 1.0), ("im", 1j)):
                 saved = w[k]
                 w[k] = saved + h * unit
-                lp, _ = N.loss_and_grad(net, g6, bs, xs)
+                lp, _ = N.loss_and_grad(net, g6, sig, bs, xs)
                 w[k] = saved - h * unit
-                lm, _ = N.loss_and_grad(net, g6, bs, xs)
+                lm, _ = N.loss_and_grad(net, g6, sig, bs, xs)
                 w[k] = saved
                 fd = (lp - lm) / (2 * h)
                 an = grads[layer][k].real if part == "re" else grads[layer][k].imag
-                assert abs(fd - an) <= 1e-8 * max(abs(an), 1e-3 * abs(loss))
+                assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-3 * abs(loss))
+
+
+def test_loss_of_exact_pairs():
+    """With N = identity the loss is (b - x)^+ A (b - x) / (x^+ A x) by its definition; on a
+    free field (unit links times the improvement coefficients) with a plane-wave source b the
+    solution is b / lambda: (1 - 1/lambda)^2 lambda |b|^2 over |b|^2 / lambda, i.e.
+    (lambda - 1)^2."""
+    from test_oracle_operator import free_field, plane_wave
+    dims = (4, 6, 4, 8)
+    g = free_field(dims, 9.0 / 8.0, -1.0 / 24.0)
+    psi, p = plane_wave(dims, (1, 2, 0, 3), np.array([0.3 + 0.1j, -0.7j, 1.1]))
+    b = oracle.restrict(dims, 0, psi)
+    sigma = 4 * 0.1 ** 2
+    s = [9.0 / 8.0 * np.sin(pm) - np.sin(3 * pm) / 24.0 for pm in p]
+    lam = sigma + 4 * sum(x * x for x in s)
+    x = b / lam
+    loss, _ = N.loss_and_grad(N.Network.identity(), g, [sigma], [b], [x])
+    assert abs(loss - (lam - 1) ** 2) <= 1e-12 * max(1.0, loss)
 
 
 def test_adam_first_step_closed_form():
