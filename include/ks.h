@@ -331,16 +331,20 @@ ks_status_t ks_batch_free(ks_batch_t b);
 
 /* ------------------------------------------------------------------ learned preconditioner */
 
-/* A gauge-covariant network used as the preconditioner of flexible CG.  Layer l maps c_in to
- * c_out channels of colour-vector fields on the full lattice:
+/* A gauge-covariant network used as the preconditioner of flexible CG (the paper leaves the
+ * solver's preconditioning open; this one is learned).  A layer maps c_in to c_out channels of
+ * colour-vector fields on the full lattice:
  *     y_c(x) = sum_{c', p} w_{c c' p} (T_p phi_{c'})(x),
  * nine paths p: the identity (p = 0), T_{+mu} phi(x) = V_mu(x) phi(x+mu) (p = 1+mu) and
  * T_{-mu} phi(x) = V_mu(x-mu)^+ phi(x-mu) (p = 5+mu), V the fat link of the gauge handle, so
- * the network commutes with gauge transformations.  Four layers, channels 1, 8, 8, 8, 1, no
- * activation (the network is linear).  Input: an even-site vector (odd sites zero); output:
- * the even sites of the last layer.  Weights: KS_NET_WEIGHTS complex numbers, layer after
- * layer, each layer w[c_out][c_in][9], complex128 (re, im) on the host. */
-#define KS_NET_WEIGHTS 1296
+ * the network commutes with gauge transformations.  The network is N = L^+ L, L two free
+ * layers with channels 1 -> 8 -> 8 and no activation: it applies four layers
+ * 1 -> 8 -> 8 -> 8 -> 1, the last two the adjoints of the first two (channels swapped, weights
+ * w'_{c' c pbar} = conj(w_{c c' p}), pbar the reversed path), so N is Hermitian and
+ * <v, N v> = |L v|^2 >= 0.  Input: an even-site vector (odd sites zero); output: the even sites
+ * of the last layer.  Weights: KS_NET_WEIGHTS complex numbers, L's first layer then its
+ * second, each w[c_out][c_in][9], complex128 (re, im) on the host. */
+#define KS_NET_WEIGHTS 648
 typedef struct ks_net_s* ks_net_t;
 
 ks_status_t ks_net_create(ks_net_t* out, const double* weights);
@@ -349,35 +353,43 @@ ks_status_t ks_net_get_weights(ks_net_t n, double* weights);
 ks_status_t ks_net_free(ks_net_t n);
 
 /* out_dev = N(in_dev), complex128 [Vh][3] device arrays of the handle's lattice.  use_mfma = 0:
- * FP32 channel mixing on the vector ALUs, transports with the FP32 fat links; 1: the 8 -> 8 and
- * 8 -> 1 layers mix on the matrix cores (binary16 operands, FP32 accumulation) and transport
- * in FP32 arithmetic with the binary16 fat-link store (built on first use).
- * Synchronous with respect to `stream` order only (no host wait). */
+ * FP32 channel mixing on the vector ALUs, transports with the FP32 fat links; 1: the three
+ * last layers (8 -> 8, 8 -> 8, 8 -> 1) mix on the matrix cores (binary16 operands, FP32
+ * accumulation) and transport in FP32 arithmetic with the binary16 fat-link store (built on
+ * first use).  Asynchronous on `stream`. */
 ks_status_t ks_net_apply(ks_net_t n, ks_gauge_t g, const double* in_dev, double* out_dev,
                          int use_mfma, hipStream_t stream);
 
-/* Loss L = (1/B) sum_j |N(b_j) - x_j|^2 / |x_j|^2 over npairs = B pairs (b_j, x_j on lattice
- * gauges[j], complex128 [Vh_j][3] device arrays) and its gradient, G = dL/dRe w + i dL/dIm w,
- * written to grad (host, complex128 [KS_NET_WEIGHTS]) when not NULL.  FP32 forward and
- * backward kernels, FP64 reductions.  Synchronises the stream. */
+/* Loss over npairs = B pairs (b_j, x_j), A_j x_j = b_j with A_j = sigma_j - D_eo D_oe on
+ * lattice gauges[j] (b_j, x_j complex128 [Vh_j][3] device arrays, sigma host [npairs]): the
+ * A-norm error of N b_j relative to that of x_j, the quantity CG minimises,
+ *     L = (1/B) sum_j (N b_j - x_j)^+ A_j (N b_j - x_j) / (x_j^+ A_j x_j)
+ * (x_j^+ A_j x_j taken as Re<x_j, b_j>), and its gradient with respect to the free weights,
+ * G = dL/dRe w + i dL/dIm w, written to grad (host, complex128 [KS_NET_WEIGHTS]) when not NULL.
+ * FP32 forward and backward kernels, FP64 A-apply and reductions.  Synchronises the stream.
+ * KS_ERR_ARG for null entries, a negative shift or Re<x_j, b_j> <= 0. */
 ks_status_t ks_net_loss_grad(ks_net_t n, int npairs, const ks_gauge_t* gauges,
-                             const double* const* b_dev, const double* const* x_dev,
-                             double* loss, double* grad, hipStream_t stream);
+                             const double* sigma, const double* const* b_dev,
+                             const double* const* x_dev, double* loss, double* grad,
+                             hipStream_t stream);
 
 /* steps Adam steps (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr, on the real and
  * imaginary parts separately); step k uses the minibatch of `batch` pairs starting at pair
  * (k * batch) mod npairs, cyclically.  loss_history (host, [steps]) receives the minibatch
  * loss before each step when not NULL.  Synchronises the stream. */
-ks_status_t ks_net_train(ks_net_t n, int npairs, const ks_gauge_t* gauges,
+ks_status_t ks_net_train(ks_net_t n, int npairs, const ks_gauge_t* gauges, const double* sigma,
                          const double* const* b_dev, const double* const* x_dev, int steps,
                          int batch, double lr, double* loss_history, hipStream_t stream);
 
-/* Flexible CG for (4 m^2 - D_eo D_oe) x = b preconditioned by the network (z = N(r)), with
- * the inner operator and vectors in p->inner precision (KS_F16 is taken as KS_F32), x in FP64,
- * FP64 reliable updates, and fallback to ks_cg_solve's method from the current x when N(r)
- * is not finite, when Re<N(r), r> <= 0, when |r| has not halved in 50 steps, or at
- * p->max_iter (st->fallback = the reason's code, st->restarts = steps of the fallback).  b_dev, x_dev as in
- * ks_cg_solve. */
+/* Flexible CG (Notay's, truncated to one previous direction) for (4 m^2 - D_eo D_oe) x = b
+ * preconditioned by the network (z = N(r)), with the inner operator and vectors in p->inner
+ * precision (KS_F16 is taken as KS_F32), x in FP64 (FP32 increments between reliable updates
+ * in reduced precision), FP64 reliable updates as in ks_cg_solve; A and N are Hermitian, so
+ * alpha = <p, r> / <p, A p> and beta = -<z, A p> / <p, A p> are real.  All scalars stay on the
+ * device (the host reads a status block every p->check_every steps).  Falls back to
+ * ks_cg_solve's method from the current x when N(r) is not finite, when <N(r), r> <= 0, when
+ * <p, A p> <= 0, when |r| has not halved over 50 steps, or at p->max_iter (st->fallback = the
+ * reason's code, st->restarts = steps of the fallback).  b_dev, x_dev as in ks_cg_solve. */
 ks_status_t ks_fcg_solve(ks_gauge_t g, ks_net_t n, double mass, const double* b_dev,
                          double* x_dev, const ks_solver_params* p, int use_mfma,
                          ks_solver_stats* st, hipStream_t stream);

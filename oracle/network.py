@@ -157,14 +157,17 @@ def half_forward(net: Network, g, r_e: np.ndarray, nb=None) -> np.ndarray:
     return phi
 
 
-def network_forward(net: Network, g, r_e: np.ndarray, nb=None):
-    """N(r_e) on even sites, plus the cache of transported activations per applied layer."""
+def network_forward(net: Network, g, r_e: np.ndarray, nb=None, keep_cache: bool = True):
+    """N(r_e) on even sites, plus the cache of transported activations per applied layer
+    (an empty list when keep_cache is False, which keeps large lattices within memory)."""
     nb = nb if nb is not None else neighbour_tables(g.dims)
     phi = embed(g.dims, 0, r_e)[None]
     cache = []
     for w in net.layers():
         phi, tphi = layer_forward(g.fat, nb, w, phi)
-        cache.append(tphi)
+        if keep_cache:
+            cache.append(tphi)
+        del tphi
     return restrict(g.dims, 0, phi[0]), cache
 
 

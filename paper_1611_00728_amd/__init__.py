@@ -448,12 +448,12 @@ class Batch:
             pass
 
 
-NET_WEIGHTS = 1296
+NET_WEIGHTS = 648
 
 
 class Net:
-    """The preconditioner network (ks_net_create); weights: complex128 [1296] (layer by layer,
-    each w[c_out][c_in][9])."""
+    """The preconditioner network N = L^+ L (ks_net_create); weights: complex128 [648], L's two
+    free layers (1 -> 8, then 8 -> 8), each w[c_out][c_in][9]."""
 
     def __init__(self, weights):
         import numpy as np
@@ -466,10 +466,12 @@ class Net:
         L.ks_net_get_weights.argtypes = [_vp, _vp]
         L.ks_net_free.argtypes = [_vp]
         L.ks_net_apply.argtypes = [_vp, _vp, _vp, _vp, C.c_int, _vp]
-        L.ks_net_loss_grad.argtypes = [_vp, C.c_int, C.POINTER(_vp), C.POINTER(_vp),
-                                       C.POINTER(_vp), C.POINTER(C.c_double), _vp, _vp]
-        L.ks_net_train.argtypes = [_vp, C.c_int, C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp),
-                                   C.c_int, C.c_int, C.c_double, _vp, _vp]
+        L.ks_net_loss_grad.argtypes = [_vp, C.c_int, C.POINTER(_vp), C.POINTER(C.c_double),
+                                       C.POINTER(_vp), C.POINTER(_vp), C.POINTER(C.c_double),
+                                       _vp, _vp]
+        L.ks_net_train.argtypes = [_vp, C.c_int, C.POINTER(_vp), C.POINTER(C.c_double),
+                                   C.POINTER(_vp), C.POINTER(_vp), C.c_int, C.c_int, C.c_double,
+                                   _vp, _vp]
         L.ks_fcg_solve.argtypes = [_vp, _vp, C.c_double, _vp, _vp, C.POINTER(SolverParams),
                                    C.c_int, C.POINTER(SolverStats), _vp]
         h = _vp()
@@ -496,30 +498,34 @@ class Net:
         return out
 
     @staticmethod
-    def _pairs(gauges, bs, xs):
+    def _pairs(gauges, sigmas, bs, xs):
         n = len(gauges)
-        if len(bs) != n or len(xs) != n:
-            raise ValueError("one gauge, source and solution per pair")
+        if len(bs) != n or len(xs) != n or len(sigmas) != n:
+            raise ValueError("one gauge, shift, source and solution per pair")
         gp = (_vp * n)(*[g.handle.value for g in gauges])
+        sp = (C.c_double * n)(*[float(v) for v in sigmas])
         bp = (_vp * n)(*[_dev_vec(b, g.vh, "b").value for b, g in zip(bs, gauges)])
         xp = (_vp * n)(*[_dev_vec(x, g.vh, "x").value for x, g in zip(xs, gauges)])
-        return n, gp, bp, xp
+        return n, gp, sp, bp, xp
 
-    def loss_grad(self, gauges, bs, xs, stream=None):
+    def loss_grad(self, gauges, sigmas, bs, xs, stream=None):
+        """A-norm loss of the pairs (A_j = sigmas[j] - D_eo D_oe on gauges[j]) and its
+        gradient with respect to the free weights."""
         import numpy as np
-        n, gp, bp, xp = self._pairs(gauges, bs, xs)
+        n, gp, sp, bp, xp = self._pairs(gauges, sigmas, bs, xs)
         loss = C.c_double()
         grad = np.zeros(NET_WEIGHTS, dtype=np.complex128)
-        _check(lib().ks_net_loss_grad(self.handle, n, gp, bp, xp, C.byref(loss),
+        _check(lib().ks_net_loss_grad(self.handle, n, gp, sp, bp, xp, C.byref(loss),
                                       _vp(grad.ctypes.data), _stream(stream)))
         return loss.value, grad
 
-    def train(self, gauges, bs, xs, steps: int, batch: int, lr: float = 1e-3, stream=None):
+    def train(self, gauges, sigmas, bs, xs, steps: int, batch: int, lr: float = 1e-3,
+              stream=None):
         import numpy as np
-        n, gp, bp, xp = self._pairs(gauges, bs, xs)
+        n, gp, sp, bp, xp = self._pairs(gauges, sigmas, bs, xs)
         hist = np.zeros(max(steps, 1))
-        _check(lib().ks_net_train(self.handle, n, gp, bp, xp, int(steps), int(batch), float(lr),
-                                  _vp(hist.ctypes.data), _stream(stream)))
+        _check(lib().ks_net_train(self.handle, n, gp, sp, bp, xp, int(steps), int(batch),
+                                  float(lr), _vp(hist.ctypes.data), _stream(stream)))
         return hist[:steps]
 
     def free(self):

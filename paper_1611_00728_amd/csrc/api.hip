@@ -83,6 +83,8 @@ using namespace ks;
         return KS_ERR_HIP;                                                              \
     }
 
+static_assert(kNetWeights == KS_NET_WEIGHTS, "network weight count of the ABI");
+
 static bool prec_ok(int p) { return p == KS_F64 || p == KS_F32 || p == KS_F16; }
 static bool recon_ok(int r) { return r == KS_RECON_18 || r == KS_RECON_12; }
 
@@ -533,22 +535,27 @@ ks_status_t ks_net_apply(ks_net_t n, ks_gauge_t g, const double* in_dev, double*
     KS_API_END
 }
 
-static void check_pairs(int npairs, const ks_gauge_t* gauges, const double* const* b,
-                        const double* const* x)
+static void check_pairs(int npairs, const ks_gauge_t* gauges, const double* sigma,
+                        const double* const* b, const double* const* x)
 {
-    KS_REQUIRE(npairs >= 1 && gauges && b && x, KS_ERR_ARG, "network: bad training pairs");
-    for (int j = 0; j < npairs; ++j)
+    KS_REQUIRE(npairs >= 1 && gauges && sigma && b && x, KS_ERR_ARG,
+               "network: bad training pairs");
+    for (int j = 0; j < npairs; ++j) {
         KS_REQUIRE(gauges[j] && b[j] && x[j], KS_ERR_ARG, "network: null entry in pair %d", j);
+        KS_REQUIRE(std::isfinite(sigma[j]) && sigma[j] >= 0, KS_ERR_ARG,
+                   "network: shift of pair %d must be finite and >= 0", j);
+    }
 }
 
 ks_status_t ks_net_loss_grad(ks_net_t n, int npairs, const ks_gauge_t* gauges,
-                             const double* const* b_dev, const double* const* x_dev,
-                             double* loss, double* grad, hipStream_t stream)
+                             const double* sigma, const double* const* b_dev,
+                             const double* const* x_dev, double* loss, double* grad,
+                             hipStream_t stream)
 {
     KS_API_BEGIN
     KS_REQUIRE(n && n->ctx, KS_ERR_ARG, "ks_net_loss_grad: null handle");
-    check_pairs(npairs, gauges, b_dev, x_dev);
-    const double l = net_loss_grad(*n->ctx, npairs, gauges, b_dev, x_dev, stream);
+    check_pairs(npairs, gauges, sigma, b_dev, x_dev);
+    const double l = net_loss_grad(*n->ctx, npairs, gauges, sigma, b_dev, x_dev, stream);
     if (loss) *loss = l;
     if (grad) {
         KS_HIP(hipMemcpyAsync(grad, n->ctx->grad, sizeof(double) * 2 * kNetWeights,
@@ -559,25 +566,28 @@ ks_status_t ks_net_loss_grad(ks_net_t n, int npairs, const ks_gauge_t* gauges,
     KS_API_END
 }
 
-ks_status_t ks_net_train(ks_net_t n, int npairs, const ks_gauge_t* gauges,
+ks_status_t ks_net_train(ks_net_t n, int npairs, const ks_gauge_t* gauges, const double* sigma,
                          const double* const* b_dev, const double* const* x_dev, int steps,
                          int batch, double lr, double* loss_history, hipStream_t stream)
 {
     KS_API_BEGIN
     KS_REQUIRE(n && n->ctx, KS_ERR_ARG, "ks_net_train: null handle");
-    check_pairs(npairs, gauges, b_dev, x_dev);
+    check_pairs(npairs, gauges, sigma, b_dev, x_dev);
     KS_REQUIRE(steps >= 0 && batch >= 1 && lr > 0, KS_ERR_ARG, "ks_net_train: bad steps/batch/lr");
     batch = std::min(batch, npairs);
     std::vector<ks_gauge_t> gs(batch);
+    std::vector<double> sg(batch);
     std::vector<const double*> bs(batch), xs(batch);
     for (int k = 0; k < steps; ++k) {
         for (int j = 0; j < batch; ++j) {
             const int q = (k * batch + j) % npairs;
             gs[j] = gauges[q];
+            sg[j] = sigma[q];
             bs[j] = b_dev[q];
             xs[j] = x_dev[q];
         }
-        const double l = net_loss_grad(*n->ctx, batch, gs.data(), bs.data(), xs.data(), stream);
+        const double l = net_loss_grad(*n->ctx, batch, gs.data(), sg.data(), bs.data(), xs.data(),
+                                       stream);
         if (loss_history) loss_history[k] = l;
         net_adam(*n->ctx, lr, stream);
     }

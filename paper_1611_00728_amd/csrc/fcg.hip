@@ -1,19 +1,25 @@
-// Flexible CG preconditioned by the network (Notay's flexible CG truncated to one previous
-// direction), with FP32 (or FP64) inner operator and vectors, FP64 solution accumulation,
-// FP64 reliable updates, and plain CG as the fallback:
+// Flexible CG preconditioned by the network N = L^+ L (Notay's flexible CG truncated to one
+// previous direction), with the inner operator and vectors in FP32 (or FP64), x accumulated in
+// FP64 (through FP32 increments between reliable updates in reduced precision), FP64 reliable
+// updates, and plain CG as the fallback:
 //
 //   r = b - A x, z = N(r), p = z
 //   repeat: q = A p, alpha = <p, r> / <p, q>, x += alpha p, r -= alpha q,
-//           z = N(r), beta = -<q, z> / <p, q>, p = z + beta p
+//           z = N(r), beta = -<z, q> / <p, q>, p = z + beta p
 //
-// (complex alpha, beta: N need not be Hermitian).  With N the identity this is CG step for
-// step.  Fallback to ks_cg_solve's method from the current x when z is not finite, when
-// Re<z, r> <= 0, when |r| has not halved over the last 50 steps, or at max_iter.
+// A and N are Hermitian, so alpha and beta are real (the real parts of the products are
+// taken); with N the identity this is CG step for step.  Every scalar lives on the device:
+// the kernels of a step read a gate flag and do nothing once it is set (converged, reliable
+// update due, or a fallback condition), so the host queues `check_every` steps at a time and
+// reads a small status block per chunk.  Fallback to ks_cg_solve's method from the current x
+// when N(r) is not finite, when <z, r> <= 0, when <p, A p> <= 0, when |r| has not halved over
+// 50 steps, or at max_iter.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
-#include <complex>
 #include <deque>
 #include <map>
+#include <utility>
 
 #include "ks_blas.h"
 #include "ks_device.h"
@@ -25,103 +31,305 @@ namespace ks {
 namespace {
 
 constexpr int kNT = 256;
+constexpr int kFin = 1024;
 
-// partial sums of <a, b> = sum conj(a) b (re, im in two arrays)
-template <int P>
-__global__ __launch_bounds__(kNT) void cdot_kernel(int vh, const void* __restrict__ a,
-                                                   const void* __restrict__ b,
-                                                   double* __restrict__ pre,
-                                                   double* __restrict__ pim)
+// fallback reasons (ks_solver_stats.fallback)
+enum { kNonFinite = 1, kNoDescent = 2, kBreakdown = 3, kStall = 4, kMaxIter = 5 };
+
+struct FcgState {
+    double pq;         // <p, A p>
+    double alpha, beta;
+    double rho;        // |r|^2 of the inner residual after the last step (as stored)
+    double rho_new;
+    double maxr;       // max |r| since the last reliable update
+    double stop2;      // (tol |b|)^2
+    double delta;      // reliable-update threshold (0: only the final check)
+    double scale;      // network input scale sqrt(3 Vh / rho): O(1) entries for binary16
+    double zr;         // <z, r>
+    double true_r2;    // |b - A x|^2 of the last FP64 recomputation
+    int vh;
+    int iter, max_iter, gate, ru_pending, done, reason;
+};
+
+// Every block sums the partials itself in one fixed order, so all blocks agree bit for bit.
+__device__ __forceinline__ double block_fused_sum(const double* __restrict__ in, int n)
 {
-    using R = typename St<P>::R;
-    const int h = blockIdx.x * blockDim.x + threadIdx.x;
-    double sr = 0.0, si = 0.0;
-    if (h < vh) {
-        cx<R> av[3], bv[3];
-        Spinor<P>::load(a, vh, h, av);
-        Spinor<P>::load(b, vh, h, bv);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            sr += (double)av[k].r * bv[k].r + (double)av[k].i * bv[k].i;
-            si += (double)av[k].r * bv[k].i - (double)av[k].i * bv[k].r;
-        }
-    }
-    sr = block_sum<kNT>(sr);
+    __shared__ double total;
+    double t = 0.0;
+    for (int k = threadIdx.x; k < n; k += kCgFuse) t += in[k];
+    t = block_sum<kCgFuse>(t);
+    if (threadIdx.x == 0) total = t;
     __syncthreads();
-    si = block_sum<kNT>(si);
-    if (threadIdx.x == 0) {
-        pre[blockIdx.x] = sr;
-        pim[blockIdx.x] = si;
-    }
+    return total;
 }
 
-// x (FP64) += alpha p; r -= alpha q (complex alpha); partial sums of |r|^2 as stored
+__device__ __forceinline__ double one_block_sum(const double* __restrict__ in, int n)
+{
+    double t = 0.0;
+    for (int k = threadIdx.x; k < n; k += kFin) t += in[k];
+    return block_sum<kFin>(t);
+}
+
+// alpha = <p, r> / <p, q> from the partials of the previous p update and of the xpay Dslash;
+// x += alpha p, r -= alpha q; partials of |r|^2 as stored.
 template <int P>
-__global__ __launch_bounds__(kNT) void fcg_update_kernel(int vh, double2* __restrict__ x,
-                                                         const void* __restrict__ p,
-                                                         const void* __restrict__ q,
-                                                         void* __restrict__ r, double ar, double ai,
-                                                         double* __restrict__ partials)
+__global__ __launch_bounds__(kCgFuse) void fcg_update_kernel(int vh, void* __restrict__ x,
+                                                             const void* __restrict__ p,
+                                                             const void* __restrict__ q,
+                                                             void* __restrict__ r,
+                                                             FcgState* __restrict__ st,
+                                                             const double* __restrict__ pq_part,
+                                                             int npq,
+                                                             const double* __restrict__ pr_part,
+                                                             int npr, double* __restrict__ rr_part)
 {
     using R = typename St<P>::R;
-    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    constexpr int kX = P == KS_F64 ? KS_F64 : KS_F32;
+    using XR = typename St<kX>::R;
+    __shared__ int gated;
+    if (threadIdx.x == 0) gated = st->gate;
+    __syncthreads();
+    if (gated) return;
+    const double pq = block_fused_sum(pq_part, npq);
+    const double pr = block_fused_sum(pr_part, npr);
+    const bool ok = isfinite(pq) && pq > 0.0 && isfinite(pr);
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (lead) {
+        st->pq = pq;
+        if (ok) {
+            st->alpha = pr / pq;
+        } else {
+            st->reason = isfinite(pq) && isfinite(pr) ? kBreakdown : kNonFinite;
+            st->gate = 1;
+        }
+    }
+    if (!ok) return;
+    const double alpha = pr / pq;
+    const int h = blockIdx.x * kCgFuse + threadIdx.x;
     double s = 0.0;
     if (h < vh) {
         cx<R> pv[3], qv[3], rv[3];
+        cx<XR> xv[3];
         Spinor<P>::load(p, vh, h, pv);
         Spinor<P>::load(q, vh, h, qv);
         Spinor<P>::load(r, vh, h, rv);
-        const cx<R> a = {(R)ar, (R)ai};
+        Spinor<kX>::load(x, vh, h, xv);
+        const XR ax = (XR)alpha;
+        const R a = (R)alpha;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            double2 t = x[(size_t)k * vh + h];
-            t.x += ar * (double)pv[k].r - ai * (double)pv[k].i;
-            t.y += ar * (double)pv[k].i + ai * (double)pv[k].r;
-            x[(size_t)k * vh + h] = t;
-            const cx<R> d = cmul(a, qv[k]);
-            rv[k].r -= d.r;
-            rv[k].i -= d.i;
+            xv[k].r = fma(ax, (XR)pv[k].r, xv[k].r);
+            xv[k].i = fma(ax, (XR)pv[k].i, xv[k].i);
+            rv[k].r = fma(-a, qv[k].r, rv[k].r);
+            rv[k].i = fma(-a, qv[k].i, rv[k].i);
         }
+        Spinor<kX>::store(x, vh, h, xv);
         Spinor<P>::store(r, vh, h, rv);
-        Spinor<P>::round(rv);
 #pragma unroll
         for (int k = 0; k < 3; ++k)
-            s += (double)rv[k].r * rv[k].r + (double)rv[k].i * rv[k].i;
+            s += (double)rv[k].r * (double)rv[k].r + (double)rv[k].i * (double)rv[k].i;
     }
-    s = block_sum<kNT>(s);
-    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+    s = block_sum<kCgFuse>(s);
+    if (threadIdx.x == 0) rr_part[blockIdx.x] = s;
 }
 
-// p = z + beta p (complex beta)
+// |r|^2 after the update: stop for a reliable update (or the final check), at max_iter, or go
+// on with the network's input scale for this r.
+__global__ __launch_bounds__(kFin) void fcg_check_kernel(const double* __restrict__ rr_part, int n,
+                                                         FcgState* __restrict__ st)
+{
+    if (st->gate) return;
+    const double rn = one_block_sum(rr_part, n);
+    if (threadIdx.x != 0) return;
+    st->iter += 1;
+    st->rho_new = rn;
+    if (!isfinite(rn)) {
+        st->reason = kNonFinite;
+        st->gate = 1;
+        return;
+    }
+    const double s = sqrt(rn);
+    if (rn <= st->stop2 || s < st->delta * st->maxr) {
+        st->ru_pending = 1;
+        st->gate = 1;
+        return;
+    }
+    st->rho = rn;
+    st->maxr = fmax(st->maxr, s);
+    st->scale = rn > 0.0 ? sqrt(3.0 * st->vh / rn) : 1.0;
+    if (st->iter >= st->max_iter) {
+        st->reason = kMaxIter;
+        st->gate = 1;
+    }
+}
+
+// partials of Re<z, r> and Re<z, q>
 template <int P>
-__global__ __launch_bounds__(kNT) void fcg_p_kernel(int vh, const void* __restrict__ z,
-                                                    void* __restrict__ p, double br, double bi)
+__global__ __launch_bounds__(kNT) void fcg_dots_kernel(int vh, const void* __restrict__ z,
+                                                       const void* __restrict__ r,
+                                                       const void* __restrict__ q,
+                                                       const FcgState* __restrict__ st,
+                                                       double* __restrict__ zr_part,
+                                                       double* __restrict__ zq_part)
 {
     using R = typename St<P>::R;
+    if (st->gate) return;
     const int h = blockIdx.x * blockDim.x + threadIdx.x;
-    if (h >= vh) return;
-    cx<R> zv[3], pv[3];
-    Spinor<P>::load(z, vh, h, zv);
-    Spinor<P>::load(p, vh, h, pv);
-    const cx<R> b = {(R)br, (R)bi};
+    double a = 0.0, b = 0.0;
+    if (h < vh) {
+        cx<R> zv[3], rv[3], qv[3];
+        Spinor<P>::load(z, vh, h, zv);
+        Spinor<P>::load(r, vh, h, rv);
+        Spinor<P>::load(q, vh, h, qv);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const cx<R> d = cmul(b, pv[k]);
-        pv[k] = {zv[k].r + d.r, zv[k].i + d.i};
+        for (int k = 0; k < 3; ++k) {
+            a += (double)zv[k].r * rv[k].r + (double)zv[k].i * rv[k].i;
+            b += (double)zv[k].r * qv[k].r + (double)zv[k].i * qv[k].i;
+        }
     }
-    Spinor<P>::store(p, vh, h, pv);
+    a = block_sum<kNT>(a);
+    __syncthreads();
+    b = block_sum<kNT>(b);
+    if (threadIdx.x == 0) {
+        zr_part[blockIdx.x] = a;
+        zq_part[blockIdx.x] = b;
+    }
+}
+
+// beta = -<z, q> / <p, q> (0 on the first step), p = z + beta p, and partials of Re<p, r> for
+// the next step's alpha.  <z, r> must be finite and positive (N positive on r).
+template <int P>
+__global__ __launch_bounds__(kCgFuse) void fcg_p_kernel(int vh, const void* __restrict__ z,
+                                                        const void* __restrict__ r,
+                                                        void* __restrict__ p,
+                                                        FcgState* __restrict__ st,
+                                                        const double* __restrict__ zr_part,
+                                                        const double* __restrict__ zq_part, int nz,
+                                                        double* __restrict__ pr_part, int first)
+{
+    using R = typename St<P>::R;
+    __shared__ int gated;
+    if (threadIdx.x == 0) gated = st->gate;
+    __syncthreads();
+    if (gated) return;
+    const double zr = block_fused_sum(zr_part, nz);
+    const double zq = block_fused_sum(zq_part, nz);
+    const double pq = st->pq;
+    // on the first step q holds no A p yet: p = z, and <z, q> is not used
+    const bool finite = isfinite(zr) && (first || isfinite(zq));
+    const bool ok = finite && zr > 0.0;
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    const double beta = first ? 0.0 : -zq / pq;
+    if (lead) {
+        st->zr = zr;
+        if (ok) {
+            st->beta = beta;
+        } else {
+            st->reason = finite ? kNoDescent : kNonFinite;
+            st->gate = 1;
+        }
+    }
+    if (!ok) return;
+    const int h = blockIdx.x * kCgFuse + threadIdx.x;
+    double s = 0.0;
+    if (h < vh) {
+        cx<R> zv[3], rv[3], pv[3];
+        Spinor<P>::load(z, vh, h, zv);
+        Spinor<P>::load(r, vh, h, rv);
+        if (first) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) pv[k] = zv[k];
+        } else {
+            Spinor<P>::load(p, vh, h, pv);
+            const R b = (R)beta;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                pv[k].r = fma(b, pv[k].r, zv[k].r);
+                pv[k].i = fma(b, pv[k].i, zv[k].i);
+            }
+        }
+        Spinor<P>::store(p, vh, h, pv);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) s += (double)pv[k].r * rv[k].r + (double)pv[k].i * rv[k].i;
+    }
+    s = block_sum<kCgFuse>(s);
+    if (threadIdx.x == 0) pr_part[blockIdx.x] = s;
+}
+
+// After r = b - A x in FP64: converged, or go on from this residual.
+__global__ __launch_bounds__(kFin) void fcg_reliable_kernel(const double* __restrict__ part, int n,
+                                                            FcgState* __restrict__ st)
+{
+    const double r2 = one_block_sum(part, n);
+    if (threadIdx.x != 0) return;
+    st->true_r2 = r2;
+    st->ru_pending = 0;
+    if (!isfinite(r2)) {
+        st->reason = kNonFinite;
+        st->gate = 1;
+        return;
+    }
+    if (r2 <= st->stop2) {
+        st->done = 1;
+        st->gate = 1;
+        return;
+    }
+    st->rho = r2;
+    st->maxr = sqrt(r2);
+    st->scale = sqrt(3.0 * st->vh / r2);
+    st->gate = 0;
+    if (st->iter >= st->max_iter) {
+        st->reason = kMaxIter;
+        st->gate = 1;
+    }
 }
 
 struct FcgBufs {
-    double* aos_in = nullptr;    // complex128 [Vh][3] network input / output staging
-    double* aos_out = nullptr;
     void* z = nullptr;
-    double* pim = nullptr;       // second partial array for complex dots
+    double* zr_part = nullptr;
+    double* zq_part = nullptr;
+    double* pr_part = nullptr;
+    FcgState* st = nullptr;
+    FcgState* st_host = nullptr;   // pinned
     int vh = 0;
     int prec = -1;
 };
 
-std::map<ks_gauge_t, FcgBufs> g_fcg;   // per gauge handle (freed with the handle's workspace)
+std::map<ks_gauge_t, FcgBufs> g_fcg;   // per gauge handle (freed with the handle)
+
+void free_bufs(FcgBufs& fb)
+{
+    device_free(fb.z);
+    device_free(fb.zr_part);
+    device_free(fb.zq_part);
+    device_free(fb.pr_part);
+    device_free(fb.st);
+    if (fb.st_host) (void)hipHostFree(fb.st_host);
+    fb = FcgBufs();
+}
+
+template <int P>
+void launch_step_kernels(int vh, void* xu, void* ps, void* qs, void* rs, FcgBufs& fb,
+                         Workspace& w, int npq, hipStream_t s)
+{
+    const int nf = blocks_for(vh, kCgFuse);
+    fcg_update_kernel<P><<<nf, kCgFuse, 0, s>>>(vh, xu, ps, qs, rs, fb.st, w.partials, npq,
+                                                 fb.pr_part, nf, w.rr_part);
+    fcg_check_kernel<<<1, kFin, 0, s>>>(w.rr_part, nf, fb.st);
+    KS_HIP(hipGetLastError());
+}
+
+template <int P>
+void launch_tail_kernels(int vh, void* zs, void* rs, void* qs, void* ps, FcgBufs& fb, int first,
+                         hipStream_t s)
+{
+    const int nb = blocks_for(vh, kNT);
+    const int nf = blocks_for(vh, kCgFuse);
+    fcg_dots_kernel<P><<<nb, kNT, 0, s>>>(vh, zs, rs, qs, fb.st, fb.zr_part, fb.zq_part);
+    fcg_p_kernel<P><<<nf, kCgFuse, 0, s>>>(vh, zs, rs, ps, fb.st, fb.zr_part, fb.zq_part, nb,
+                                           fb.pr_part, first);
+    KS_HIP(hipGetLastError());
+}
 
 }  // namespace
 
@@ -129,10 +337,7 @@ void fcg_release(ks_gauge_t g)
 {
     auto it = g_fcg.find(g);
     if (it == g_fcg.end()) return;
-    device_free(it->second.aos_in);
-    device_free(it->second.aos_out);
-    device_free(it->second.z);
-    device_free(it->second.pim);
+    free_bufs(it->second);
     g_fcg.erase(it);
 }
 
@@ -150,61 +355,35 @@ ks_status_t fcg_core(ks_gauge_t g, NetCtx& net, double sigma, const double* b, d
     gauge_prepare(g, KS_F32, KS_RECON_18, s);
     FcgBufs& fb = g_fcg[g];
     if (fb.vh != vh || fb.prec != (int)P) {
-        device_free(fb.aos_in);
-        device_free(fb.aos_out);
-        device_free(fb.z);
-        device_free(fb.pim);
-        fb = FcgBufs();
-        fb.aos_in = static_cast<double*>(device_alloc((size_t)vh * 48));
-        fb.aos_out = static_cast<double*>(device_alloc((size_t)vh * 48));
+        free_bufs(fb);
         fb.z = device_alloc(field_bytes(G, P));
-        fb.pim = static_cast<double*>(device_alloc(sizeof(double) * (w.npart + 8)));
+        fb.zr_part = static_cast<double*>(device_alloc(sizeof(double) * blocks_for(vh, kNT)));
+        fb.zq_part = static_cast<double*>(device_alloc(sizeof(double) * blocks_for(vh, kNT)));
+        fb.pr_part = static_cast<double*>(device_alloc(sizeof(double) * blocks_for(vh, kCgFuse)));
+        fb.st = static_cast<FcgState*>(device_alloc(sizeof(FcgState)));
+        KS_HIP(hipHostMalloc(reinterpret_cast<void**>(&fb.st_host), sizeof(FcgState)));
         fb.vh = vh;
         fb.prec = (int)P;
     }
-    // inner vectors
     const size_t fbytes = field_bytes(G, P);
-    if (!w.rs[P]) w.rs[P] = device_alloc(fbytes);
-    if (!w.ps[P]) w.ps[P] = device_alloc(fbytes);
-    if (!w.qs[P]) w.qs[P] = device_alloc(fbytes);
-    if (!w.ts[P]) w.ts[P] = device_alloc(fbytes);
+    for (void** v : {&w.rs[P], &w.ps[P], &w.qs[P], &w.ts[P]})
+        if (!*v) {
+            *v = device_alloc(fbytes);
+            w.bytes += fbytes;
+        }
+    const bool sloppy = P != KS_F64;
+    if (sloppy && !w.dx32) {
+        w.dx32 = device_alloc(field_bytes(G, KS_F32));
+        w.bytes += field_bytes(G, KS_F32);
+    }
     void* rs = (P == KS_F64) ? static_cast<void*>(w.r64) : w.rs[P];
     void* ps = w.ps[P];
     void* qs = w.qs[P];
     void* ts = w.ts[P];
     void* zs = fb.z;
-    const int nb = blocks_for(vh, kNT);
-    double* hs = w.host_scal;
-
-    auto sync_read = [&](int n) {
-        KS_HIP(hipMemcpyAsync(hs, w.scal, sizeof(double) * n, hipMemcpyDeviceToHost, s));
-        KS_HIP(hipStreamSynchronize(s));
-    };
-    auto cdot = [&](const void* a, const void* bb, int slot) {
-        if (P == KS_F64) cdot_kernel<KS_F64><<<nb, kNT, 0, s>>>(vh, a, bb, w.partials, fb.pim);
-        else cdot_kernel<KS_F32><<<nb, kNT, 0, s>>>(vh, a, bb, w.partials, fb.pim);
-        KS_HIP(hipGetLastError());
-        reduce_sum(w.partials, nb, w.scal + slot, s);
-        reduce_sum(fb.pim, nb, w.scal + slot + 1, s);
-    };
-    // true residual into r64 and the inner r; returns |r|^2
-    auto reliable = [&]() {
-        apply_A64(g, sigma, x, w.ax64, s, nullptr);
-        sub_norm_partials(vh, b, w.ax64, w.r64, w.partials, s);
-        reduce_sum(w.partials, w.npart, w.scal, s);
-        if (P != KS_F64) convert_field(vh, KS_F64, w.r64, P, rs, nullptr, s);
-        sync_read(1);
-        return hs[0];
-    };
-    auto precondition = [&](double rho) {
-        // z = N(r): the network is linear, so the input is scaled to O(1) entries and the
-        // output scaled back
-        export_field(G, P, rs, fb.aos_in, s);
-        const double sc = rho > 0 ? std::sqrt((double)vh / rho) : 1.0;
-        if (use_mfma) net_apply_mfma(net, g, fb.aos_in, fb.aos_out, sc, s);
-        else net_apply_f32(net, g, fb.aos_in, fb.aos_out, sc, s);
-        import_field(G, P, fb.aos_out, zs, s);
-    };
+    void* xu = sloppy ? w.dx32 : static_cast<void*>(x);
+    FcgState* st = fb.st;
+    FcgState* hs = fb.st_host;
 
     stats = ks_solver_stats();
     const double b2 = norm2_host(g, b, s);
@@ -214,36 +393,44 @@ ks_status_t fcg_core(ks_gauge_t g, NetCtx& net, double sigma, const double* b, d
         KS_HIP(hipStreamSynchronize(s));
         return KS_SUCCESS;
     }
-    const double stop2 = prm.tol * prm.tol * b2;
-    const double delta = (P == KS_F64) ? 0.0 : prm.delta;
-    double rho = reliable();
-    double maxr = std::sqrt(rho);
-    double true_r2 = rho;
-    int it = 0, ru = 0;
-    bool done = rho <= stop2, fallback = false;
-    int reason = 0;   // why the flexible iteration stopped (see ks_solver_stats.fallback)
-    std::deque<double> hist;
-    hist.push_back(std::sqrt(rho));
-    std::complex<double> zr;
-    if (!done) {
-        precondition(rho);
-        convert_field(vh, P, zs, P, ps, nullptr, s);   // p = z
-        cdot(zs, rs, 0);
-        sync_read(2);
-        zr = {hs[0], hs[1]};
-    }
-    while (!done) {
-        if (!std::isfinite(zr.real()) || !std::isfinite(zr.imag())) reason = 1;
-        else if (zr.real() <= 0.0) reason = 2;
-        else if (it >= prm.max_iter) reason = 5;
-        if (reason) {
-            fallback = true;
-            break;
-        }
+    FcgState init{};
+    init.stop2 = prm.tol * prm.tol * b2;
+    init.delta = sloppy ? prm.delta : 0.0;
+    init.max_iter = prm.max_iter;
+    init.vh = vh;
+    init.gate = 1;
+    *hs = init;
+    KS_HIP(hipMemcpyAsync(st, hs, sizeof(FcgState), hipMemcpyHostToDevice, s));
+    if (sloppy) KS_HIP(hipMemsetAsync(w.dx32, 0, field_bytes(G, KS_F32), s));
+
+    auto read_state = [&]() {
+        KS_HIP(hipMemcpyAsync(hs, st, sizeof(FcgState), hipMemcpyDeviceToHost, s));
+        KS_HIP(hipStreamSynchronize(s));
+    };
+    auto flush = [&]() {
+        if (sloppy) flush_dx(vh, w.dx32, x, s);
+    };
+    // r = b - A x in FP64 (after adding x's FP32 increments), into the inner r
+    auto reliable = [&]() {
+        flush();
+        apply_A64(g, sigma, x, w.ax64, s, nullptr);
+        sub_norm_partials(vh, b, w.ax64, w.r64, w.partials, s);
+        fcg_reliable_kernel<<<1, kFin, 0, s>>>(w.partials, w.npart, st);
+        KS_HIP(hipGetLastError());
+        if (sloppy) convert_field(vh, KS_F64, w.r64, P, rs, &st->gate, s);
+    };
+    // z = N(r), the dot products, and the new direction
+    auto tail = [&](int first) {
+        net_apply_spinor(net, g, P, rs, zs, &st->scale, &st->gate, use_mfma, s);
+        if (P == KS_F64) launch_tail_kernels<KS_F64>(vh, zs, rs, qs, ps, fb, first, s);
+        else launch_tail_kernels<KS_F32>(vh, zs, rs, qs, ps, fb, first, s);
+    };
+    auto step = [&]() {
         DslashArgs a1;
         a1.out_parity = 1;
         a1.in = ps;
         a1.out = ts;
+        a1.gate = &st->gate;
         dslash(g, P, RC, a1, s);
         DslashArgs a2;
         a2.out_parity = 0;
@@ -252,66 +439,67 @@ ks_status_t fcg_core(ks_gauge_t g, NetCtx& net, double sigma, const double* b, d
         a2.x = ps;
         a2.a = sigma;
         a2.dot_partials = w.partials;
+        a2.gate = &st->gate;
         dslash(g, P, RC, a2, s);
-        reduce_sum(w.partials, dslash_blocks(g, P, RC), w.scal + 2, s);
-        if (P == KS_F64) cdot_kernel<KS_F64><<<nb, kNT, 0, s>>>(vh, ps, rs, w.partials, fb.pim);
-        else cdot_kernel<KS_F32><<<nb, kNT, 0, s>>>(vh, ps, rs, w.partials, fb.pim);
-        KS_HIP(hipGetLastError());
-        reduce_sum(w.partials, nb, w.scal + 0, s);
-        reduce_sum(fb.pim, nb, w.scal + 1, s);
-        sync_read(3);
-        const double pap = hs[2];
-        const std::complex<double> pr(hs[0], hs[1]);
-        if (!(pap > 0.0) || !std::isfinite(pap)) {
-            fallback = true;
-            reason = 3;
+        const int npq = dslash_blocks(g, P, RC);
+        if (P == KS_F64) launch_step_kernels<KS_F64>(vh, xu, ps, qs, rs, fb, w, npq, s);
+        else launch_step_kernels<KS_F32>(vh, xu, ps, qs, rs, fb, w, npq, s);
+        tail(0);
+    };
+
+    reliable();
+    tail(1);
+    int ru = 0, restarts = 0;
+    ks_status_t rc = KS_SUCCESS;
+    int reason = 0;
+    const int chunk = std::max(1, prm.check_every);
+    std::deque<std::pair<int, double>> hist;   // (step, |r|) at each host read
+    for (;;) {
+        read_state();
+        if (hs->done) break;
+        if (hs->reason) {
+            reason = hs->reason;
             break;
         }
-        const std::complex<double> alpha = pr / pap;
-        if (P == KS_F64)
-            fcg_update_kernel<KS_F64><<<nb, kNT, 0, s>>>(vh, reinterpret_cast<double2*>(x), ps, qs, rs,
-                                                         alpha.real(), alpha.imag(), w.partials);
-        else
-            fcg_update_kernel<KS_F32><<<nb, kNT, 0, s>>>(vh, reinterpret_cast<double2*>(x), ps, qs, rs,
-                                                         alpha.real(), alpha.imag(), w.partials);
-        KS_HIP(hipGetLastError());
-        reduce_sum(w.partials, nb, w.scal, s);
-        sync_read(1);
-        double rn = hs[0];
-        ++it;
-        if (rn <= stop2 || std::sqrt(rn) < delta * maxr) {
-            rn = reliable();
-            true_r2 = rn;
-            ++ru;
-            maxr = std::sqrt(rn);
-            if (rn <= stop2) {
-                done = true;
+        if (hs->ru_pending) {
+            const bool final_check = hs->rho_new <= hs->stop2;
+            reliable();
+            read_state();
+            if (hs->done) break;
+            if (hs->reason) {
+                reason = hs->reason;
                 break;
             }
+            if (final_check) {
+                if (++restarts > prm.max_restarts) {
+                    rc = KS_ERR_NOT_CONVERGED;
+                    set_error("flexible CG: true residual above tolerance after %d restarts",
+                              restarts - 1);
+                    break;
+                }
+            } else {
+                ++ru;
+            }
+            hist.clear();
+            tail(0);
+            continue;
         }
-        maxr = std::max(maxr, std::sqrt(rn));
-        hist.push_back(std::sqrt(rn));
-        if (hist.size() > 51) hist.pop_front();
-        if (hist.size() == 51 && hist.back() > 0.5 * hist.front()) {
-            fallback = true;
-            reason = 4;
+        // |r| must halve over any 50 steps
+        hist.emplace_back(hs->iter, std::sqrt(hs->rho));
+        while (hist.size() > 1 && hist.back().first - hist[1].first >= 50) hist.pop_front();
+        if (hist.back().first - hist.front().first >= 50 &&
+            hist.back().second > 0.5 * hist.front().second) {
+            reason = kStall;
             break;
         }
-        rho = rn;
-        precondition(rho);
-        cdot(qs, zs, 0);   // <q, z>
-        cdot(zs, rs, 2);   // <z, r>
-        sync_read(4);
-        const std::complex<double> qz(hs[0], hs[1]);
-        zr = {hs[2], hs[3]};
-        const std::complex<double> beta = -qz / pap;
-        if (P == KS_F64) fcg_p_kernel<KS_F64><<<nb, kNT, 0, s>>>(vh, zs, ps, beta.real(), beta.imag());
-        else fcg_p_kernel<KS_F32><<<nb, kNT, 0, s>>>(vh, zs, ps, beta.real(), beta.imag());
-        KS_HIP(hipGetLastError());
+        for (int k = 0; k < chunk; ++k) step();
     }
-    ks_status_t rc = KS_SUCCESS;
+    flush();   // x = the last iterate also when the loop stopped for a fallback
+    read_state();
+    const int it = hs->iter;
+    double true_r2 = hs->true_r2;
     int fb_iters = 0;
-    if (fallback) {
+    if (reason && rc == KS_SUCCESS) {
         ks_solver_params q = prm;
         q.max_iter = std::max(1, prm.max_iter - it);
         ks_solver_stats cs;
@@ -323,8 +511,16 @@ ks_status_t fcg_core(ks_gauge_t g, NetCtx& net, double sigma, const double* b, d
     stats.iters = it + fb_iters;
     stats.reliable_updates = ru;
     stats.restarts = fb_iters;        // steps taken by the fallback CG
-    stats.fallback = fallback ? reason : 0;
+    stats.fallback = reason;
     stats.true_rel_resid = std::sqrt(true_r2 / b2);
+    // per flexible step: the CG step's bytes, the network's layers on the full lattice, its
+    // input and output (r read, the full-lattice input written, z written) and the two dot
+    // products (z, r, q) and the p update (z, r, p read, p written)
+    const double sb = (double)field_bytes(G, P) / vh;
+    stats.model_bytes = (double)it * vh *
+                            (cg_iter_model_bytes(P, RC) + 2.0 * net_model_bytes_per_site(use_mfma) +
+                             sb + 48 + 24 + 3 * sb + 4 * sb) +
+                        (ru + restarts + 1) * (2 * dslash_model_bytes(KS_F64, KS_RECON_18) + 192) * vh;
     stats.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return rc;
 }

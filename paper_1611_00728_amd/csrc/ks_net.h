@@ -7,7 +7,10 @@
 
 namespace ks {
 
-constexpr int kNetWeights = 1 * 8 * 9 + 8 * 8 * 9 + 8 * 8 * 9 + 8 * 1 * 9;   // complex weights
+// N = L^+ L: the free weights are those of L's two layers (1 -> 8, 8 -> 8); the network
+// applies four layers (1 -> 8 -> 8 -> 8 -> 1), the last two the adjoints of the first two.
+constexpr int kNetWeights = 1 * 8 * 9 + 8 * 8 * 9;                             // free, complex
+constexpr int kNetLayerWeights = kNetWeights + 8 * 8 * 9 + 8 * 1 * 9;          // applied, complex
 constexpr int kWgradBlocks = 512;
 
 extern const int kLayerIn[4];
@@ -27,12 +30,13 @@ struct NetBuffers {
 };
 
 struct NetCtx {
-    double* w64 = nullptr;      // master weights, complex as (re, im) pairs, layer by layer
-    float* w32 = nullptr;       // FP32 copy used by the kernels
-    float* wadj = nullptr;      // adjoint-layer weights (backward)
+    double* w64 = nullptr;      // master free weights, complex as (re, im) pairs, layer by layer
+    float* w32 = nullptr;       // FP32 weights of the four applied layers
+    float* wadj = nullptr;      // adjoint-layer weights of the applied layers (backward)
     double* adam_m = nullptr;
     double* adam_v = nullptr;
-    double* grad = nullptr;
+    double* grad = nullptr;     // gradient of the free weights
+    double* grad4 = nullptr;    // gradient of the four applied layers' weights
     double* scal = nullptr;
     double* host = nullptr;     // pinned
     int step = 0;               // Adam steps taken
@@ -54,10 +58,19 @@ void net_apply_f32(NetCtx& n, ks_gauge_t g, const double* in, double* out, doubl
 void net_apply_mfma(NetCtx& n, ks_gauge_t g, const double* in, double* out, double in_scale,
                     hipStream_t s);
 void net_mfma_prepare(NetCtx& n, hipStream_t s);
+// algorithmic bytes of one network application per site of the full lattice: each layer reads
+// its site's 8 stored fat links once (FP32, or binary16 on the matrix-core path's three last
+// layers) and its input channels, and writes its output channels (FP32 complex colour vectors)
+double net_model_bytes_per_site(int use_mfma);
 void net_layer_mfma(NetCtx& n, ks_gauge_t g, const float2* in, float2* out, int which,
-                    hipStream_t s);
-double net_loss_grad(NetCtx& n, int npairs, const ks_gauge_t* gauges, const double* const* b,
-                     const double* const* x, hipStream_t s);
+                    const int* gate, hipStream_t s);
+// N applied to an inner-precision field r (Spinor<prec> layout) into z, for the solver: the
+// input is multiplied by *in_scale (device) and the output divided by it; every launch does
+// nothing while *gate != 0.
+void net_apply_spinor(NetCtx& n, ks_gauge_t g, ks_prec_t prec, const void* r, void* z,
+                      const double* in_scale, const int* gate, int use_mfma, hipStream_t s);
+double net_loss_grad(NetCtx& n, int npairs, const ks_gauge_t* gauges, const double* sigma,
+                     const double* const* b, const double* const* x, hipStream_t s);
 void net_adam(NetCtx& n, double lr, hipStream_t s);
 
 ks_status_t fcg_core(ks_gauge_t g, NetCtx& net, double sigma, const double* b, double* x,

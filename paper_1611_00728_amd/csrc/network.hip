@@ -1,9 +1,11 @@
 // Gauge-covariant preconditioner network on the GPU: forward (inference), adjoint and
-// weight-gradient passes, loss, Adam.
+// weight-gradient passes, A-norm loss, Adam.
 //
 // Layer:  y_c(x) = sum_{c', p} w_{c c' p} (T_p phi_{c'})(x), nine paths p: the identity,
 // T_{+mu} phi(x) = V_mu(x) phi(x+mu) (p = 1+mu) and T_{-mu} phi(x) = V_mu(x-mu)^+ phi(x-mu)
-// (p = 5+mu), with the operator's fat link V.  Channels 1 -> 8 -> 8 -> 8 -> 1, no activation.
+// (p = 5+mu), with the operator's fat link V.  The network is N = L^+ L, L two free layers
+// (1 -> 8 -> 8): it applies four layers 1 -> 8 -> 8 -> 8 -> 1, the last two the adjoints of
+// the first two, so N is Hermitian and <v, N v> = |L v|^2 (no activation).
 // Activations live on the full lattice as two checkerboard halves, [parity][channel][colour][Vh]
 // complex FP32.  The FP32 channel mixing runs on the vector ALUs (training, and the reference
 // inference path); the inference path also has an MFMA form (network_mfma.hip).
@@ -17,6 +19,7 @@
 
 #include "ks_device.h"
 #include "ks_net.h"
+#include "ks_solvers.h"
 
 namespace ks {
 
@@ -36,8 +39,10 @@ __global__ __launch_bounds__(kNT) void net_layer_kernel(Geom g, const float2* __
                                                         float2* __restrict__ out,
                                                         const void* __restrict__ fat_e,
                                                         const void* __restrict__ fat_o,
-                                                        const float2* __restrict__ w)
+                                                        const float2* __restrict__ w,
+                                                        const int* __restrict__ gate)
 {
+    if (gate && *gate) return;
     const int vh = g.Vh;
     // each XCD takes one contiguous range of sites, so its L2 holds most neighbour activations
     const int t = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
@@ -291,23 +296,29 @@ __global__ void net_extract_kernel(int vh, const float2* __restrict__ act, doubl
     }
 }
 
-// loss term of one pair and the output gradient: diff = N(b) - x on even sites,
-// G = coef * diff (even), 0 (odd); per-block partial sums of |diff|^2
-__global__ __launch_bounds__(kNT) void net_loss_kernel(int vh, const float2* __restrict__ outp,
-                                                       const double2* __restrict__ x, double coef,
-                                                       float2* __restrict__ gy,
-                                                       double* __restrict__ partials)
+// A-norm loss term of one pair and the output gradient: with y = N(b) (even sites of the last
+// layer) and ay = A y (FP64 planes), partial sums of Re<y - x, A y - b> = (y - x)^+ A (y - x)
+// (A x = b) and G = coef (A y - b) on even sites, 0 on odd ones (the Wirtinger gradient of
+// the pair's loss is 2 A (y - x) over its normalisation).
+__global__ __launch_bounds__(kNT) void net_anorm_loss_kernel(int vh, const float2* __restrict__ y,
+                                                             const double2* __restrict__ ay,
+                                                             const double2* __restrict__ b,
+                                                             const double2* __restrict__ x,
+                                                             double coef, float2* __restrict__ gy,
+                                                             double* __restrict__ partials)
 {
     const int h = blockIdx.x * blockDim.x + threadIdx.x;
     double s = 0.0;
     if (h < vh) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const float2 o = outp[(size_t)k * vh + h];
+            const float2 o = y[(size_t)k * vh + h];
+            const double2 a = ay[(size_t)k * vh + h];
+            const double2 bv = b[(size_t)h * 3 + k];
             const double2 xv = x[(size_t)h * 3 + k];
-            const double dr = o.x - xv.x, di = o.y - xv.y;
-            s += dr * dr + di * di;
-            gy[(size_t)k * vh + h] = make_float2((float)(coef * dr), (float)(coef * di));
+            const double rr = a.x - bv.x, ri = a.y - bv.y;
+            s += (o.x - xv.x) * rr + (o.y - xv.y) * ri;
+            gy[(size_t)k * vh + h] = make_float2((float)(coef * rr), (float)(coef * ri));
             gy[(size_t)(3 + k) * vh + h] = make_float2(0.f, 0.f);
         }
     }
@@ -315,8 +326,21 @@ __global__ __launch_bounds__(kNT) void net_loss_kernel(int vh, const float2* __r
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
-// |x|^2 partials of a complex128 [Vh][3] vector
-__global__ __launch_bounds__(kNT) void net_norm_kernel(int vh, const double2* __restrict__ x,
+// even sites of the last layer (FP32 planes) -> FP64 planes [3][Vh]
+__global__ void net_out_f64_kernel(int vh, const float2* __restrict__ y, double2* __restrict__ out)
+{
+    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= vh) return;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const float2 v = y[(size_t)k * vh + h];
+        out[(size_t)k * vh + h] = make_double2(v.x, v.y);
+    }
+}
+
+// partials of Re<x, b> of two complex128 [Vh][3] vectors
+__global__ __launch_bounds__(kNT) void net_rdot_kernel(int vh, const double2* __restrict__ x,
+                                                       const double2* __restrict__ b,
                                                        double* __restrict__ partials)
 {
     const int h = blockIdx.x * blockDim.x + threadIdx.x;
@@ -324,18 +348,102 @@ __global__ __launch_bounds__(kNT) void net_norm_kernel(int vh, const double2* __
     if (h < vh)
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const double2 v = x[(size_t)h * 3 + k];
-            s += v.x * v.x + v.y * v.y;
+            const double2 u = x[(size_t)h * 3 + k], v = b[(size_t)h * 3 + k];
+            s += u.x * v.x + u.y * v.y;
         }
     s = block_sum<kNT>(s);
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
-// One Adam step on every real of the FP64 master weights; refreshes the FP32 copy.
+__device__ __forceinline__ int reversed_path(int p) { return p == 0 ? 0 : (p <= 4 ? p + 4 : p - 4); }
+
+// FP32 weights of the four applied layers from the FP64 free weights: layers 1 and 2 as they
+// are, layer 3 = adjoint of layer 2, layer 4 = adjoint of layer 1
+// (w'[c'][c][pbar] = conj(w[c][c'][p])).
+__global__ void net_expand_kernel(const double2* __restrict__ w, float2* __restrict__ w32)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    constexpr int n1 = 8 * 1 * 9, n2 = 8 * 8 * 9;
+    if (k >= kNetLayerWeights) return;
+    double2 v;
+    if (k < n1 + n2) {
+        v = w[k];
+    } else if (k < n1 + 2 * n2) {
+        const int j = k - n1 - n2;                        // layer 3: [c'][c][q], 8 x 8
+        const int q = j % 9, c = (j / 9) % 8, cp = j / 72;
+        const double2 u = w[n1 + (c * 8 + cp) * 9 + reversed_path(q)];
+        v = make_double2(u.x, -u.y);
+    } else {
+        const int j = k - n1 - 2 * n2;                    // layer 4: [0][c][q]
+        const int q = j % 9, c = j / 9;
+        const double2 u = w[c * 9 + reversed_path(q)];
+        v = make_double2(u.x, -u.y);
+    }
+    w32[k] = make_float2((float)v.x, (float)v.y);
+}
+
+// Gradient of the free weights from the four layers' gradients: a free weight collects its
+// own layer's G plus the conjugate of G at its place in the adjoint layer.
+__global__ void net_fold_kernel(const double2* __restrict__ g4, double2* __restrict__ g)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    constexpr int n1 = 8 * 1 * 9, n2 = 8 * 8 * 9;
+    if (k >= kNetWeights) return;
+    double2 a = g4[k], t;
+    if (k < n1) {                                          // w1[c][0][p]
+        const int p = k % 9, c = k / 9;
+        t = g4[n1 + 2 * n2 + c * 9 + reversed_path(p)];    // layer 4 [0][c][pbar]
+    } else {                                               // w2[c][c'][p]
+        const int j = k - n1;
+        const int p = j % 9, cp = (j / 9) % 8, c = j / 72;
+        t = g4[n1 + n2 + (cp * 8 + c) * 9 + reversed_path(p)];   // layer 3 [c'][c][pbar]
+    }
+    g[k] = make_double2(a.x + t.x, a.y - t.y);
+}
+
+// network input from an inner-precision field: even sites r * scale, odd sites zero
+template <int P>
+__global__ void net_embed_spinor_kernel(int vh, const void* __restrict__ r,
+                                        const double* __restrict__ scale, float2* __restrict__ act,
+                                        const int* __restrict__ gate)
+{
+    if (gate && *gate) return;
+    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= vh) return;
+    const float sc = (float)*scale;
+    cx<typename St<P>::R> v[3];
+    Spinor<P>::load(r, vh, h, v);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        act[(size_t)k * vh + h] = make_float2(sc * (float)v[k].r, sc * (float)v[k].i);
+        act[(size_t)(3 + k) * vh + h] = make_float2(0.f, 0.f);
+    }
+}
+
+// network output (even sites of the last layer) divided by scale into an inner-precision field
+template <int P>
+__global__ void net_extract_spinor_kernel(int vh, const float2* __restrict__ act,
+                                          const double* __restrict__ scale, void* __restrict__ z,
+                                          const int* __restrict__ gate)
+{
+    if (gate && *gate) return;
+    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= vh) return;
+    const float inv = (float)(1.0 / *scale);
+    using R = typename St<P>::R;
+    cx<R> v[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const float2 a = act[(size_t)k * vh + h];
+        v[k] = {(R)(inv * a.x), (R)(inv * a.y)};
+    }
+    Spinor<P>::store(z, vh, h, v);
+}
+
+// One Adam step on every real of the FP64 master weights.
 __global__ void net_adam_kernel(double* __restrict__ w, double* __restrict__ m,
                                 double* __restrict__ v, const double* __restrict__ grad, int n,
-                                double lr, double b1, double b2, double eps, double c1, double c2,
-                                float* __restrict__ w32)
+                                double lr, double b1, double b2, double eps, double c1, double c2)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
@@ -345,23 +453,23 @@ __global__ void net_adam_kernel(double* __restrict__ w, double* __restrict__ m,
     m[k] = mk;
     v[k] = vk;
     const double mh = mk / c1, vhat = vk / c2;
-    const double nw = w[k] - lr * mh / (sqrt(vhat) + eps);
-    w[k] = nw;
-    w32[k] = (float)nw;
-}
-
-__global__ void to_f32_vec_kernel(const double* __restrict__ a, float* __restrict__ b, int n)
-{
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n) b[k] = (float)a[k];
+    w[k] = w[k] - lr * mh / (sqrt(vhat) + eps);
 }
 
 template <int CIN, int COUT>
-void layer(ks_gauge_t g, const float2* in, float2* out, const float2* w, hipStream_t s)
+void layer(ks_gauge_t g, const float2* in, float2* out, const float2* w, hipStream_t s,
+           const int* gate = nullptr)
 {
     const LinkStore& st = g->store[KS_F32][0];
     net_layer_kernel<CIN, COUT><<<blocks_for(2L * g->geom.Vh, kNT), kNT, 0, s>>>(
-        g->geom, in, out, st.fat[0], st.fat[1], w);
+        g->geom, in, out, st.fat[0], st.fat[1], w, gate);
+    KS_HIP(hipGetLastError());
+}
+
+void expand_weights(NetCtx& n, hipStream_t s)
+{
+    net_expand_kernel<<<blocks_for(kNetLayerWeights, 256), 256, 0, s>>>(
+        reinterpret_cast<const double2*>(n.w64), reinterpret_cast<float2*>(n.w32));
     KS_HIP(hipGetLastError());
 }
 
@@ -380,6 +488,16 @@ void wgrad(NetCtx& n, NetBuffers& B, ks_gauge_t g, const float2* in, const float
 }  // namespace
 
 const int kLayerIn[4] = {1, 8, 8, 8};
+
+double net_model_bytes_per_site(int use_mfma)
+{
+    double total = 0.0;
+    for (int l = 0; l < 4; ++l) {
+        const double links = (use_mfma && l > 0) ? 8 * 36 : 8 * 72;
+        total += links + 24.0 * (kLayerIn[l] + kLayerOut[l]);
+    }
+    return total;
+}
 const int kLayerOut[4] = {8, 8, 8, 1};
 
 size_t layer_weight_offset(int l)
@@ -424,6 +542,7 @@ void net_free(NetCtx* n)
     device_free(n->adam_m);
     device_free(n->adam_v);
     device_free(n->grad);
+    device_free(n->grad4);
     device_free(n->scal);
     device_free(n->wmma);
     if (n->host) (void)hipHostFree(n->host);
@@ -435,12 +554,14 @@ NetCtx* net_create(const double* w_host)
     NetCtx* n = new NetCtx();
     try {
         const size_t nr = 2 * (size_t)kNetWeights;
+        const size_t nl = 2 * (size_t)kNetLayerWeights;
         n->w64 = static_cast<double*>(device_alloc(sizeof(double) * nr));
-        n->w32 = static_cast<float*>(device_alloc(sizeof(float) * nr));
-        n->wadj = static_cast<float*>(device_alloc(sizeof(float) * nr));
+        n->w32 = static_cast<float*>(device_alloc(sizeof(float) * nl));
+        n->wadj = static_cast<float*>(device_alloc(sizeof(float) * nl));
         n->adam_m = static_cast<double*>(device_alloc(sizeof(double) * nr));
         n->adam_v = static_cast<double*>(device_alloc(sizeof(double) * nr));
         n->grad = static_cast<double*>(device_alloc(sizeof(double) * nr));
+        n->grad4 = static_cast<double*>(device_alloc(sizeof(double) * nl));
         n->scal = static_cast<double*>(device_alloc(sizeof(double) * 64));
         KS_HIP(hipHostMalloc(reinterpret_cast<void**>(&n->host), sizeof(double) * 64));
         net_set_weights(*n, w_host, nullptr);
@@ -457,8 +578,7 @@ void net_set_weights(NetCtx& n, const double* w_host, hipStream_t s)
     KS_HIP(hipMemcpyAsync(n.w64, w_host, sizeof(double) * nr, hipMemcpyHostToDevice, s));
     KS_HIP(hipMemsetAsync(n.adam_m, 0, sizeof(double) * nr, s));
     KS_HIP(hipMemsetAsync(n.adam_v, 0, sizeof(double) * nr, s));
-    to_f32_vec_kernel<<<blocks_for(nr, 256), 256, 0, s>>>(n.w64, n.w32, nr);
-    KS_HIP(hipGetLastError());
+    expand_weights(n, s);
     KS_HIP(hipStreamSynchronize(s));
     n.step = 0;
     n.version += 1;
@@ -509,20 +629,55 @@ void net_apply_mfma(NetCtx& n, ks_gauge_t g, const double* in, double* out, doub
     net_embed_kernel<<<blocks_for(vh), kBlock, 0, s>>>(vh, reinterpret_cast<const double2*>(in),
                                                        in_scale, B.act[0]);
     layer<1, 8>(g, B.act[0], B.act[1], w + layer_weight_offset(0), s);
-    net_layer_mfma(n, g, B.act[1], B.act[2], 1, s);
-    net_layer_mfma(n, g, B.act[2], B.act[3], 2, s);
-    net_layer_mfma(n, g, B.act[3], B.act[4], 3, s);
+    net_layer_mfma(n, g, B.act[1], B.act[2], 1, nullptr, s);
+    net_layer_mfma(n, g, B.act[2], B.act[3], 2, nullptr, s);
+    net_layer_mfma(n, g, B.act[3], B.act[4], 3, nullptr, s);
     net_extract_kernel<<<blocks_for(vh), kBlock, 0, s>>>(vh, B.act[4], 1.0 / in_scale,
                                                          reinterpret_cast<double2*>(out));
     KS_HIP(hipGetLastError());
 }
 
-// Loss of the pairs and its gradient, accumulated into n.grad (zeroed first).
-double net_loss_grad(NetCtx& n, int npairs, const ks_gauge_t* gauges, const double* const* b,
-                     const double* const* x, hipStream_t s)
+void net_apply_spinor(NetCtx& n, ks_gauge_t g, ks_prec_t prec, const void* r, void* z,
+                      const double* in_scale, const int* gate, int use_mfma, hipStream_t s)
 {
-    const int nr = 2 * kNetWeights;
-    KS_HIP(hipMemsetAsync(n.grad, 0, sizeof(double) * nr, s));
+    KS_REQUIRE(prec == KS_F64 || prec == KS_F32, KS_ERR_ARG,
+               "network: the solver's vectors must be FP64 or FP32");
+    gauge_prepare(g, KS_F32, KS_RECON_18, s);
+    if (use_mfma) {
+        gauge_prepare(g, KS_F16, KS_RECON_18, s);
+        net_mfma_prepare(n, s);
+    }
+    NetBuffers& B = net_buffers(n, g->geom);
+    const int vh = g->geom.Vh;
+    const int nb = blocks_for(vh);
+    const float2* w = reinterpret_cast<const float2*>(n.w32);
+    if (prec == KS_F64)
+        net_embed_spinor_kernel<KS_F64><<<nb, kBlock, 0, s>>>(vh, r, in_scale, B.act[0], gate);
+    else
+        net_embed_spinor_kernel<KS_F32><<<nb, kBlock, 0, s>>>(vh, r, in_scale, B.act[0], gate);
+    layer<1, 8>(g, B.act[0], B.act[1], w + layer_weight_offset(0), s, gate);
+    if (use_mfma) {
+        net_layer_mfma(n, g, B.act[1], B.act[2], 1, gate, s);
+        net_layer_mfma(n, g, B.act[2], B.act[3], 2, gate, s);
+        net_layer_mfma(n, g, B.act[3], B.act[4], 3, gate, s);
+    } else {
+        layer<8, 8>(g, B.act[1], B.act[2], w + layer_weight_offset(1), s, gate);
+        layer<8, 8>(g, B.act[2], B.act[3], w + layer_weight_offset(2), s, gate);
+        layer<8, 1>(g, B.act[3], B.act[4], w + layer_weight_offset(3), s, gate);
+    }
+    if (prec == KS_F64)
+        net_extract_spinor_kernel<KS_F64><<<nb, kBlock, 0, s>>>(vh, B.act[4], in_scale, z, gate);
+    else
+        net_extract_spinor_kernel<KS_F32><<<nb, kBlock, 0, s>>>(vh, B.act[4], in_scale, z, gate);
+    KS_HIP(hipGetLastError());
+}
+
+// A-norm loss of the pairs and its gradient: the four applied layers' gradients accumulate in
+// n.grad4 (zeroed first), then fold into the free weights' gradient n.grad.
+double net_loss_grad(NetCtx& n, int npairs, const ks_gauge_t* gauges, const double* sigma,
+                     const double* const* b, const double* const* x, hipStream_t s)
+{
+    KS_HIP(hipMemsetAsync(n.grad4, 0, sizeof(double) * 2 * kNetLayerWeights, s));
     const float2* w = reinterpret_cast<const float2*>(n.w32);
     float2* wa = reinterpret_cast<float2*>(n.wadj);
     for (int l = 1; l < 4; ++l) {
@@ -535,25 +690,32 @@ double net_loss_grad(NetCtx& n, int npairs, const ks_gauge_t* gauges, const doub
     for (int j = 0; j < npairs; ++j) {
         ks_gauge_t g = gauges[j];
         gauge_prepare(g, KS_F32, KS_RECON_18, s);
+        Workspace& ws = workspace(g);
         NetBuffers& B = net_buffers(n, g->geom);
         const int vh = g->geom.Vh;
         const int nb = blocks_for(vh, kNT);
-        // |x|^2
-        net_norm_kernel<<<nb, kNT, 0, s>>>(vh, reinterpret_cast<const double2*>(x[j]), B.part);
+        const double2* bj = reinterpret_cast<const double2*>(b[j]);
+        const double2* xj = reinterpret_cast<const double2*>(x[j]);
+        // x^+ A x = Re<x, b>
+        net_rdot_kernel<<<nb, kNT, 0, s>>>(vh, xj, bj, B.part);
         reduce_sum(B.part, nb, n.scal, s);
         KS_HIP(hipMemcpyAsync(n.host, n.scal, sizeof(double), hipMemcpyDeviceToHost, s));
         KS_HIP(hipStreamSynchronize(s));
-        const double nx2 = n.host[0];
-        KS_REQUIRE(nx2 > 0, KS_ERR_ARG, "network training: solution %d is zero", j);
-        net_embed_kernel<<<blocks_for(vh), kBlock, 0, s>>>(vh, reinterpret_cast<const double2*>(b[j]),
-                                                           1.0, B.act[0]);
+        const double xax = n.host[0];
+        KS_REQUIRE(xax > 0, KS_ERR_ARG, "network training: pair %d has Re<x, b> <= 0", j);
+        net_embed_kernel<<<blocks_for(vh), kBlock, 0, s>>>(vh, bj, 1.0, B.act[0]);
         net_forward(n, B, g, s);
-        net_loss_kernel<<<nb, kNT, 0, s>>>(vh, B.act[4], reinterpret_cast<const double2*>(x[j]),
-                                           2.0 / (nx2 * npairs), B.grad[4], B.part);
+        // A y in FP64 on the pair's lattice
+        net_out_f64_kernel<<<blocks_for(vh), kBlock, 0, s>>>(vh, B.act[4],
+                                                             reinterpret_cast<double2*>(ws.r64));
+        apply_A64(g, sigma[j], ws.r64, ws.ax64, s, nullptr);
+        net_anorm_loss_kernel<<<nb, kNT, 0, s>>>(vh, B.act[4],
+                                                 reinterpret_cast<const double2*>(ws.ax64), bj, xj,
+                                                 2.0 / (xax * npairs), B.grad[4], B.part);
         reduce_sum(B.part, nb, n.scal + 1, s);
         KS_HIP(hipMemcpyAsync(n.host + 1, n.scal + 1, sizeof(double), hipMemcpyDeviceToHost, s));
         // backward: weight gradients and the adjoint layers
-        double* gr = n.grad;
+        double* gr = n.grad4;
         wgrad<8, 1>(n, B, g, B.act[3], B.grad[4], gr + 2 * layer_weight_offset(3), s);
         layer<1, 8>(g, B.grad[4], B.grad[3], wa + layer_weight_offset(3), s);
         wgrad<8, 8>(n, B, g, B.act[2], B.grad[3], gr + 2 * layer_weight_offset(2), s);
@@ -562,8 +724,11 @@ double net_loss_grad(NetCtx& n, int npairs, const ks_gauge_t* gauges, const doub
         layer<8, 8>(g, B.grad[2], B.grad[1], wa + layer_weight_offset(1), s);
         wgrad<1, 8>(n, B, g, B.act[0], B.grad[1], gr + 2 * layer_weight_offset(0), s);
         KS_HIP(hipStreamSynchronize(s));
-        loss += n.host[1] / (nx2 * npairs);
+        loss += n.host[1] / (xax * npairs);
     }
+    net_fold_kernel<<<blocks_for(kNetWeights, 256), 256, 0, s>>>(
+        reinterpret_cast<const double2*>(n.grad4), reinterpret_cast<double2*>(n.grad));
+    KS_HIP(hipGetLastError());
     return loss;
 }
 
@@ -574,8 +739,9 @@ void net_adam(NetCtx& n, double lr, hipStream_t s)
     const double b1 = 0.9, b2 = 0.999;
     net_adam_kernel<<<blocks_for(nr, 256), 256, 0, s>>>(n.w64, n.adam_m, n.adam_v, n.grad, nr, lr,
                                                        b1, b2, 1e-8, 1.0 - std::pow(b1, n.step),
-                                                       1.0 - std::pow(b2, n.step), n.w32);
+                                                       1.0 - std::pow(b2, n.step));
     KS_HIP(hipGetLastError());
+    expand_weights(n, s);
     n.version += 1;
 }
 

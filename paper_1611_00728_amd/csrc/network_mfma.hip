@@ -63,8 +63,10 @@ __global__ __launch_bounds__(256) void net_layer_mfma_kernel(Geom g, const float
                                                              const void* __restrict__ fat_e,
                                                              const void* __restrict__ fat_o,
                                                              const half4_t* __restrict__ frag,
-                                                             float link_scale)
+                                                             float link_scale,
+                                                             const int* __restrict__ gate)
 {
+    if (gate && *gate) return;
     const int vh = g.Vh;
     const int lane = threadIdx.x & 63;
     const int n = lane & 15, grp = lane >> 4;
@@ -163,17 +165,17 @@ void net_mfma_prepare(NetCtx& n, hipStream_t s)
 }
 
 void net_layer_mfma(NetCtx& n, ks_gauge_t g, const float2* in, float2* out, int which,
-                    hipStream_t s)
+                    const int* gate, hipStream_t s)
 {
     const LinkStore& st = g->store[KS_F16][0];
     const half4_t* fr = reinterpret_cast<const half4_t*>(n.wmma) + (which - 1) * 9 * 64;
     const int nb = blocks_for(2L * g->geom.Vh, kBlockSites);
     if (kLayerOut[which] == 8)
         net_layer_mfma_kernel<8, KS_F16><<<nb, 256, 0, s>>>(g->geom, in, out, st.fat[0], st.fat[1],
-                                                             fr, st.fat_scale);
+                                                             fr, st.fat_scale, gate);
     else
         net_layer_mfma_kernel<1, KS_F16><<<nb, 256, 0, s>>>(g->geom, in, out, st.fat[0], st.fat[1],
-                                                             fr, st.fat_scale);
+                                                             fr, st.fat_scale, gate);
     KS_HIP(hipGetLastError());
 }
 

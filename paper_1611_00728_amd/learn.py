@@ -1,6 +1,7 @@
 """Training pipeline of the learned preconditioner: (source, FP64 solution) pairs produced by
 the library's own FP64 CG on sub-lattices and on the full lattice, then Adam steps of the
-library's GPU training kernels.  Argument marshalling and bookkeeping only."""
+library's GPU training kernels on the A-norm loss.  Argument marshalling and bookkeeping
+only."""
 from __future__ import annotations
 
 import time
@@ -23,14 +24,14 @@ def block_origins(dims, bdims):
 
 def solve_pairs(gauge: Gauge, mass: float, sources, tol: float = 1e-10):
     """x_j = A^-1 b_j by FP64 CG on the GPU for every source (complex128 [Vh][3] host arrays);
-    returns the device (b, x) tensors."""
+    returns the pairs (gauge, sigma = 4 m^2, device b, device x)."""
     import torch
     pairs = []
     for b in sources:
         bd = torch.from_numpy(np.ascontiguousarray(b)).cuda()
         xd = torch.zeros_like(bd)
         cg_solve(gauge, mass, bd, xd, default_params(tol=tol, inner=F64))
-        pairs.append((gauge, bd, xd))
+        pairs.append((gauge, 4.0 * mass * mass, bd, xd))
     torch.cuda.synchronize()
     return pairs
 
@@ -40,7 +41,8 @@ def solve_pairs_batched(fields, sources, mass: float, tol: float = 1e-10, check_
     fields: objects with .dims, .fat, .naik (one per lattice); sources[l]: list of nrhs
     complex128 [Vh][3] host arrays for lattice l (nrhs 1, 2 or 4, the same for every lattice).
     Returns (pairs, seconds of the batched solve, stats): pairs are (Gauge handle of the
-    lattice, device b, device x); the link upload and the handles are not timed."""
+    lattice, sigma = 4 m^2, device b, device x); the link upload and the handles are not
+    timed."""
     import torch
     nrhs = len(sources[0])
     if any(len(s) != nrhs for s in sources):
@@ -57,7 +59,7 @@ def solve_pairs_batched(fields, sources, mass: float, tol: float = 1e-10, check_
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     B.free()
-    pairs = [(gauges[k // nrhs], bs[k], xs[k]) for k in range(len(bs))]
+    pairs = [(gauges[k // nrhs], 4.0 * mass * mass, bs[k], xs[k]) for k in range(len(bs))]
     return pairs, dt, stats
 
 
@@ -67,6 +69,6 @@ def train(net: Net, pairs, steps: int, batch: int, lr: float):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     hist = net.train([p[0] for p in pairs], [p[1] for p in pairs], [p[2] for p in pairs],
-                     steps, batch, lr)
+                     [p[3] for p in pairs], steps, batch, lr)
     torch.cuda.synchronize()
     return hist, time.perf_counter() - t0
