@@ -81,15 +81,65 @@ def _chunks(V: int, chunk: int = 1 << 17):
         yield s, min(V, s + chunk)
 
 
+_POOL_STATE = {}
+
+
+def _shared_array(shape) -> np.ndarray:
+    """A complex128 array in an anonymous shared mapping: forked worker processes write into
+    the parent's memory (no named shared-memory files)."""
+    import mmap
+    buf = mmap.mmap(-1, int(np.prod(shape)) * 16)
+    return np.ndarray(shape, dtype=np.complex128, buffer=buf)
+
+
+def _pool_su3(args):
+    s, e, g, scale = args
+    _POOL_STATE["out"][:, s:e] = np.swapaxes(su3_from_gaussian(g, scale), 0, 1)
+    return s
+
+
 def thin_links(dims, scale: float, seed: int) -> np.ndarray:
-    """Unsigned thin links U, complex128 [4][V][3][3]."""
+    """Unsigned thin links U, complex128 [4][V][3][3].  The draws are taken chunk after chunk
+    from one stream; on large lattices the matrices of the chunks are computed by a pool of
+    worker processes writing into shared memory (the same operations on the same draws, so
+    the result does not depend on the number of workers)."""
     V = lattice_volume(dims)
     rng = np.random.default_rng(np.random.SeedSequence(seed).spawn(2)[0])
-    U = np.empty((4, V, 3, 3), dtype=np.complex128)
-    for s, e in _chunks(V):
-        g = rng.standard_normal((e - s, 4, 3, 3, 2))
-        U[:, s:e] = np.swapaxes(su3_from_gaussian(g, scale), 0, 1)
+    chunks = list(_chunks(V))
+    workers = _workers(len(chunks))
+    if workers <= 1:
+        U = np.empty((4, V, 3, 3), dtype=np.complex128)
+        for s, e in chunks:
+            g = rng.standard_normal((e - s, 4, 3, 3, 2))
+            U[:, s:e] = np.swapaxes(su3_from_gaussian(g, scale), 0, 1)
+        return U
+    import multiprocessing as mp
+    shape = (4, V, 3, 3)
+    _POOL_STATE["out"] = _shared_array(shape)
+    try:
+        with mp.get_context("fork").Pool(workers) as pool:
+            tasks = ((s, e, rng.standard_normal((e - s, 4, 3, 3, 2)), scale) for s, e in chunks)
+            for _ in pool.imap_unordered(_pool_su3, tasks, chunksize=1):
+                pass
+        U = np.array(_POOL_STATE["out"])
+    finally:
+        _POOL_STATE.clear()
     return U
+
+
+def _workers(nchunks: int) -> int:
+    """Worker processes for chunked generation: none for a few chunks, none once this process
+    has initialised a GPU through torch (the workers are forked), else up to 16 (or the
+    KS_INPUT_WORKERS environment variable)."""
+    import os
+    import sys
+    if nchunks < 4:
+        return 1
+    torch = sys.modules.get("torch")
+    if torch is not None and torch.cuda.is_initialized():
+        return 1
+    n = int(os.environ.get("KS_INPUT_WORKERS", min(16, os.cpu_count() or 1)))
+    return max(1, min(n, nchunks))
 
 
 def _shift_fwd(A: np.ndarray, dims, mu: int, hops: int) -> np.ndarray:
@@ -108,18 +158,79 @@ def naik_from_thin(U: np.ndarray, dims) -> np.ndarray:
     return W
 
 
+def _fat_chunk(U, s, e, g):
+    N = (g[..., 0] + 1j * g[..., 1]) * np.sqrt(0.5)
+    return FAT_DIAG * U[:, s:e] + FAT_NOISE * np.swapaxes(N, 0, 1)
+
+
+def _site_shift(dims, s, e, mu, hops):
+    """Index of site i + hops mu_hat for the sites i in [s, e) (periodic wrap)."""
+    nx, ny, nz, nt = (int(d) for d in dims)
+    i = np.arange(s, e, dtype=np.int64)
+    c = [i % nx, (i // nx) % ny, (i // (nx * ny)) % nz, i // (nx * ny * nz)]
+    n = (nx, ny, nz, nt)
+    c[mu] = (c[mu] + hops) % n[mu]
+    return c[0] + nx * (c[1] + ny * (c[2] + nz * c[3]))
+
+
+def _pool_fat_naik(args):
+    """Fat and Naik links of the sites [s, e), phases and boundary signs folded in: the same
+    operations as the whole-lattice form, row by row."""
+    s, e, g, dims = args
+    U, fat, naik = _POOL_STATE["U"], _POOL_STATE["fat"], _POOL_STATE["naik"]
+    fat[:, s:e] = _fat_chunk(U, s, e, g)
+    for mu in range(4):
+        U1 = U[mu][_site_shift(dims, s, e, mu, 1)]
+        U2 = U[mu][_site_shift(dims, s, e, mu, 2)]
+        naik[mu, s:e] = NAIK_COEFF * (U[mu, s:e] @ U1 @ U2)
+    _fold_rows(fat, naik, dims, s, e)
+    return s
+
+
 def fat_and_naik(U: np.ndarray, dims, seed: int):
-    """Phase-folded fat link V and Naik link W built from the unsigned thin links U."""
+    """Phase-folded fat link V and Naik link W built from the unsigned thin links U.  On large
+    lattices the chunks are computed by a pool of worker processes over shared memory (same
+    draws, same operations per row, so the result does not depend on the number of
+    workers)."""
     V = lattice_volume(dims)
     rng = np.random.default_rng(np.random.SeedSequence(seed).spawn(2)[1])
-    fat = np.empty_like(U)
-    for s, e in _chunks(V):
-        g = rng.standard_normal((e - s, 4, 3, 3, 2))
-        N = (g[..., 0] + 1j * g[..., 1]) * np.sqrt(0.5)
-        fat[:, s:e] = FAT_DIAG * U[:, s:e] + FAT_NOISE * np.swapaxes(N, 0, 1)
-    naik = naik_from_thin(U, dims)
-    fold_phases(fat, naik, dims)
+    chunks = list(_chunks(V))
+    workers = _workers(len(chunks))
+    if workers <= 1:
+        fat = np.empty_like(U)
+        for s, e in chunks:
+            fat[:, s:e] = _fat_chunk(U, s, e, rng.standard_normal((e - s, 4, 3, 3, 2)))
+        naik = naik_from_thin(U, dims)
+        fold_phases(fat, naik, dims)
+        return fat, naik
+    import multiprocessing as mp
+    shape = U.shape
+    _POOL_STATE["U"] = U                       # read by the forked workers, never written
+    _POOL_STATE["fat"] = _shared_array(shape)
+    _POOL_STATE["naik"] = _shared_array(shape)
+    try:
+        with mp.get_context("fork").Pool(workers) as pool:
+            tasks = ((s, e, rng.standard_normal((e - s, 4, 3, 3, 2)), tuple(dims))
+                     for s, e in chunks)
+            for _ in pool.imap_unordered(_pool_fat_naik, tasks, chunksize=1):
+                pass
+        fat = np.array(_POOL_STATE["fat"])
+        naik = np.array(_POOL_STATE["naik"])
+    finally:
+        _POOL_STATE.clear()
     return fat, naik
+
+
+def _fold_rows(fat, naik, dims, s, e):
+    nx, ny, nz, nt = (int(d) for d in dims)
+    i = np.arange(s, e, dtype=np.int64)
+    x, y, z, t = i % nx, (i // nx) % ny, (i // (nx * ny)) % nz, i // (nx * ny * nz)
+    for mu in range(4):
+        eta = staggered_phase(mu, x, y, z, t)
+        s1 = eta * (time_bc_sign(1, t, nt) if mu == 3 else 1.0)
+        s3 = eta * (time_bc_sign(3, t, nt) if mu == 3 else 1.0)
+        fat[mu, s:e] *= s1[:, None, None]
+        naik[mu, s:e] *= s3[:, None, None]
 
 
 def fold_phases(fat: np.ndarray, naik: np.ndarray, dims) -> None:

@@ -87,3 +87,16 @@ def test_bench_byte_models():
     per_site = 12 * bench.BATCH_STEP_BYTES + 2 * bench.BATCH_RU_BYTES
     want = (100 + 200) * per_site
     assert got == want
+
+
+def test_parallel_generation_is_bit_identical(monkeypatch):
+    """The chunked generation of a large field gives the same bits with a pool of worker
+    processes as computed in one process (same draws in the same order, same operations)."""
+    import hashlib
+    dims = (16, 16, 16, 128)               # four chunks of 2^17 sites
+    monkeypatch.setenv("KS_INPUT_WORKERS", "3")
+    a = make_gauge(dims, 0.5, 4321, keep_thin=True)
+    monkeypatch.setenv("KS_INPUT_WORKERS", "1")
+    b = make_gauge(dims, 0.5, 4321, keep_thin=True)
+    for x, y in ((a.thin, b.thin), (a.fat, b.fat), (a.naik, b.naik)):
+        assert hashlib.sha256(x.tobytes()).digest() == hashlib.sha256(y.tobytes()).digest()
