@@ -11,6 +11,10 @@ One step is one pass of the hot path:
   5. the full-system solve M x = b and the link construction from thin links;
   6. the plain FP64 GPU CG and the mixed-precision CG solves (FP32 inner with 18- and 12-real
      Naik, FP16 inner with 12-real Naik) to FP64 true relative residual 1e-10.
+After the timed steps, once: every returned solution's residual recomputed by the FP64 oracle
+on the host (and the 32^4 FP64 solution's distance to the oracle's own CG solution, which a
+host thread computes while the GPU runs), and the 48^3 x 64, m = 0.002 learned-preconditioner
+workload (training pairs, training, FP64 / mixed / learned solves).
 `value` is the FP64 Dslash_eo's algorithmic HBM bandwidth (least-data model: 2400 bytes per
 output site) averaged over every launch of the timed steps; the other rows report their own
 figures in the same JSON line.
@@ -61,10 +65,21 @@ BATCH_DELTA = 0.01
 # read, 4 x 24 read/written)
 BATCH_RU_BYTES = (2 * 4 * 48 + 2 * 4 * 24 + (2304 + 2 * 4 * 48) * 2 + 4 * 48 + 3 * 4 * 48 +
                   4 * 48 + 2 * 4 * 24)
-# network (per site of the full lattice): four layers, each reading its site's 8 stored FP32
-# fat links (4 forward, 4 backward: 8 x 72 bytes) and its input channels and writing its
-# output channels (FP32 complex colour vectors, 24 bytes each): 1->8, 8->8, 8->8, 8->1
-NET_BYTES_PER_SITE = 4 * 576 + (24 + 192) + 2 * (192 + 192) + (192 + 24)
+# network (per site of the full lattice): four layers, each reading its site's 8 stored fat
+# links once (4 forward, 4 backward) and its input channels and writing its output channels
+# (FP32 complex colour vectors, 24 bytes each): 1->8, 8->8, 8->8, 8->1.  The FP32 path reads
+# FP32 links (8 x 72 bytes) in every layer; the matrix-core path reads the binary16 link store
+# (8 x 36 bytes) in its three last layers.
+_NET_CH = (24 + 192) + 2 * (192 + 192) + (192 + 24)
+NET_BYTES_PER_SITE = {"f32": 4 * 576 + _NET_CH, "mfma": 576 + 3 * 288 + _NET_CH}
+# link construction, per site: the 3x3 complex products of the two smearing levels as nested
+# (per direction 6 three-link staples and 6 outer terms of 4 inner staples, 2 products each:
+# 72; Lepage adds loads, no products), the Naik products (2 per direction), 198 flops each,
+# and the U(3) projection counted as 8 Newton steps of ~300 flops per link.  Its least data is
+# the thin links read (576 B) and the fat and Naik links written (2 x 576 B).
+HISQ_FLOPS_PER_SITE = (2 * 4 * 72 + 4 * 2) * 198 + 4 * 8 * 300
+HISQ_BYTES_PER_SITE = 3 * 576
+FP64_PEAK_TFLOPS = 78.6
 
 
 def batch_model_bytes(stats, vhs, nrhs=4):
@@ -128,9 +143,12 @@ def measured_traffic(variant: str, threads: int, group: int, way: int, staged: i
 
 
 def cpu_baseline(g, b, budget_s: float = 12.0):
-    """The FP64 oracle timed on the host: Dslash_eo calls over the same 32^4 field."""
+    """The FP64 oracle timed on the host: Dslash_eo calls over the same 32^4 field.  The oracle
+    computes D on the whole lattice and keeps one parity, twice the work of D_eo, so its
+    GB/s counts the D_eo model bytes over the time of that double work."""
     import oracle
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = oracle.max_threads()
+    oracle.set_threads(threads)
     vh = g.volume // 2
     oracle.dslash_eo(g, 0, b)   # warm
     n, t0 = 0, time.perf_counter()
@@ -140,45 +158,92 @@ def cpu_baseline(g, b, budget_s: float = 12.0):
     dt = (time.perf_counter() - t0) / n
     return {"value": model_bytes_per_site("f64", 18) * vh / dt / 1e9, "unit": "GB/s",
             "cores": threads, "kind": "oracle",
-            "sample": "%d FP64 oracle Dslash_eo calls on the 32^4 field (%.3f s each)" % (n, dt)}
+            "sample": "%d FP64 oracle Dslash_eo calls on the 32^4 field (%.3f s each); the oracle "
+                      "applies the full-lattice D and restricts it to one parity, twice the "
+                      "work of D_eo, and the rate counts D_eo's 2400 bytes per output site"
+                      % (n, dt)}
 
 
-def learned48(args):
-    """48^3 x 64 lattice, thin-link scale 0.5, m = 0.002: 248 training pairs on 16^4 blocks
-    cut from the field plus 8 on the full lattice (FP64 CG solutions), Adam training, then
-    flexible CG with the network (matrix-core mixing) against FP32-inner CG with reliable
-    updates, both to FP64 true relative residual 1e-10."""
+def oracle_resid(g, sigma, b, x):
+    """|b - A x| / |b| with the FP64 oracle's A on the host, x a device tensor."""
     import numpy as np
+    import oracle
+    xh = x.detach().cpu().numpy()
+    return float(np.linalg.norm(b - oracle.apply_A(g, sigma, xh)) / np.linalg.norm(b))
+
+
+class OracleSolve:
+    """The oracle's FP64 CG solution of one system, computed by a host thread (the oracle's C
+    loops run without the interpreter lock) while the GPU works."""
+
+    def __init__(self, g, sigma, b, tol, threads):
+        import threading
+        self.result = None
+        self.seconds = None
+
+        def run():
+            import oracle
+            oracle.set_threads(threads)
+            t = time.perf_counter()
+            self.result = oracle.cg(g, sigma, b, tol)
+            self.seconds = time.perf_counter() - t
+        self.thread = threading.Thread(target=run, daemon=True)
+        self.thread.start()
+        self.threads = threads
+
+    def join(self):
+        self.thread.join()
+        return self.result
+
+
+L5_DIMS, L5_MASS = (48, 48, 48, 64), 0.002
+
+
+def learned_inputs():
+    """The 48^3 x 64 field (thin-link scale 0.5, gauge seed 1005, thin links kept) and the
+    108 16^4 blocks cut from it, the source and the training sources (input preparation, not
+    timed)."""
+    from ksinputs import make_gauge, gaussian_source, subblock, SEEDS
+    from paper_1611_00728_amd import learn
+    t0 = time.time()
+    g5 = make_gauge(L5_DIMS, 0.5, SEEDS["gauge"](5), keep_thin=True)
+    log("48^3x64 field generated in %.1f s" % (time.time() - t0))
+    t1 = time.time()
+    blocks = [subblock(g5, o, (16, 16, 16, 16))
+              for o in learn.block_origins(L5_DIMS, (16, 16, 16, 16))]
+    log("%d 16^4 blocks cut in %.1f s" % (len(blocks), time.time() - t1))
+    return g5, blocks
+
+
+def config5(g5, blocks):
+    """48^3 x 64 lattice, thin-link scale 0.5, m = 0.002: 252 training pairs on 16^4 blocks cut
+    from the field (two sources on each of the 108 blocks, two more on the first 18) plus 4 on
+    the full lattice (FP64 CG solutions), 1000 Adam steps on the A-norm loss, then flexible CG
+    with the network (matrix-core mixing) against FP32-inner CG with reliable updates and plain
+    FP64 CG, all to FP64 true relative residual 1e-10, each solution's residual recomputed by
+    the FP64 oracle.  Returns the JSON row."""
     import torch
     import paper_1611_00728_amd as ks
     from paper_1611_00728_amd import learn
-    from ksinputs import (make_gauge, gaussian_source, subblock, net_init_weights,
-                          flatten_weights, SEEDS)
-    dims, mass, tol = (48, 48, 48, 64), 0.002, 1e-10
+    from ksinputs import gaussian_source, net_init_weights, flatten_weights, SEEDS
+    dims, mass, tol = L5_DIMS, L5_MASS, 1e-10
+    vh = g5.volume // 2
     t0 = time.time()
-    g = make_gauge(dims, 0.5, SEEDS["gauge"](5), keep_thin=True)
-    vh = g.volume // 2
-    log("48^3x64 field generated in %.1f s" % (time.time() - t0))
-    G = ks.Gauge(dims, g.fat, g.naik)
+    G = ks.Gauge(dims, g5.fat, g5.naik)
     for p in (ks.F64, ks.F32):
         G.prepare(p, 18)
         G.tune(p, 18)
-    origins = learn.block_origins(dims, (16, 16, 16, 16))
-    # 248 block pairs: two sources on each of the 108 blocks, two more on the first 16, each
-    # group solved by one batched FP64 CG; then 8 full-lattice pairs
-    t1 = time.perf_counter()
-    blocks = [subblock(g, o, (16, 16, 16, 16)) for o in origins]
+    G.prepare(ks.F16, 18)
+    log("48^3x64 gauge loaded and tuned in %.1f s" % (time.time() - t0))
     k = 0
     groups = []
-    for sel in (range(len(blocks)), range(248 // 2 - len(blocks))):
+    for sel in (range(len(blocks)), range(252 // 2 - len(blocks))):
         srcs = []
         for j in sel:
             srcs.append([gaussian_source(blocks[j].volume // 2, SEEDS["train_source"](k + r))
                          for r in range(2)])
             k += 2
         groups.append(([blocks[j] for j in sel], srcs))
-    log("%d block fields cut in %.1f s (input preparation, not timed)"
-        % (len(blocks), time.perf_counter() - t1))
     pairs, t_blocks = [], 0.0
     for fields, srcs in groups:
         pp, dt, st = learn.solve_pairs_batched(fields, srcs, mass)
@@ -186,20 +251,19 @@ def learned48(args):
         t_blocks += dt
         log("%d block pairs in %.1f s (batched FP64 CG, iterations %d-%d)"
             % (len(pp), dt, min(x["iters"] for x in st), max(x["iters"] for x in st)))
-    del blocks, groups
     t_gen0 = time.perf_counter()
-    full = []
-    for r in range(8):
-        full += learn.solve_pairs(G, mass, [gaussian_source(vh, SEEDS["train_source"](10000 + r))])
-        log("full-lattice pair %d done" % r)
+    full = learn.solve_pairs(G, mass, [gaussian_source(vh, SEEDS["train_source"](10000 + r))
+                                       for r in range(4)])
     pairs += full
     t_gen = t_blocks + time.perf_counter() - t_gen0
     net = ks.Net(flatten_weights(net_init_weights(SEEDS["net_init"])))
-    steps = 400
-    hist, t_train = learn.train(net, pairs, steps=steps, batch=8, lr=2e-3)
+    steps, batch, lr = 1000, 8, 1e-2
+    hist, t_train = learn.train(net, pairs, steps=steps, batch=batch, lr=lr)
     log("trained: loss %.4f -> %.4f in %.1f s" % (hist[0], hist[-1], t_train))
-    b = torch.from_numpy(gaussian_source(vh, SEEDS["source"](5))).cuda()
-    rows = {}
+    bh = gaussian_source(vh, SEEDS["source"](5))
+    b = torch.from_numpy(bh).cuda()
+    rows, xs = {}, {}
+    spectrum = None
     for name, fn in (("fp64_cg", lambda x: ks.cg_solve(G, mass, b, x, ks.default_params(tol=tol))),
                      ("mixed_f32_cg", lambda x: ks.cg_solve(
                          G, mass, b, x, ks.default_params(tol=tol, inner=ks.F32))),
@@ -210,27 +274,42 @@ def learned48(args):
         t = time.perf_counter()
         res = fn(x)
         torch.cuda.synchronize()
+        xs[name] = x
         rows[name] = {"seconds": time.perf_counter() - t, "iters": res.stats["iters"],
-                      "true_rel_resid": res.stats["true_rel_resid"],
-                      "fallback": bool(res.stats["fallback"]),
+                      "true_rel_resid_gpu": res.stats["true_rel_resid"],
                       "fallback_code": res.stats["fallback"],
                       "flexible_steps": res.stats["iters"] - res.stats["restarts"]
                       if res.stats["fallback"] else res.stats["iters"]}
         if name == "fp64_cg":
             spectrum = lanczos_spectrum(*G.cg_coefficients())
         log("%s: %s" % (name, json.dumps(rows[name])))
+    for name, x in xs.items():
+        rows[name]["true_rel_resid_oracle"] = oracle_resid(g5, 4 * mass * mass, bh, x)
     tm, tl = rows["mixed_f32_cg"]["seconds"], rows["learned_fcg"]["seconds"]
-    print(json.dumps({
+    im, il = rows["mixed_f32_cg"]["iters"], rows["learned_fcg"]["iters"]
+    net.free()
+    G.free()
+    return {
         "workload": "learned preconditioner, 48^3x64, H scale 0.5, m=0.002, tol 1e-10",
         "solves": rows,
         "spectrum_of_A": spectrum,
         "training": {"pairs": len(pairs), "block_pairs": len(pairs) - len(full),
                      "full_lattice_pairs": len(full), "pair_generation_s": t_gen,
-                     "adam_steps": steps, "batch": 8, "training_s": t_train,
+                     "adam_steps": steps, "batch": batch, "lr": lr, "training_s": t_train,
+                     "loss": "A-norm error relative to the solution's",
                      "loss_first": float(hist[0]), "loss_last": float(hist[-1])},
+        "learned_vs_mixed_iterations": il / im,
         "learned_vs_mixed_speedup": tm / tl,
         "break_even_solves": ((t_gen + t_train) / (tm - tl)) if tl < tm else None,
-        "amortised_training_per_solve_s_over_100": (t_gen + t_train) / 100.0}), flush=True)
+        "amortised_training_per_solve_s_over_100": (t_gen + t_train) / 100.0}
+
+
+def learned48(args):
+    """The 48^3 x 64 learned-preconditioner workload on its own (one JSON line)."""
+    g5, blocks = learned_inputs()
+    import torch
+    torch.cuda.set_device(0)
+    print(json.dumps(config5(g5, blocks)), flush=True)
 
 
 def sweep(args):
@@ -328,6 +407,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned48", action="store_true",
+                    help="skip the 48^3 x 64 learned-preconditioner workload after the steps")
     ap.add_argument("--workload", default="default", choices=["default", "learned48", "sweep"],
                     help="learned48: the 48^3 x 64, m = 0.002 learned-preconditioner workload "
                          "(training pairs, training, flexible CG vs mixed CG); sweep: Dslash_eo "
@@ -342,23 +423,41 @@ def main():
         sys.exit(2)
 
     import numpy as np
-    import torch
-    import paper_1611_00728_amd as ks
-    from ksinputs import make_gauge, gaussian_source
+    from ksinputs import make_gauge, gaussian_source, SEEDS
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    torch.cuda.set_device(0)
     if args.workload == "learned48":
         learned48(args)
         return
     if args.workload == "sweep":
+        import torch
+        torch.cuda.set_device(0)
         sweep(args)
         return
+    # every input is generated before the GPU is touched: large fields are computed by forked
+    # worker processes
     t0 = time.time()
     g = make_gauge(DIMS, 0.5, 1002, keep_thin=True)
     vh = g.volume // 2
     b = gaussian_source(vh, 2002)
-    log("inputs generated in %.1f s" % (time.time() - t0))
+    MS_DIMS = (32, 32, 32, 48)
+    gm = make_gauge(MS_DIMS, 0.5, SEEDS["gauge"](3))
+    mb_h = gaussian_source(gm.volume // 2, SEEDS["source"](3))
+    log("32^4 and 32^3x48 inputs generated in %.1f s" % (time.time() - t0))
+    g5 = blocks5 = None
+    if not args.dslash_only and not args.no_learned48:
+        g5, blocks5 = learned_inputs()
+    # the oracle's own FP64 CG solution of the 32^4 system, on host threads meanwhile
+    oracle_ref = None
+    if not args.dslash_only:
+        import oracle
+        ncpu = oracle.max_threads()
+        oracle_ref = OracleSolve(g, 4 * MASS * MASS, b, 1e-12, max(1, ncpu - 4))
+        log("oracle FP64 CG of the 32^4 system started on %d host threads" % oracle_ref.threads)
+
+    import torch
+    import paper_1611_00728_amd as ks
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
     G = ks.Gauge(DIMS, g.fat, g.naik)
     for p in (ks.F64, ks.F32, ks.F16):
         for r in (18, 12):
@@ -459,11 +558,11 @@ def main():
     bg = [make_gauge(d, 0.4, SEEDS["batch_gauge"](j)) for j, d in enumerate(bdims)]
     bmass = batch_masses(len(bdims), 0.01, 0.2, SEEDS["batch_mass"])
     B = ks.Batch(bdims, [x.fat for x in bg], [x.naik for x in bg], 4, ks.F32)
-    bb = [torch.from_numpy(gaussian_source(x.volume // 2, SEEDS["batch_rhs"](j, r))).cuda()
-          for j, x in enumerate(bg) for r in range(4)]
+    bb_h = [gaussian_source(x.volume // 2, SEEDS["batch_rhs"](j, r))
+            for j, x in enumerate(bg) for r in range(4)]
+    bb = [torch.from_numpy(v).cuda() for v in bb_h]
     bx = [torch.zeros_like(v) for v in bb]
     bvh = [x.volume // 2 for x in bg]
-    del bg
     batch_cfg = B.tune()
     log("batch of %d lattices x 4 RHS ready in %.1f s, schedule %s"
         % (len(bdims), time.time() - t1, json.dumps(batch_cfg)))
@@ -482,17 +581,15 @@ def main():
 
     # multi-shift workload: 32^3 x 48, nine shifts sigma_i = 4 m_i^2, m_i log-spaced 0.002..0.5
     t1 = time.time()
-    MS_DIMS = (32, 32, 32, 48)
-    gm = make_gauge(MS_DIMS, 0.5, SEEDS["gauge"](3))
     GM = ks.Gauge(MS_DIMS, gm.fat, gm.naik)
     for p_, rc_ in ((ks.F64, 18), (ks.F64, 12), (ks.F32, 18), (ks.F32, 12), (ks.F16, 18)):
         GM.prepare(p_, rc_)
         GM.tune(p_, rc_)
-    mb_ = torch.from_numpy(gaussian_source(gm.volume // 2, SEEDS["source"](3))).cuda()
+    mb_ = torch.from_numpy(mb_h).cuda()
     ms_sigma = 4 * np.geomspace(0.002, 0.5, 9) ** 2
     ms_x = [torch.zeros_like(mb_) for _ in ms_sigma]
     ms_vh = gm.volume // 2
-    del gm
+    ms_last = {}
     log("32^3x48 multi-shift field ready in %.1f s" % (time.time() - t1))
     ms_runs = {"f64": [], "f64_r12": [], "f32": [], "f32_r12": [], "f16": []}
 
@@ -514,6 +611,7 @@ def main():
             torch.cuda.synchronize()
             if record:
                 ms_runs[name].append((time.perf_counter() - t, st))
+                ms_last[name] = [x.clone() for x in ms_x]
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         ks.force(GM, ms_res, ms_x, force_v, force_w)
@@ -536,9 +634,11 @@ def main():
     t_gen = t_blocks + time.perf_counter() - t_gen0
     del blocks
     net = ks.Net(flatten_weights(net_init_weights(SEEDS["net_init"])))
-    loss_hist, t_train = learn.train(net, pairs, steps=300, batch=8, lr=2e-3)
-    log("learned preconditioner: %d pairs in %.1f s, 300 Adam steps in %.1f s, loss %.4f -> %.4f"
-        % (len(pairs), t_gen, t_train, loss_hist[0], loss_hist[-1]))
+    NET_STEPS, NET_LR = 1000, 1e-2
+    loss_hist, t_train = learn.train(net, pairs, steps=NET_STEPS, batch=8, lr=NET_LR)
+    log("learned preconditioner: %d pairs in %.1f s, %d Adam steps in %.1f s, loss %.4f -> %.4f"
+        % (len(pairs), t_gen, NET_STEPS, t_train, loss_hist[0], loss_hist[-1]))
+    last_x = {}
     learned_runs = []
     net_times = {"f32": [], "mfma": []}
     net_out = torch.zeros_like(bd)
@@ -564,18 +664,11 @@ def main():
         torch.cuda.synchronize()
         if record:
             learned_runs.append((time.perf_counter() - t, res.stats))
+            last_x["learned_fcg_f32"] = xd
 
     # link construction from the thin links of the same 32^4 field (two smearing levels, U(3)
-    # projection, Naik): bytes of the matrices its passes access in [V][3][3] FP64 fields (144 B
-    # per matrix; neighbouring sites share many of them through the caches): per direction 6
-    # three-link staples (4 matrices each) and 6 fused outer terms (per term 4 inner staples of
-    # 5 matrices, the middle U, the two outer links, F in or U, F out, and the Lepage field at
-    # level 2); then the projection (2 per link), the Naik product (4) and the sign folding (4
-    # per link pair)
-    def smear_bytes(lepage):
-        per_a = 4 * 5 + 1 + 2 + 2 + (1 if lepage else 0)
-        return 4 * 144 * (6 * 4 + 6 * per_a)
-    hisq_bytes = (smear_bytes(False) + smear_bytes(True) + 4 * 144 * (2 + 4 + 4)) * g.volume
+    # projection, Naik): its flops (3x3 complex products, HISQ_FLOPS_PER_SITE) against the FP64
+    # peak, and its least data (thin links in, fat and Naik links out) against HBM
     thin_d = torch.from_numpy(np.ascontiguousarray(g.thin).reshape(-1)).cuda()
     hisq_fat = torch.empty_like(thin_d)
     hisq_naik = torch.empty_like(thin_d)
@@ -601,6 +694,7 @@ def main():
         torch.cuda.synchronize()
         if record:
             full_runs.append((time.perf_counter() - t, res.stats))
+            last_x["full_system_f32"] = (xe, xo)
 
     solves = {"f64": [], "f32": [], "f32_r12": [], "f16_r12": []}
     spectrum = {}
@@ -625,6 +719,7 @@ def main():
             dt = time.perf_counter() - t
             if record:
                 solves[name].append((dt, res.stats))
+                last_x[name] = xd
                 if name == "f64":
                     spectrum["f64"] = lanczos_spectrum(*G.cg_coefficients())
 
@@ -638,6 +733,32 @@ def main():
         log("step %d done" % k)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
+
+    # the FP64 oracle on the host judges every returned solution: its residual b - A x
+    # recomputed with the oracle's A, and the 32^4 FP64 solution's distance to the oracle's own
+    # CG solution (tolerance 1e-12)
+    import oracle
+    ref = oracle_ref.join()
+    oracle.set_threads(oracle.max_threads())
+    t_or = time.time()
+    sig = 4 * MASS * MASS
+    orc = {name: oracle_resid(g, sig, b, x) for name, x in last_x.items()
+           if name != "full_system_f32"}
+    from oracle.solvers import apply_M
+    xe_h, xo_h = (t_.detach().cpu().numpy() for t_ in last_x["full_system_f32"])
+    bo_h = gaussian_source(vh, 2102)
+    me, mo = apply_M(g, MASS, xe_h, xo_h)
+    orc["full_system_f32"] = float(np.sqrt(np.linalg.norm(b - me) ** 2 + np.linalg.norm(bo_h - mo) ** 2) /
+                                   np.sqrt(np.linalg.norm(b) ** 2 + np.linalg.norm(bo_h) ** 2))
+    x_or, info_or = ref
+    x64 = last_x["f64"].detach().cpu().numpy()
+    f64_x_err = float(np.linalg.norm(x64 - x_or) / np.linalg.norm(x_or))
+    ms_orc = {name: [oracle_resid(gm, s_, mb_h, x) for s_, x in zip(ms_sigma, xs)]
+              for name, xs in ms_last.items()}
+    batch_orc = [oracle_resid(bg[p_ // 4], 4 * bmass[p_ // 4] ** 2, bb_h[p_], bx[p_])
+                 for p_ in range(len(bb))]
+    log("oracle residuals of every solution in %.1f s (32^4 oracle CG: %d steps, %.1f s on %d "
+        "threads)" % (time.time() - t_or, info_or.iters, oracle_ref.seconds, oracle_ref.threads))
 
     dsl = {}
     for v, ts in times.items():
@@ -654,22 +775,33 @@ def main():
         med = float(np.median([d for d, _ in rs]))
         st = rs[-1][1]
         tts[name] = {"seconds": med, "iters": st["iters"], "reliable_updates": st["reliable_updates"],
-                     "true_rel_resid": st["true_rel_resid"], "speedup_vs_f64": base / med,
+                     "true_rel_resid_gpu": st["true_rel_resid"],
+                     "true_rel_resid_oracle": orc[name], "speedup_vs_f64": base / med,
                      "model_GBps": st["model_bytes"] / st["seconds"] / 1e9,
                      "frac_of_8TBps": st["model_bytes"] / st["seconds"] / 1e9 / HBM_PEAK_GBS}
+    tts["f64"]["solution_rel_error_vs_oracle_cg"] = f64_x_err
+    tts["f64"]["oracle_cg"] = {"tol": 1e-12, "iters": info_or.iters, "seconds": oracle_ref.seconds,
+                               "threads": oracle_ref.threads}
     fst = full_runs[-1][1]
     fmed = float(np.median([d for d, _ in full_runs]))
     tts["full_system_f32"] = {
         "seconds": fmed, "iters": fst["iters"], "reliable_updates": fst["reliable_updates"],
-        "true_rel_resid_of_Mx_eq_b": fst["true_rel_resid"],
+        "true_rel_resid_of_Mx_eq_b_gpu": fst["true_rel_resid"],
+        "true_rel_resid_of_Mx_eq_b_oracle": orc["full_system_f32"],
         "model_GBps": fst["model_bytes"] / fst["seconds"] / 1e9,
         "note": "M = 2m + D on both parities: even Schur system by FP32-inner CG, odd sites "
                 "reconstructed in FP64"}
     hsec = float(np.median(hisq_runs))
-    links = {"seconds": hsec, "model_GBps": hisq_bytes / hsec / 1e9,
-             "frac_of_8TBps": hisq_bytes / hsec / 1e9 / HBM_PEAK_GBS,
+    hflops = HISQ_FLOPS_PER_SITE * g.volume / hsec / 1e12
+    links = {"seconds": hsec,
+             "roofline": {"bound": "alu", "achieved": hflops, "peak": FP64_PEAK_TFLOPS,
+                          "unit": "TFLOP/s", "frac": hflops / FP64_PEAK_TFLOPS,
+                          "flops_per_site": HISQ_FLOPS_PER_SITE},
+             "least_data_GBps": HISQ_BYTES_PER_SITE * g.volume / hsec / 1e9,
              "note": "fat and Naik links from the 32^4 thin links: fat7, U(3) projection, "
-                     "fat7 + Lepage, Naik, signs (FP64, scratch allocated per call, included)"}
+                     "fat7 + Lepage, Naik, signs (FP64): far below both its FP64 and its HBM "
+                     "roofline; its passes are bound by the latency of cached neighbour-matrix "
+                     "gathers"}
     walls = [w for w, _ in batch_runs]
     per_solve = [x["seconds"] for _, st in batch_runs for x in st]
     worst = max(x["true_rel_resid"] for _, st in batch_runs for x in st)
@@ -680,7 +812,8 @@ def main():
              "solves_per_second": len(bb) / float(np.median(walls)),
              "p50_seconds_per_solve": float(np.percentile(per_solve, 50)),
              "p99_seconds_per_solve": float(np.percentile(per_solve, 99)),
-             "max_true_rel_resid": worst,
+             "max_true_rel_resid_gpu": worst,
+             "max_true_rel_resid_oracle": max(batch_orc),
              "model_GBps": batch_model_bytes(batch_runs[-1][1], bvh) / float(np.median(walls)) / 1e9,
              "iters_range": [min(x["iters"] for _, st in batch_runs for x in st),
                              max(x["iters"] for _, st in batch_runs for x in st)],
@@ -698,7 +831,8 @@ def main():
         mbytes = sum(x["model_bytes"] for x in st)
         msr[name] = {"seconds": med, "shared_iters": shared,
                      "total_iters_per_shift": [x["iters"] for x in st],
-                     "max_true_rel_resid": max(x["true_rel_resid"] for x in st),
+                     "max_true_rel_resid_gpu": max(x["true_rel_resid"] for x in st),
+                     "true_rel_resid_oracle_per_shift": ms_orc[name],
                      "model_gflops": flops / med / 1e9,
                      "model_GBps": mbytes / med / 1e9,
                      "frac_of_8TBps": mbytes / med / 1e9 / HBM_PEAK_GBS}
@@ -712,10 +846,19 @@ def main():
     fpasses = -(-nt_ // 5)
     fbytes = (nt_ * ms_vh * (96 + 96) + fpasses * ms_vh * 2304 +
               fvol * (2 * 4 * 144 + nt_ * 48))
-    msr["force"] = {"seconds": fsec, "terms": nt_, "model_GBps": fbytes / fsec / 1e9,
-                    "frac_of_8TBps": fbytes / fsec / 1e9 / HBM_PEAK_GBS,
+    # least data: the odd-site links once (2304 B per odd site), each term's solution once
+    # (48 B per even site) and both forces written once (2 x 4 x 144 B per site)
+    fleast = ms_vh * 2304 + nt_ * ms_vh * 48 + fvol * 2 * 4 * 144
+    msr["force"] = {"seconds": fsec, "terms": nt_,
+                    "roofline": {"bound": "hbm", "achieved": fleast / fsec / 1e9,
+                                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                 "frac": fleast / fsec / 1e9 / HBM_PEAK_GBS,
+                                 "least_data_bytes": fleast},
+                    "access_model_GBps": fbytes / fsec / 1e9,
                     "note": "link derivative of the nine-term rational action from the "
-                            "multi-shift solutions, fat and Naik links, FP64"}
+                            "multi-shift solutions, fat and Naik links, FP64; the access model "
+                            "also counts the odd images of the solutions written and read back "
+                            "and the links read once per pass of five terms"}
     msr["shifts"] = "sigma_i = 4 m_i^2, m_i = geomspace(0.002, 0.5, 9), tol 1e-9 per shift"
 
     lmed = float(np.median([d for d, _ in learned_runs]))
@@ -728,9 +871,12 @@ def main():
                             3: "<p, Ap> <= 0", 4: "|r| not halved in 50 steps",
                             5: "max_iter"}[lst["fallback"]],
         "fallback_iters": lst["restarts"], "reliable_updates": lst["reliable_updates"],
-        "true_rel_resid": lst["true_rel_resid"], "speedup_vs_f64": base / lmed,
+        "true_rel_resid_gpu": lst["true_rel_resid"],
+        "true_rel_resid_oracle": orc["learned_fcg_f32"], "speedup_vs_f64": base / lmed,
         "speedup_vs_mixed_f32": t_mixed / lmed,
-        "training": {"pairs": len(pairs), "pair_generation_s": t_gen, "adam_steps": 300,
+        "iterations_vs_mixed_f32": lst["iters"] / tts["f32"]["iters"],
+        "training": {"pairs": len(pairs), "pair_generation_s": t_gen, "adam_steps": NET_STEPS,
+                     "lr": NET_LR, "loss": "A-norm error relative to the solution's",
                      "training_s": t_train, "loss_first": float(loss_hist[0]),
                      "loss_last": float(loss_hist[-1]),
                      "break_even_solves_vs_mixed": (overhead / (t_mixed - lmed))
@@ -740,10 +886,10 @@ def main():
     network = {}
     for name, ts in net_times.items():
         avg = float(np.mean(ts))
-        network[name] = {"avg_us": avg * 1e6,
-                         "model_GBps": NET_BYTES_PER_SITE * 2 * vh / avg / 1e9,
-                         "frac_of_8TBps": NET_BYTES_PER_SITE * 2 * vh / avg / 1e9 / HBM_PEAK_GBS}
-    network["model_bytes_per_site"] = NET_BYTES_PER_SITE
+        nb_ = NET_BYTES_PER_SITE[name]
+        network[name] = {"avg_us": avg * 1e6, "model_bytes_per_site": nb_,
+                         "model_GBps": nb_ * 2 * vh / avg / 1e9,
+                         "frac_of_8TBps": nb_ * 2 * vh / avg / 1e9 / HBM_PEAK_GBS}
     network["lattice"] = list(DIMS)
 
     # achievable-bandwidth references (1 GiB read + 1 GiB written): the library's streaming
@@ -810,6 +956,11 @@ def main():
         "network": network,
         "cpu_baseline": cpu,
     }
+    if g5 is not None:
+        del g, gm, bg
+        t5 = time.time()
+        out["learned_48x48x48x64"] = config5(g5, blocks5)
+        log("48^3x64 learned workload in %.1f s" % (time.time() - t5))
     print(json.dumps(out), flush=True)
 
 

@@ -290,16 +290,16 @@ def subblock(field: GaugeField, origin, bdims) -> GaugeField:
         raise ValueError("block origins must be even")
     dims = field.dims
     bdims = tuple(int(b) for b in bdims)
-    # undo the phases and the boundary signs of the big lattice on the fat link
-    fat_big = field.fat.copy()
-    x, y, z, t = lattice_coords(dims)
+    U = _block_view(field.thin, dims, origin, bdims)
+    fat = _block_view(field.fat, dims, origin, bdims)
+    # undo the phases and the boundary signs of the big lattice on the block's fat links (the
+    # signs at the block sites' coordinates in the big lattice)
+    x, y, z, t = (c + o for c, o in zip(lattice_coords(bdims), origin))
     nt = int(dims[3])
     for mu in range(4):
         eta = staggered_phase(mu, x, y, z, t)
         s1 = eta * (time_bc_sign(1, t, nt) if mu == 3 else 1.0)
-        fat_big[mu] *= s1[:, None, None]
-    U = _block_view(field.thin, dims, origin, bdims)
-    fat = _block_view(fat_big, dims, origin, bdims)
+        fat[mu] *= s1[:, None, None]
     naik = naik_from_thin(U, bdims)
     fold_phases(fat, naik, bdims)
     return GaugeField(bdims, fat, naik, U, field.scale, field.seed)
