@@ -226,7 +226,10 @@ ks_status_t ks_cg_coefficients(ks_gauge_t g, int n_max, double* alpha, double* b
  * in at every reliable update of the base system); every shift whose FP64 true residual is
  * then above its target is refined from x_i by ks_cg_solve's method (several at once, one
  * right-hand side each, FP32 inner, reliable updates at p->delta / 10, when the inner precision
- * is reduced).  st: nshift entries. */
+ * is reduced).  In reduced precision a shared iteration that breaks down (a non-finite value,
+ * or <p, A p> <= 0) is not an error: every x_i returns to its FP64 value at the last reliable
+ * update and is refined like the others.  The base (smallest) shift's solution is updated for
+ * as long as any shift iterates, whatever its own tolerance.  st: nshift entries. */
 ks_status_t ks_multishift_cg_solve(ks_gauge_t g, int nshift, const double* sigma,
                                    const double* b_dev, double* const* x_dev,
                                    const double* tol, const ks_solver_params* p,

@@ -29,7 +29,7 @@ constexpr int kFinish = 1024;
 struct MSState {
     double rho, alpha, alpha_prev, beta, beta_prev, pAp;
     double maxr, ru_delta;   // reliable updates of the base residual (ru_delta 0: none)
-    int iter, max_iter, gate, stop_next, status, nactive, nshift, ru_pending;
+    int iter, max_iter, gate, stop_next, status, nactive, nshift, ru_pending, base;
     double delta[kMaxShift], stop2[kMaxShift];
     double zeta[kMaxShift], zeta_prev[kMaxShift];
     double alpha_i[kMaxShift], beta_i[kMaxShift];
@@ -70,8 +70,10 @@ __global__ __launch_bounds__(kFinish) void ms_alpha_kernel(const double* __restr
     const double a = st->rho / pap;
     st->alpha = a;
     for (int i = 0; i < st->nshift; ++i) {
-        st->upd[i] = st->active[i];
-        if (!st->active[i]) continue;
+        // the base shift's solution keeps being updated while any shift iterates: the base
+        // reliable update recomputes r from it, and every shifted residual is zeta_i r
+        st->upd[i] = st->active[i] || i == st->base;
+        if (!st->upd[i]) continue;
         const double z = st->zeta[i], zp = st->zeta_prev[i];
         const double zn = z * zp * st->alpha_prev /
                           (a * st->beta_prev * (zp - z) + zp * st->alpha_prev * (1.0 + st->delta[i] * a));
@@ -132,7 +134,7 @@ __global__ __launch_bounds__(kFinish) void ms_beta_kernel(const double* __restri
         st->beta_i[i] = b * ratio * ratio;
         st->zeta_prev[i] = st->zeta[i];
         st->zeta[i] = zn;
-        if (zn * zn * rn <= st->stop2[i]) {
+        if (st->active[i] && zn * zn * rn <= st->stop2[i]) {
             st->active[i] = 0;
             st->nactive -= 1;
         }
@@ -350,6 +352,7 @@ ks_status_t multishift_core(ks_gauge_t g, int nshift, const double* sigma, const
     hs->max_iter = prm.max_iter;
     hs->nshift = nshift;
     hs->nactive = nshift;
+    hs->base = i0;
     for (int i = 0; i < nshift; ++i) {
         hs->delta[i] = sigma[i] - s0;
         hs->stop2[i] = tol[i] * tol[i] * b2;
@@ -393,12 +396,23 @@ ks_status_t multishift_core(ks_gauge_t g, int nshift, const double* sigma, const
     double model_bytes = 0.0;
     int last_iter = 0;
     int ms_ru = 0;
+    bool rolled_back = false;
     for (;;) {
         KS_HIP(hipMemcpyAsync(hs, st, sizeof(MSState), hipMemcpyDeviceToHost, s));
         KS_HIP(hipStreamSynchronize(s));
-        model_bytes += (hs->iter - last_iter) * multishift_iter_model_bytes(P, RC, hs->nactive, hs->active[i0] != 0) * vh;
+        // the base shift's vectors are updated while any shift iterates
+        const int nupd = hs->nactive + (hs->nactive > 0 && !hs->active[i0] ? 1 : 0);
+        model_bytes += (hs->iter - last_iter) * multishift_iter_model_bytes(P, RC, nupd, true) * vh;
         last_iter = hs->iter;
         if (hs->status != 0) {
+            if (sloppy) {
+                // the reduced-precision recursion broke down (a non-finite value, or
+                // <p, A p> <= 0 from rounding): the x_i increments since the last reliable
+                // update are dropped, every x_i goes back to its FP64 value at that update, and
+                // the FP64 check below sends each shift to the refinement
+                rolled_back = true;
+                break;
+            }
             result = static_cast<ks_status_t>(hs->status);
             set_error("multi-shift CG: %s at step %d",
                       result == KS_ERR_BREAKDOWN ? "breakdown" : "non-finite value", hs->iter);
@@ -427,7 +441,7 @@ ks_status_t multishift_core(ks_gauge_t g, int nshift, const double* sigma, const
         for (int k = 0; k < chunk; ++k) iteration();
     }
     const int ms_iters = hs->iter;
-    flush();
+    if (!rolled_back) flush();
 
     // FP64 verdict per shift; refine the ones above target from x_i
     std::vector<int> need;

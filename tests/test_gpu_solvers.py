@@ -220,6 +220,50 @@ def test_multishift(ks, cfg1, inner):
         assert rel_l2(x, xo[i]) <= 2e-9 * (16.0 + s) / s
 
 
+def test_multishift_loose_base_tolerance(ks, cfg1):
+    """The base (smallest) shift may reach a looser tolerance first: its solution keeps being
+    updated while the heavier shifts iterate, so the base reliable updates stay consistent and
+    the shared iteration takes about the steps of the uniform-tolerance run; every x_i is
+    judged by the oracle against its own tolerance."""
+    announce("multishift loose base tolerance")
+    g, G, b, _, _ = cfg1
+    sig = 4 * np.geomspace(0.002, 0.5, 9) ** 2
+    shared = {}
+    for name, tols in (("uniform", [1e-10] * 9), ("loose", [1e-6] + [1e-10] * 8)):
+        xs = [zeros_dev(b.shape) for _ in sig]
+        rc, stats = ks.multishift_cg_solve(G, sig, dev(b), xs, tols,
+                                           ks.default_params(inner=ks.F32, check_every=4),
+                                           raise_on_error=False)
+        assert rc == 0, name
+        shared[name] = min(st["iters"] for st in stats)
+        for i, s in enumerate(sig):
+            assert true_rel(g, s, b, host(xs[i])) <= tols[i], (name, i)
+    # the heavier shifts converge before the base would reach 1e-10: the loose run stops
+    # earlier, never later
+    assert shared["loose"] <= shared["uniform"] + 4, shared
+
+
+@pytest.mark.parametrize("delta", [0.03, 0.01, 0.003])
+def test_multishift_f16_small_delta(ks, delta):
+    """FP16 shared iterations with rare reliable updates: whether or not the binary16
+    recursion breaks down, the solve succeeds (a broken-down shared phase falls back to the
+    last reliable update and refines every shift); each x_i judged by the oracle."""
+    announce("multishift f16 delta", delta)
+    dims = (16, 16, 16, 16)
+    g = make_gauge(dims, 0.5, 1003)
+    G = ks.Gauge(dims, g.fat, g.naik)
+    b = gaussian_source(g.volume // 2, 2003)
+    sig = 4 * np.geomspace(0.002, 0.5, 9) ** 2
+    xs = [zeros_dev(b.shape) for _ in sig]
+    rc, stats = ks.multishift_cg_solve(G, sig, dev(b), xs, 1e-9,
+                                       ks.default_params(inner=ks.F16, check_every=8, delta=delta),
+                                       raise_on_error=False)
+    assert rc == 0
+    for i, s in enumerate(sig):
+        assert true_rel(g, s, b, host(xs[i])) <= 1e-9, i
+    G.free()
+
+
 def test_multishift_single_shift_equals_cg(ks, cfg1):
     announce("multishift one shift")
     g, G, b, _, _ = cfg1
