@@ -59,12 +59,13 @@ BATCH_STEP_BYTES = 1344 + 1440 + 576 + 288
 # A-applies (the fastest of a lattice's four residuals sets their rate), so it takes them at a
 # 100-fold drop; the FP32 recursion keeps the same step counts there (single-mass CG keeps 0.1)
 BATCH_DELTA = 0.01
-# one FP64 reliable update for 4 right-hand sides: the increments added into the FP64 x
-# (x read and written 2 x 4 x 48, increments read and cleared 2 x 4 x 24), two FP64 multi-RHS
-# hopping terms, r = b - Ax (2 reads, 1 write of 4 x 48) and the conversion to FP32 (4 x 48
-# read, 4 x 24 read/written)
-BATCH_RU_BYTES = (2 * 4 * 48 + 2 * 4 * 24 + (2304 + 2 * 4 * 48) * 2 + 4 * 48 + 3 * 4 * 48 +
-                  4 * 48 + 2 * 4 * 24)
+# one FP64 reliable update for 4 right-hand sides (a step of its own for the lattice): the
+# increments added into the FP64 x (x read and written 2 x 4 x 48, increments read and cleared
+# 2 x 4 x 24), the odd FP64 hopping term (links 2304, x gathered 4 x 48, t written 4 x 48), the
+# even one with r = b - (sigma x - D t) (links 2304, t, x, b read and r written: 4 x 4 x 48),
+# and the restart of the inner vectors (r64 read 4 x 48, r and p read and written 4 x 4 x 24)
+BATCH_RU_BYTES = (2 * 4 * 48 + 2 * 4 * 24) + (2304 + 2 * 4 * 48) + (2304 + 4 * 4 * 48) + \
+    (4 * 48 + 4 * 4 * 24)
 # network (per site of the full lattice): four layers, each reading its site's 8 stored fat
 # links once (4 forward, 4 backward) and its input channels and writing its output channels
 # (FP32 complex colour vectors, 24 bytes each): 1->8, 8->8, 8->8, 8->1.  The FP32 path reads

@@ -309,10 +309,12 @@ ks_status_t ks_batch_create(ks_batch_t* out, int nlat, const int* dims, const do
  * nrhs + r.  masses: host [nlat]; b_dev, x_dev: host arrays of nlat*nrhs device pointers to
  * complex128 [Vh_l][3] (x holds the initial guess, then the solution).  Every pair has its own
  * CG scalars on the device; FP64 reliable updates are taken per lattice (when one pair's
- * residual has fallen by p->delta, the lattice's other unfinished pairs take the update with
- * it, since it costs the lattice one multi-RHS A-apply either way); the host replays a HIP
- * graph of p->check_every steps (captured on the first call, replayed by later ones) until
- * every pair has finished.  st: nlat*nrhs entries.  Returns KS_SUCCESS if every pair reached
+ * residual has met its target or fallen by p->delta, the lattice's other unfinished pairs take
+ * the update with it in the next step, since it costs the lattice one multi-RHS A-apply either
+ * way).  A step is four launches over the whole batch (two multi-RHS hopping terms, the update,
+ * the direction update; a lattice taking a reliable update spends that step on it in FP64);
+ * the host replays a HIP graph of p->check_every steps (captured on the first call, replayed
+ * by later ones) until every pair has finished.  st: nlat*nrhs entries.  Returns KS_SUCCESS if every pair reached
  * p->tol, else the first failing pair's code (all stats filled).  p->inner and p->recon are
  * ignored (the batch's inner precision and 18-real links are used). */
 ks_status_t ks_batch_solve(ks_batch_t b, const double* masses, const double* const* b_dev,

@@ -85,95 +85,138 @@ struct MVec {
     }
 };
 
-// R <= 4: the flags of all pairs are loaded together, not one after another
-__device__ __forceinline__ bool lattice_busy(const BatchPair* pairs, int p0, int R, bool ru)
+// The step's mode for a lattice, from the live pair fields (committed by the last kernel of
+// the previous step): 2 when a pair still iterating has a reliable update due, 1 while a pair
+// still iterates, 0 when every pair is done.  R <= 4: the flags of all pairs are loaded
+// together, not one after another.
+__device__ __forceinline__ int lattice_mode(const BatchPair* pairs, int p0, int R)
 {
-    bool busy = false;
+    int busy = 0, ru = 0;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         if (r < R) {
             const BatchPair& q = pairs[p0 + r];
-            busy = busy || (ru ? (q.ru_now && !q.done) : !q.done);
+            busy |= !q.done;
+            ru |= (!q.done && q.ru_now);
         }
     }
-    return busy;
+    return ru ? 2 : (busy ? 1 : 0);
 }
 
-// out_r = D in_r for every RHS r of the site (XPAY: out_r = sigma_r x_r - D in_r, with
-// per-tile partial sums of Re<x_r, out_r>), on lattices with a pair still iterating.
+// res_r = (D in_r)(h) for the R right-hand sides of site h, links and vectors of precision PP.
+// UNROLL hops per pass of the 16: FP32 keeps four link and neighbour loads in flight
+// (measured best; a full unroll is slower); FP64 at four hops would spill.
+template <int PP, int R>
+__device__ __forceinline__ void hop_site(const LatDesc& L, int par, int h, const void* fat,
+                                         const void* naik, const char* in,
+                                         cx<typename St<PP>::R> res[3][R])
+{
+    using T = typename St<PP>::R;
+    using V = MVec<PP, R>;
+    const Geom& g = L.g;
+    const int vh = g.Vh;
+    int c[4];
+    cb_coords(g, h, par, c);
+    const int i = site_index(g, c);
+    int nb[16];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        nb[mu] = hop_cb(g, i, c, mu, +1);
+        nb[4 + mu] = hop_cb(g, i, c, mu, -1);
+        nb[8 + mu] = hop_cb(g, i, c, mu, +3);
+        nb[12 + mu] = hop_cb(g, i, c, mu, -3);
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int r = 0; r < R; ++r) res[k][r] = {0, 0};
+    constexpr int kHopUnroll = PP == KS_F64 ? 1 : 4;
+#pragma unroll kHopUnroll
+    for (int s = 0; s < 16; ++s) {
+        cx<T> m[9];
+        if (s < 8) load_link<PP, 9>(fat, s, vh, h, m);
+        else load_link<PP, 9>(naik, s - 8, vh, h, m);
+        cx<T> v[3][R];
+        V::load(in, L.vec_off, vh, nb[s], v);
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+#pragma unroll
+                for (int r = 0; r < R; ++r) cfma(res[a][r], m[a * 3 + b], v[b][r]);
+    }
+}
+
+// The two hopping terms of a step over every (lattice, site tile): XPAY = false gives the odd
+// image, XPAY = true the even output.  Per lattice, in the step's mode:
+//   1 (CG step, inner precision): t = D_oe p; then q = sigma p - D_eo t with per-tile partial
+//     sums of Re<p, q>;
+//   2 (reliable update, FP64): t64 = D_oe x; then r64 = b - (sigma x - D_eo t64) with per-tile
+//     partial sums of |r64|^2.
+// Each link load serves all R right-hand sides of the site.  The second term's lead block of a
+// lattice (its first tile) records the step's mode for the two kernels that follow.
 template <int P, int R, bool XPAY, int NT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void batch_dslash_kernel(
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void batch_hop_kernel(
     const LatDesc* __restrict__ lats, const int2* __restrict__ tiles, int ntiles, int par,
     const char* __restrict__ in, char* __restrict__ out, const char* __restrict__ xv,
-    const BatchPair* __restrict__ pairs, double* __restrict__ partials)
+    const char* __restrict__ in64, char* __restrict__ out64, const char* __restrict__ x64,
+    const char* __restrict__ b64, BatchPair* __restrict__ pairs, double* __restrict__ partials)
 {
     using T = typename St<P>::R;
-    using V = MVec<P, R>;
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int2 tl = tiles[t];
         const LatDesc& L = lats[tl.x];
-        const bool busy = lattice_busy(pairs, L.pair0, R, false);
-        if (!busy) {
+        const int mode = lattice_mode(pairs, L.pair0, R);
+        if (XPAY && tl.y == 0 && threadIdx.x == 0) pairs[L.pair0].s_mode = mode;
+        if (mode == 0) {
             if (XPAY && threadIdx.x < R) partials[(size_t)t * R + threadIdx.x] = 0.0;
             continue;
         }
-        const Geom& g = L.g;
-        const int vh = g.Vh;
+        const int vh = L.g.Vh;
         const int h = tl.y + threadIdx.x;
         double dot[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) dot[r] = 0.0;
         if (h < vh) {
-            const void* fat = (P == KS_F64) ? L.fat64[par] : L.fat32[par];
-            const void* naik = (P == KS_F64) ? L.naik64[par] : L.naik32[par];
-            int c[4];
-            cb_coords(g, h, par, c);
-            const int i = site_index(g, c);
-            int nb[16];
+            if (mode == 1) {
+                const void* fat = (P == KS_F64) ? L.fat64[par] : L.fat32[par];
+                const void* naik = (P == KS_F64) ? L.naik64[par] : L.naik32[par];
+                cx<T> res[3][R];
+                hop_site<P, R>(L, par, h, fat, naik, in, res);
+                if (XPAY) {
+                    cx<T> xs[3][R];
+                    MVec<P, R>::load(xv, L.vec_off, vh, h, xs);
 #pragma unroll
-            for (int mu = 0; mu < 4; ++mu) {
-                nb[mu] = hop_cb(g, i, c, mu, +1);
-                nb[4 + mu] = hop_cb(g, i, c, mu, -1);
-                nb[8 + mu] = hop_cb(g, i, c, mu, +3);
-                nb[12 + mu] = hop_cb(g, i, c, mu, -3);
+                    for (int k = 0; k < 3; ++k)
+#pragma unroll
+                        for (int r = 0; r < R; ++r) {
+                            const T sg = (T)pairs[L.pair0 + r].sigma;
+                            res[k][r].r = sg * xs[k][r].r - res[k][r].r;
+                            res[k][r].i = sg * xs[k][r].i - res[k][r].i;
+                            dot[r] += (double)xs[k][r].r * (double)res[k][r].r +
+                                      (double)xs[k][r].i * (double)res[k][r].i;
+                        }
+                }
+                MVec<P, R>::store(out, L.vec_off, vh, h, res);
+            } else {
+                cx<double> res[3][R];
+                hop_site<KS_F64, R>(L, par, h, L.fat64[par], L.naik64[par], in64, res);
+                if (XPAY) {
+                    cx<double> xs[3][R], bs[3][R];
+                    MVec<KS_F64, R>::load(x64, L.vec_off, vh, h, xs);
+                    MVec<KS_F64, R>::load(b64, L.vec_off, vh, h, bs);
+#pragma unroll
+                    for (int k = 0; k < 3; ++k)
+#pragma unroll
+                        for (int r = 0; r < R; ++r) {
+                            const double sg = pairs[L.pair0 + r].sigma;
+                            res[k][r].r = bs[k][r].r - (sg * xs[k][r].r - res[k][r].r);
+                            res[k][r].i = bs[k][r].i - (sg * xs[k][r].i - res[k][r].i);
+                            dot[r] += res[k][r].r * res[k][r].r + res[k][r].i * res[k][r].i;
+                        }
+                }
+                MVec<KS_F64, R>::store(out64, L.vec_off, vh, h, res);
             }
-            cx<T> res[3][R];
-#pragma unroll
-            for (int k = 0; k < 3; ++k)
-#pragma unroll
-                for (int r = 0; r < R; ++r) res[k][r] = {0, 0};
-            // FP32: four hops per pass keep four link and neighbour loads in flight
-            // (measured best; a full unroll is slower); FP64 at four hops would spill
-            constexpr int kHopUnroll = P == KS_F64 ? 1 : 4;
-#pragma unroll kHopUnroll
-            for (int s = 0; s < 16; ++s) {
-                cx<T> m[9];
-                if (s < 8) load_link<P, 9>(fat, s, vh, h, m);
-                else load_link<P, 9>(naik, s - 8, vh, h, m);
-                cx<T> v[3][R];
-                V::load(in, L.vec_off, vh, nb[s], v);
-#pragma unroll
-                for (int a = 0; a < 3; ++a)
-#pragma unroll
-                    for (int b = 0; b < 3; ++b)
-#pragma unroll
-                        for (int r = 0; r < R; ++r) cfma(res[a][r], m[a * 3 + b], v[b][r]);
-            }
-            if (XPAY) {
-                cx<T> xs[3][R];
-                V::load(xv, L.vec_off, vh, h, xs);
-#pragma unroll
-                for (int k = 0; k < 3; ++k)
-#pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        const T sg = (T)pairs[L.pair0 + r].sigma;
-                        res[k][r].r = sg * xs[k][r].r - res[k][r].r;
-                        res[k][r].i = sg * xs[k][r].i - res[k][r].i;
-                        dot[r] += (double)xs[k][r].r * (double)res[k][r].r +
-                                  (double)xs[k][r].i * (double)res[k][r].i;
-                    }
-            }
-            V::store(out, L.vec_off, vh, h, res);
         }
         if (XPAY) {
 #pragma unroll
@@ -186,185 +229,314 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void ba
     }
 }
 
-// FP64 reliable-update form of the multi-RHS hopping term (out_r = D in_r, or with XPAY
-// out_r = sigma_r x_r - D in_r), for the few lattices whose update is due.  Such a launch has
-// little work, so the tile walk of the inner-precision kernel would leave most of the chip
-// idle and each site's chain of 16 dependent link and neighbour loads would set the time.
-// Here every block first finds, with one parallel scan, the lattices with an update due and
-// numbers their 64-site chunks; the chunks are spread over the whole grid; and four lanes
-// share a site, each taking the four matrices of one hop kind (forward one-link, backward
-// one-link, forward Naik, backward Naik): four times the waves and a quarter of the chain.
-// A two-step butterfly adds the four sums (every lane ends with the same total) and lanes 0-2
-// store one colour each.  No partial sums: the residual kernel that follows computes its own.
-constexpr int kRuLanes = 4;                // lanes per site (8 ties, 16 is slower)
-constexpr int kRuSites = 256 / kRuLanes;   // sites per chunk (one block's pass)
-constexpr int kRuGrid = 1024;              // blocks of a reliable-update launch
-
-template <int R, bool XPAY>
-__global__ __launch_bounds__(256) void batch_dslash_ru_kernel(
-    const LatDesc* __restrict__ lats, int nlat, int par, const char* __restrict__ in,
-    char* __restrict__ out, const char* __restrict__ xv, const BatchPair* __restrict__ pairs)
+// Sums over the lattice's tiles of the partials of every RHS (thread j adds tiles j, j + NT,
+// ... in order, then the fixed wave and block order): every block of the lattice gets the
+// same totals bit for bit.
+template <int NT>
+__device__ __forceinline__ void lattice_totals(const LatDesc& L, const double* __restrict__ part,
+                                               int R, double tot[4])
 {
-    using V = MVec<KS_F64, R>;
-    __shared__ int pref[257];   // pref[j]: chunks of the chunk-group's lattices before j
-    constexpr int kM = 16 / kRuLanes;   // matrices per lane, all of one hop kind
-    const int part = threadIdx.x & (kRuLanes - 1);
-    const int sl = threadIdx.x / kRuLanes;
-    const int kind = (part * kM) >> 2;  // 0: +1, 1: -1 (one-link), 2: +3, 3: -3 (Naik)
-    const int dist = (kind & 1) ? ((kind & 2) ? -3 : -1) : ((kind & 2) ? 3 : 1);
-    const int mu0 = (part * kM) & 3;
-    for (int l0 = 0; l0 < nlat; l0 += 256) {
-        const int l = l0 + threadIdx.x;
-        int n = 0;
-        if (l < nlat && lattice_busy(pairs, lats[l].pair0, R, true))
-            n = (lats[l].g.Vh + kRuSites - 1) / kRuSites;
-        if (threadIdx.x == 0) pref[0] = 0;
-        pref[threadIdx.x + 1] = n;
-        __syncthreads();
-        for (int off = 1; off < 256; off <<= 1) {   // inclusive scan of pref[1..256]
-            const int v = threadIdx.x >= off ? pref[threadIdx.x + 1 - off] : 0;
-            __syncthreads();
-            pref[threadIdx.x + 1] += v;
-            __syncthreads();
-        }
-        const int total = pref[256];
-        for (int u = blockIdx.x; u < total; u += gridDim.x) {
-            int lo = 0, hi = 256;   // the lattice j with pref[j] <= u < pref[j + 1]
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (pref[mid] <= u) lo = mid;
-                else hi = mid;
-            }
-            const LatDesc& L = lats[l0 + lo];
-            const Geom& g = L.g;
-            const int vh = g.Vh;
-            const int h = (u - pref[lo]) * kRuSites + sl;
-            const void* links = kind < 2 ? L.fat64[par] : L.naik64[par];
-            cx<double> res[3][R];
+    __shared__ double red[NT / 64][4];
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int t = L.tile_begin + threadIdx.x; t < L.tile_end; t += NT)
+        for (int r = 0; r < R; ++r) s[r] += part[(size_t)t * R + r];
 #pragma unroll
-            for (int k = 0; k < 3; ++k)
+    for (int r = 0; r < 4; ++r) s[r] = wave_sum(s[r]);
+    if ((threadIdx.x & 63) == 0)
 #pragma unroll
-                for (int r = 0; r < R; ++r) res[k][r] = {0.0, 0.0};
-            if (h < vh) {
-                int c[4];
-                cb_coords(g, h, par, c);
-                const int i = site_index(g, c);
-#pragma unroll 1
-                for (int mu = mu0; mu < mu0 + kM; ++mu) {
-                    cx<double> m[9];
-                    load_link<KS_F64, 9>(links, (kind & 1) * 4 + mu, vh, h, m);
-                    cx<double> v[3][R];
-                    V::load(in, L.vec_off, vh, hop_cb(g, i, c, mu, dist), v);
+        for (int r = 0; r < 4; ++r) red[threadIdx.x >> 6][r] = s[r];
+    __syncthreads();
 #pragma unroll
-                    for (int a = 0; a < 3; ++a)
+    for (int r = 0; r < 4; ++r) {
+        double v = 0.0;
 #pragma unroll
-                        for (int b = 0; b < 3; ++b)
-#pragma unroll
-                            for (int r = 0; r < R; ++r) cfma(res[a][r], m[a * 3 + b], v[b][r]);
-                }
-            }
-#pragma unroll
-            for (int off = 1; off < kRuLanes; off <<= 1)
-#pragma unroll
-                for (int k = 0; k < 3; ++k)
-#pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        res[k][r].r += __shfl_xor(res[k][r].r, off);
-                        res[k][r].i += __shfl_xor(res[k][r].i, off);
-                    }
-            if (h >= vh) continue;
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                if (part != k) continue;
-                const size_t o = V::off(L.vec_off, vh, k, h);
-                double2* dst = reinterpret_cast<double2*>(out + o);
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    double2 w = make_double2(res[k][r].r, res[k][r].i);
-                    if (XPAY) {
-                        const double2 x = reinterpret_cast<const double2*>(xv + o)[r];
-                        const double sg = pairs[L.pair0 + r].sigma;
-                        w = make_double2(sg * x.x - w.x, sg * x.y - w.y);
-                    }
-                    dst[r] = w;
-                }
-            }
-        }
-        __syncthreads();   // pref is rewritten by the next group of lattices
+        for (int k = 0; k < NT / 64; ++k) v += red[k][r];
+        tot[r] = v;
     }
+    __syncthreads();   // red is reused by the next tile
 }
 
-// x += alpha p (FP64 x, or with FP32 inner iterations its FP32 increments); r -= alpha q;
-// partial sums of |r|^2 per RHS
+// The update of a step; a capped grid strides over the tiles (the lattice totals that every
+// block needs are summed once per block and lattice, not once per tile).
+//   mode 1: alpha = rho / <p, A p> per pair from the lattice's partials; x += alpha p (FP64 x,
+//     or its FP32 increments with FP32 inner iterations), r -= alpha q, partials of |r|^2;
+//     a pair with <p, A p> <= 0 or not finite stops with an error.
+//   mode 2 (after r64 = b - A x): each pair finishes (|r64| at target; or the step cap, not
+//     converged; or a non-finite value) or continues from r = r64 with beta = |r64|^2 / rho
+//     (0 for the initial residual): p = r + beta p.
+// Results for the next kernel go to the shadow fields (the lead block of the lattice).
 template <int P, int R, int NT>
-__global__ __launch_bounds__(NT) void batch_update_kernel(const LatDesc* __restrict__ lats,
-                                                         const int2* __restrict__ tiles, int ntiles,
-                                                         char* __restrict__ x, const char* __restrict__ p,
-                                                         const char* __restrict__ q, char* __restrict__ r,
-                                                         const BatchPair* __restrict__ pairs,
-                                                         double* __restrict__ partials)
+__global__ __launch_bounds__(NT) void batch_update_kernel(
+    const LatDesc* __restrict__ lats, const int2* __restrict__ tiles, int ntiles,
+    char* __restrict__ x, char* __restrict__ p, const char* __restrict__ q,
+    char* __restrict__ r, const char* __restrict__ r64, BatchPair* __restrict__ pairs,
+    const double* __restrict__ part, double* __restrict__ part2)
 {
     using T = typename St<P>::R;
+    using MV = MVec<P, R>;
+    int cached = -1;           // the lattice whose totals tot holds (the grid strides over the
+    double tot[4];             // tiles, so a block's tiles mostly share a lattice)
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int2 tl = tiles[t];
         const LatDesc& L = lats[tl.x];
-        if (!lattice_busy(pairs, L.pair0, R, false)) {
-            if (threadIdx.x < R) partials[(size_t)t * R + threadIdx.x] = 0.0;
-            continue;
+        const int mode = pairs[L.pair0].s_mode;
+        if (mode == 0) continue;
+        if (tl.x != cached) {
+            lattice_totals<NT>(L, part, R, tot);
+            cached = tl.x;
         }
+        const bool lead = tl.y == 0 && threadIdx.x == 0;
         const int vh = L.g.Vh;
         const int h = tl.y + threadIdx.x;
-        double nrm[R];
-#pragma unroll
-        for (int k = 0; k < R; ++k) nrm[k] = 0.0;
-        if (h < vh) {
-            // xv: x itself (FP64), or x's FP32 increments since the last reliable update
-            cx<T> pv[3][R], qv[3][R], rv[3][R], xv[3][R];
-            MVec<P, R>::load(p, L.vec_off, vh, h, pv);
-            MVec<P, R>::load(q, L.vec_off, vh, h, qv);
-            MVec<P, R>::load(r, L.vec_off, vh, h, rv);
-            MVec<P, R>::load(x, L.vec_off, vh, h, xv);
+        if (mode == 1) {
+            double al[R];
+            bool go[R];
 #pragma unroll
             for (int k = 0; k < R; ++k) {
                 const BatchPair& pp = pairs[L.pair0 + k];
-                // a finished pair keeps x and r as they are: its direction p is no longer
-                // maintained (never written for a pair that starts finished), so it must not
-                // enter even with a zero step
-                if (pp.done) continue;
-                const T af = (T)pp.alpha;
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    xv[c][k].r = fma(af, pv[c][k].r, xv[c][k].r);
-                    xv[c][k].i = fma(af, pv[c][k].i, xv[c][k].i);
-                    rv[c][k].r = fma(-af, qv[c][k].r, rv[c][k].r);
-                    rv[c][k].i = fma(-af, qv[c][k].i, rv[c][k].i);
-                    nrm[k] += (double)rv[c][k].r * rv[c][k].r + (double)rv[c][k].i * rv[c][k].i;
+                const double pap = tot[k];
+                const bool ok = isfinite(pap) && pap > 0.0;
+                go[k] = !pp.done && ok;
+                al[k] = go[k] ? pp.rho / pap : 0.0;
+                if (lead) {
+                    BatchPair& w = pairs[L.pair0 + k];
+                    w.s_alpha = al[k];
+                    w.s_done = pp.done || !ok;
+                    w.s_status = (!pp.done && !ok) ? (isfinite(pap) ? KS_ERR_BREAKDOWN
+                                                                    : KS_ERR_NONFINITE)
+                                                   : pp.status;
+                    w.s_iter = pp.iter;
+                    w.s_rho = pp.rho;
+                    w.s_maxr = pp.maxr;
                 }
             }
-            MVec<P, R>::store(x, L.vec_off, vh, h, xv);
-            MVec<P, R>::store(r, L.vec_off, vh, h, rv);
-        }
+            double nrm[R];
 #pragma unroll
-        for (int k = 0; k < R; ++k) {
-            const double s = block_sum<NT>(nrm[k]);
-            if (threadIdx.x == 0) partials[(size_t)t * R + k] = s;
-            __syncthreads();
+            for (int k = 0; k < R; ++k) nrm[k] = 0.0;
+            if (h < vh) {
+                // xv: x itself (FP64), or x's FP32 increments since the last reliable update
+                cx<T> pv[3][R], qv[3][R], rv[3][R], xv[3][R];
+                MV::load(p, L.vec_off, vh, h, pv);
+                MV::load(q, L.vec_off, vh, h, qv);
+                MV::load(r, L.vec_off, vh, h, rv);
+                MV::load(x, L.vec_off, vh, h, xv);
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    // a finished pair keeps x and r: its direction is no longer maintained
+                    if (!go[k]) continue;
+                    const T af = (T)al[k];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        xv[c][k].r = fma(af, pv[c][k].r, xv[c][k].r);
+                        xv[c][k].i = fma(af, pv[c][k].i, xv[c][k].i);
+                        rv[c][k].r = fma(-af, qv[c][k].r, rv[c][k].r);
+                        rv[c][k].i = fma(-af, qv[c][k].i, rv[c][k].i);
+                        nrm[k] += (double)rv[c][k].r * rv[c][k].r + (double)rv[c][k].i * rv[c][k].i;
+                    }
+                }
+                MV::store(x, L.vec_off, vh, h, xv);
+                MV::store(r, L.vec_off, vh, h, rv);
+            }
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const double s = block_sum<NT>(nrm[k]);
+                if (threadIdx.x == 0) part2[(size_t)t * R + k] = s;
+                __syncthreads();
+            }
+        } else {
+            double be[R];
+            bool cont[R];
+            int fresh[R];
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const BatchPair& pp = pairs[L.pair0 + k];
+                const double r2 = tot[k];
+                const bool live = !pp.done;
+                const bool fin = !isfinite(r2);
+                const bool met = !fin && r2 <= pp.stop2;
+                const bool cap = !fin && !met && pp.iter >= pp.max_iter;
+                cont[k] = live && !fin && !met && !cap;
+                fresh[k] = pp.first;
+                be[k] = cont[k] ? (pp.first ? 0.0 : r2 / pp.rho) : 0.0;
+                if (lead) {
+                    BatchPair& w = pairs[L.pair0 + k];
+                    w.s_done = pp.done || !cont[k];
+                    w.s_finished = live && !cont[k];
+                    w.s_status = !live ? pp.status : fin ? KS_ERR_NONFINITE
+                                                        : cap ? KS_ERR_NOT_CONVERGED : pp.status;
+                    w.s_true_r2 = live ? r2 : pp.true_r2;
+                    w.s_ru = pp.ru + ((live && !pp.first) ? 1 : 0);
+                    w.s_beta = be[k];
+                    w.s_rho = cont[k] ? r2 : pp.rho;
+                    w.s_maxr = cont[k] ? sqrt(r2) : pp.maxr;
+                    w.s_iter = pp.iter;
+                }
+            }
+            if (h < vh) {
+                cx<double> a[3][R];
+                cx<T> rv[3][R], pv[3][R];
+                MVec<KS_F64, R>::load(r64, L.vec_off, vh, h, a);
+                MV::load(r, L.vec_off, vh, h, rv);
+                MV::load(p, L.vec_off, vh, h, pv);
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    if (!cont[k]) continue;
+                    const T b = (T)be[k];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        rv[c][k] = {(T)a[c][k].r, (T)a[c][k].i};
+                        if (fresh[k]) {
+                            pv[c][k] = rv[c][k];
+                        } else {
+                            pv[c][k].r = fma(b, pv[c][k].r, rv[c][k].r);
+                            pv[c][k].i = fma(b, pv[c][k].i, rv[c][k].i);
+                        }
+                    }
+                }
+                MV::store(r, L.vec_off, vh, h, rv);
+                MV::store(p, L.vec_off, vh, h, pv);
+            }
         }
     }
 }
 
-// FP32 inner: x += dx, dx = 0 on the lattices with a reliable update due (all = 1: every
-// lattice, at the end of a solve)
+// The last kernel of a step (grid as for the update).
+//   mode 1: |r|^2 of every pair from the lattice's partials; a pair whose residual met its
+//     target or the step cap, or fell by delta since the last reliable update, asks for a
+//     reliable update, and then every pair of the lattice still iterating takes it in the next
+//     step (it costs the lattice one FP64 multi-RHS A-apply whatever the number of pairs):
+//     x's FP32 increments are added into x here.  Otherwise p = r + beta p, beta = |r|^2 / rho.
+//   mode 2: the reliable update's results are committed.
+// The lead block commits the live fields of the lattice's pairs from the shadows.
+template <int P, int R, int NT>
+__global__ __launch_bounds__(NT) void batch_direction_kernel(
+    const LatDesc* __restrict__ lats, const int2* __restrict__ tiles, int ntiles,
+    const char* __restrict__ r, char* __restrict__ p, char* __restrict__ x64,
+    char* __restrict__ dx, BatchPair* __restrict__ pairs, const double* __restrict__ part2)
+{
+    using T = typename St<P>::R;
+    using MV = MVec<P, R>;
+    int cached = -1;
+    double tot[4];
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int2 tl = tiles[t];
+        const LatDesc& L = lats[tl.x];
+        const int mode = pairs[L.pair0].s_mode;
+        if (mode == 0) continue;
+        const bool lead = tl.y == 0 && threadIdx.x == 0;
+        if (mode == 2) {
+            if (lead) {
+                const unsigned long long now = wall_clock64();
+                for (int k = 0; k < R; ++k) {
+                    BatchPair& w = pairs[L.pair0 + k];
+                    if (w.done) continue;
+                    w.done = w.s_done;
+                    w.status = w.s_status;
+                    w.true_r2 = w.s_true_r2;
+                    w.ru = w.s_ru;
+                    w.beta = w.s_beta;
+                    w.rho = w.s_rho;
+                    w.maxr = w.s_maxr;
+                    w.ru_now = 0;
+                    w.first = 0;
+                    if (w.s_finished) w.t_done = now;
+                }
+            }
+            continue;
+        }
+        if (tl.x != cached) {
+            lattice_totals<NT>(L, part2, R, tot);
+            cached = tl.x;
+        }
+        bool live[R], nonfin[R], due[R];
+        bool any_due = false;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const BatchPair& pp = pairs[L.pair0 + k];
+            const double rn = tot[k];
+            live[k] = !pp.s_done;
+            nonfin[k] = live[k] && !isfinite(rn);
+            const bool met = rn <= pp.stop2 || pp.s_iter + 1 >= pp.max_iter;
+            const bool fell = sqrt(rn) < pp.delta * pp.s_maxr;
+            due[k] = live[k] && !nonfin[k] && (met || fell);
+            any_due = any_due || due[k];
+        }
+        const int vh = L.g.Vh;
+        const int h = tl.y + threadIdx.x;
+        if (h < vh) {
+            if (any_due) {
+                if (P == KS_F32 && dx) {
+                    cx<double> xv[3][R];
+                    cx<float> dv[3][R], zero[3][R];
+                    MVec<KS_F64, R>::load(x64, L.vec_off, vh, h, xv);
+                    MVec<KS_F32, R>::load(dx, L.vec_off, vh, h, dv);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+#pragma unroll
+                        for (int k = 0; k < R; ++k) {
+                            xv[c][k].r += (double)dv[c][k].r;
+                            xv[c][k].i += (double)dv[c][k].i;
+                            zero[c][k] = {0.f, 0.f};
+                        }
+                    MVec<KS_F64, R>::store(x64, L.vec_off, vh, h, xv);
+                    MVec<KS_F32, R>::store(dx, L.vec_off, vh, h, zero);
+                }
+            } else {
+                cx<T> rv[3][R], pv[3][R];
+                MV::load(r, L.vec_off, vh, h, rv);
+                MV::load(p, L.vec_off, vh, h, pv);
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    if (!live[k] || nonfin[k]) continue;
+                    const T b = (T)(tot[k] / pairs[L.pair0 + k].s_rho);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        pv[c][k].r = fma(b, pv[c][k].r, rv[c][k].r);
+                        pv[c][k].i = fma(b, pv[c][k].i, rv[c][k].i);
+                    }
+                }
+                MV::store(p, L.vec_off, vh, h, pv);
+            }
+        }
+        if (lead) {
+            const unsigned long long now = wall_clock64();
+            for (int k = 0; k < R; ++k) {
+                BatchPair& w = pairs[L.pair0 + k];
+                if (w.done) continue;
+                w.alpha = w.s_alpha;
+                if (w.s_done) {   // <p, A p> broke down in the update
+                    w.done = 1;
+                    w.status = w.s_status;
+                    w.t_done = now;
+                    continue;
+                }
+                w.iter = w.s_iter + 1;
+                const double rn = tot[k];
+                if (nonfin[k]) {
+                    w.done = 1;
+                    w.status = KS_ERR_NONFINITE;
+                    w.t_done = now;
+                } else if (any_due) {
+                    w.ru_now = due[k] ? 2 : 1;
+                } else {
+                    w.beta = rn / w.s_rho;
+                    w.rho = rn;
+                    w.maxr = fmax(w.s_maxr, sqrt(rn));
+                }
+            }
+        }
+    }
+}
+
+// FP32 inner: x += dx, dx = 0 on every lattice (the remaining increments at the end)
 template <int R, int NT>
 __global__ __launch_bounds__(NT) void batch_flush_kernel(const LatDesc* __restrict__ lats,
                                                         const int2* __restrict__ tiles, int ntiles,
-                                                        char* __restrict__ x, char* __restrict__ dx,
-                                                        const BatchPair* __restrict__ pairs, int all)
+                                                        char* __restrict__ x, char* __restrict__ dx)
 {
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int2 tl = tiles[t];
         const LatDesc& L = lats[tl.x];
-        if (!all && !lattice_busy(pairs, L.pair0, R, true)) continue;
         const int vh = L.g.Vh;
         const int h = tl.y + threadIdx.x;
         if (h >= vh) continue;
@@ -385,257 +557,12 @@ __global__ __launch_bounds__(NT) void batch_flush_kernel(const LatDesc* __restri
     }
 }
 
-// FP64: r64 = b - Ax for lattices with an update due; partial sums of |r|^2
-template <int R, int NT>
-__global__ __launch_bounds__(NT) void batch_resid_kernel(const LatDesc* __restrict__ lats,
-                                                        const int2* __restrict__ tiles, int ntiles,
-                                                        const char* __restrict__ b,
-                                                        const char* __restrict__ ax,
-                                                        char* __restrict__ r64,
-                                                        const BatchPair* __restrict__ pairs,
-                                                        double* __restrict__ partials)
-{
-    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const int2 tl = tiles[t];
-        const LatDesc& L = lats[tl.x];
-        if (!lattice_busy(pairs, L.pair0, R, true)) {
-            if (threadIdx.x < R) partials[(size_t)t * R + threadIdx.x] = 0.0;
-            continue;
-        }
-        const int vh = L.g.Vh;
-        const int h = tl.y + threadIdx.x;
-        double nrm[R];
-#pragma unroll
-        for (int k = 0; k < R; ++k) nrm[k] = 0.0;
-        if (h < vh) {
-            cx<double> bv[3][R], av[3][R];
-            MVec<KS_F64, R>::load(b, L.vec_off, vh, h, bv);
-            MVec<KS_F64, R>::load(ax, L.vec_off, vh, h, av);
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-#pragma unroll
-                for (int k = 0; k < R; ++k) {
-                    bv[c][k].r -= av[c][k].r;
-                    bv[c][k].i -= av[c][k].i;
-                    nrm[k] += bv[c][k].r * bv[c][k].r + bv[c][k].i * bv[c][k].i;
-                }
-            MVec<KS_F64, R>::store(r64, L.vec_off, vh, h, bv);
-        }
-#pragma unroll
-        for (int k = 0; k < R; ++k) {
-            const double s = block_sum<NT>(nrm[k]);
-            if (threadIdx.x == 0) partials[(size_t)t * R + k] = s;
-            __syncthreads();
-        }
-    }
-}
-
-// r_inner = r64 for pairs whose reliable update ran this step and that continue
-template <int P, int R, int NT>
-__global__ __launch_bounds__(NT) void batch_load_r_kernel(const LatDesc* __restrict__ lats,
-                                                         const int2* __restrict__ tiles, int ntiles,
-                                                         const char* __restrict__ r64,
-                                                         char* __restrict__ rs,
-                                                         const BatchPair* __restrict__ pairs)
-{
-    using T = typename St<P>::R;
-    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const int2 tl = tiles[t];
-        const LatDesc& L = lats[tl.x];
-        if (!lattice_busy(pairs, L.pair0, R, true)) continue;
-        const int vh = L.g.Vh;
-        const int h = tl.y + threadIdx.x;
-        if (h >= vh) continue;
-        cx<double> a[3][R];
-        cx<T> o[3][R];
-        MVec<KS_F64, R>::load(r64, L.vec_off, vh, h, a);
-        MVec<P, R>::load(rs, L.vec_off, vh, h, o);
-#pragma unroll
-        for (int k = 0; k < R; ++k) {
-            const BatchPair& pp = pairs[L.pair0 + k];
-            if (!pp.ru_now) continue;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) o[c][k] = {(T)a[c][k].r, (T)a[c][k].i};
-        }
-        MVec<P, R>::store(rs, L.vec_off, vh, h, o);
-    }
-}
-
-// p = r + beta p for pairs still iterating (p = r where beta is 0 after the initial update)
-template <int P, int R, int NT>
-__global__ __launch_bounds__(NT) void batch_xpay_kernel(const LatDesc* __restrict__ lats,
-                                                       const int2* __restrict__ tiles, int ntiles,
-                                                       const char* __restrict__ rs, char* __restrict__ ps,
-                                                       const BatchPair* __restrict__ pairs, int fresh)
-{
-    using T = typename St<P>::R;
-    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const int2 tl = tiles[t];
-        const LatDesc& L = lats[tl.x];
-        if (!lattice_busy(pairs, L.pair0, R, false)) continue;
-        const int vh = L.g.Vh;
-        const int h = tl.y + threadIdx.x;
-        if (h >= vh) continue;
-        cx<T> rv[3][R], pv[3][R];
-        MVec<P, R>::load(rs, L.vec_off, vh, h, rv);
-        MVec<P, R>::load(ps, L.vec_off, vh, h, pv);
-#pragma unroll
-        for (int k = 0; k < R; ++k) {
-            const BatchPair& pp = pairs[L.pair0 + k];
-            if (pp.done) continue;
-            const T b = (T)pp.beta;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                if (fresh) {
-                    pv[c][k] = rv[c][k];
-                } else {
-                    pv[c][k].r = fma(b, pv[c][k].r, rv[c][k].r);
-                    pv[c][k].i = fma(b, pv[c][k].i, rv[c][k].i);
-                }
-            }
-        }
-        MVec<P, R>::store(ps, L.vec_off, vh, h, pv);
-    }
-}
-
-// ---------------------------------------------------------------- per-pair scalar steps
-// One block per pair; it sums its lattice's tile partials in tile order.
-
+// One block per pair: its lattice's tile partials in tile order.
 __device__ __forceinline__ double pair_sum(const LatDesc& L, const double* part, int R, int r)
 {
     double s = 0.0;
     for (int t = L.tile_begin + threadIdx.x; t < L.tile_end; t += kFin) s += part[(size_t)t * R + r];
     return block_sum<kFin>(s);
-}
-
-// The scalar steps run one block of kLat threads per lattice: one pass over the lattice's tile
-// partials gives the sums of all its R pairs (thread j adds tiles j, j + kLat, ... in order,
-// then wave sums and the waves in order, for all pairs in one LDS round), so a lattice with
-// many tiles is summed as fast as a small one.
-constexpr int kLat = 1024;
-
-__device__ __forceinline__ void lattice_sums(const LatDesc& L, const double* __restrict__ part,
-                                             int R, double* tot)
-{
-    __shared__ double red[kLat / 64][4];
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int t = L.tile_begin + threadIdx.x; t < L.tile_end; t += kLat)
-        for (int r = 0; r < R; ++r) s[r] += part[(size_t)t * R + r];
-    // every pair's wave sums in one LDS round; thread r then adds pair r's waves in order
-#pragma unroll
-    for (int r = 0; r < 4; ++r) s[r] = wave_sum(s[r]);
-    if ((threadIdx.x & 63) == 0)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) red[threadIdx.x >> 6][r] = s[r];
-    __syncthreads();
-    if (threadIdx.x < R) {
-        double v = 0.0;
-#pragma unroll
-        for (int k = 0; k < kLat / 64; ++k) v += red[k][threadIdx.x];
-        tot[threadIdx.x] = v;
-    }
-    __syncthreads();
-}
-
-// alpha = rho / <p, A p> per pair (thread r of the lattice's block takes pair r)
-__global__ __launch_bounds__(kLat) void batch_alpha_kernel(const LatDesc* __restrict__ lats, int R,
-                                                           BatchPair* __restrict__ pairs,
-                                                           const double* __restrict__ part)
-{
-    const LatDesc& L = lats[blockIdx.x];
-    if (!lattice_busy(pairs, L.pair0, R, false)) return;
-    __shared__ double tot[4];
-    lattice_sums(L, part, R, tot);
-    if (threadIdx.x >= R) return;
-    BatchPair& q = pairs[L.pair0 + threadIdx.x];
-    if (q.done) return;
-    const double pap = tot[threadIdx.x];
-    q.ru_now = 0;
-    if (!isfinite(pap) || !(pap > 0.0)) {
-        q.status = isfinite(pap) ? KS_ERR_BREAKDOWN : KS_ERR_NONFINITE;
-        q.done = 1;
-        q.t_done = wall_clock64();
-        q.alpha = 0.0;
-        return;
-    }
-    q.alpha = q.rho / pap;
-}
-
-// One block per lattice.  Each pair's |r|^2 of the step (its tile partials in tile order) and
-// the pair's own decision (update due: target met or step cap; or |r| fell by delta), then
-// the lattice's: a reliable update costs the lattice one FP64 multi-RHS A-apply whatever the
-// number of its pairs that take part, so when one pair's residual has fallen by delta every
-// unfinished pair takes the update with it (the right-hand sides then stay in step instead of
-// each paying its own).  Pairs without an update continue: beta = |r|^2 / rho, rho = |r|^2.
-__global__ __launch_bounds__(kLat) void batch_beta_kernel(const LatDesc* __restrict__ lats, int R,
-                                                          BatchPair* __restrict__ pairs,
-                                                          const double* __restrict__ part)
-{
-    const LatDesc& L = lats[blockIdx.x];
-    if (!lattice_busy(pairs, L.pair0, R, false)) return;
-    __shared__ double rn[4];
-    lattice_sums(L, part, R, rn);
-    if (threadIdx.x >= 64) return;   // lane r of the first wave takes pair r
-    const int r = threadIdx.x;
-    BatchPair* q = r < R ? &pairs[L.pair0 + r] : nullptr;
-    bool live = q && !q->done;
-    if (live) {
-        q->iter += 1;
-        q->rn = rn[r];
-        if (!isfinite(q->rn)) {
-            q->status = KS_ERR_NONFINITE;
-            q->done = 1;
-            q->t_done = wall_clock64();
-            live = false;
-        } else if (q->rn <= q->stop2 || q->iter >= q->max_iter) {
-            q->ru_now = 1;
-        } else if (sqrt(q->rn) < q->delta * q->maxr) {
-            q->ru_now = 2;
-        }
-    }
-    const bool drop = __any(live && q->ru_now == 2);
-    if (!live) return;
-    if (drop && q->ru_now == 0) q->ru_now = 1;
-    if (q->ru_now) return;
-    q->beta = q->rn / q->rho;
-    q->rho = q->rn;
-    q->maxr = fmax(q->maxr, sqrt(q->rn));
-}
-
-// After r = b - A x in FP64 for the lattices with an update due: each such pair either
-// finishes or continues with beta = |r|^2 / rho (thread r of the lattice's block, pair r)
-__global__ __launch_bounds__(kLat) void batch_reliable_kernel(const LatDesc* __restrict__ lats, int R,
-                                                              BatchPair* __restrict__ pairs,
-                                                              const double* __restrict__ part,
-                                                              int initial)
-{
-    const LatDesc& L = lats[blockIdx.x];
-    if (!lattice_busy(pairs, L.pair0, R, true)) return;
-    __shared__ double tot[4];
-    lattice_sums(L, part, R, tot);
-    if (threadIdx.x >= R) return;
-    BatchPair& q = pairs[L.pair0 + threadIdx.x];
-    if (!q.ru_now || q.done) return;
-    const double r2 = tot[threadIdx.x];
-    q.true_r2 = r2;
-    if (!initial) q.ru += 1;
-    if (!isfinite(r2)) {
-        q.status = KS_ERR_NONFINITE;
-        q.done = 1;
-    } else if (r2 <= q.stop2) {
-        q.done = 1;
-    } else if (q.iter >= q.max_iter) {
-        q.status = KS_ERR_NOT_CONVERGED;
-        q.done = 1;
-    }
-    if (q.done) {
-        q.t_done = wall_clock64();
-        q.ru_now = 0;
-        return;
-    }
-    q.beta = initial ? 0.0 : r2 / q.rho;
-    q.rho = r2;
-    q.maxr = sqrt(r2);
 }
 
 __global__ void batch_census_kernel(const BatchPair* __restrict__ pairs, int n, int* __restrict__ out)
@@ -702,7 +629,8 @@ __global__ __launch_bounds__(kFin) void batch_init_pairs_kernel(const LatDesc* _
     q.stop2 = tol * tol * s;
     q.delta = delta;
     q.max_iter = max_iter;
-    q.ru_now = (s > 0.0) ? 1 : 0;   // the initial residual is one FP64 reliable update
+    q.ru_now = (s > 0.0) ? 1 : 0;   // the initial residual is the first step's FP64 update
+    q.first = 1;
     q.done = (s > 0.0) ? 0 : 1;
     pairs[pi] = q;
     b2_out[pi] = s;
@@ -732,79 +660,62 @@ __global__ void batch_io_kernel(const LatDesc* __restrict__ lats, char* __restri
 
 // ---------------------------------------------------------------- launchers
 
+constexpr int kUpdateGrid = 2048;   // blocks of the update and direction kernels
+
 template <int R, int NT>
 struct BatchLaunch {
-    static void dslash(BatchCtx& c, int prec, bool xpay, int par, const char* in, char* out,
-                       const char* x, hipStream_t s)
+    // a hopping term of the step: odd image (xpay = false) or even output (xpay = true)
+    static void hop(BatchCtx& c, bool xpay, hipStream_t s)
     {
         const int nt = c.ntiles[c.tile_idx];
         const int2* tl = c.tiles[c.tile_idx];
         const int grid = c.grid(nt);
-        double* part = c.partials;
-#define KS_BD(P, X)                                                                            \
-    batch_dslash_kernel<P, R, X, NT><<<grid, NT, 0, s>>>(c.lats_dev, tl, nt, par, in, out, x,   \
-                                                       c.pairs, part)
-        if (prec == KS_F64) {
-            if (xpay) KS_BD(KS_F64, true);
-            else KS_BD(KS_F64, false);
+#define KS_BH(P, X)                                                                            \
+    batch_hop_kernel<P, R, X, NT><<<grid, NT, 0, s>>>(                                          \
+        c.lats_dev, tl, nt, X ? 0 : 1, X ? c.ts : c.ps, X ? c.qs : c.ts, c.ps,                  \
+        X ? c.t64 : c.x64, X ? c.r64 : c.t64, c.x64, c.b64, c.pairs, c.partials)
+        if (c.prec == KS_F64) {
+            if (xpay) KS_BH(KS_F64, true);
+            else KS_BH(KS_F64, false);
         } else {
-            if (xpay) KS_BD(KS_F32, true);
-            else KS_BD(KS_F32, false);
+            if (xpay) KS_BH(KS_F32, true);
+            else KS_BH(KS_F32, false);
         }
-#undef KS_BD
+#undef KS_BH
         KS_HIP(hipGetLastError());
     }
+    // one step: two hopping terms, the update, the direction update (four launches)
     static void step(BatchCtx& c, hipStream_t s)
     {
         const int nt = c.ntiles[c.tile_idx];
         const int2* tl = c.tiles[c.tile_idx];
-        const int grid = nt;   // streaming vector kernels: one block per tile (the tuned
-                                // persistent schedule is for the hopping terms)
-        const int P = c.prec;
-        // inner A-apply
-        dslash(c, P, false, 1, c.ps, c.ts, nullptr, s);
-        dslash(c, P, true, 0, c.ts, c.qs, c.ps, s);
-        const int nlat = (int)c.lats_host.size();
-        batch_alpha_kernel<<<nlat, kLat, 0, s>>>(c.lats_dev, R, c.pairs, c.partials);
-        if (P == KS_F64)
-            batch_update_kernel<KS_F64, R, NT><<<grid, NT, 0, s>>>(c.lats_dev, tl, nt, c.x64, c.ps, c.qs, c.rs, c.pairs, c.partials);
-        else
-            batch_update_kernel<KS_F32, R, NT><<<grid, NT, 0, s>>>(c.lats_dev, tl, nt, c.dx32, c.ps, c.qs, c.rs, c.pairs, c.partials);
-        batch_beta_kernel<<<nlat, kLat, 0, s>>>(c.lats_dev, R, c.pairs, c.partials);
-        reliable(c, 0, s);
-        if (P == KS_F64)
-            batch_xpay_kernel<KS_F64, R, NT><<<grid, NT, 0, s>>>(c.lats_dev, tl, nt, c.rs, c.ps, c.pairs, 0);
-        else
-            batch_xpay_kernel<KS_F32, R, NT><<<grid, NT, 0, s>>>(c.lats_dev, tl, nt, c.rs, c.ps, c.pairs, 0);
+        hop(c, false, s);
+        hop(c, true, s);
+        // the update kernels stride over the tiles with a capped grid: every block sums its
+        // lattices' partials, once per lattice it meets
+        const int ug = std::min(nt, kUpdateGrid);
+        if (c.prec == KS_F64) {
+            batch_update_kernel<KS_F64, R, NT><<<ug, NT, 0, s>>>(c.lats_dev, tl, nt, c.x64, c.ps,
+                                                                 c.qs, c.rs, c.r64, c.pairs,
+                                                                 c.partials, c.partials2);
+            batch_direction_kernel<KS_F64, R, NT><<<ug, NT, 0, s>>>(c.lats_dev, tl, nt, c.rs,
+                                                                    c.ps, c.x64, nullptr, c.pairs,
+                                                                    c.partials2);
+        } else {
+            batch_update_kernel<KS_F32, R, NT><<<ug, NT, 0, s>>>(c.lats_dev, tl, nt, c.dx32, c.ps,
+                                                                 c.qs, c.rs, c.r64, c.pairs,
+                                                                 c.partials, c.partials2);
+            batch_direction_kernel<KS_F32, R, NT><<<ug, NT, 0, s>>>(c.lats_dev, tl, nt, c.rs,
+                                                                    c.ps, c.x64, c.dx32, c.pairs,
+                                                                    c.partials2);
+        }
         KS_HIP(hipGetLastError());
     }
-    // FP64 r = b - A x for the pairs flagged ru_now, then the per-pair decision
-    static void reliable(BatchCtx& c, int initial, hipStream_t s)
-    {
-        const int nt = c.ntiles[c.tile_idx];
-        const int2* tl = c.tiles[c.tile_idx];
-        const int grid = nt;   // streaming vector kernels: one block per tile (the tuned
-                                // persistent schedule is for the hopping terms)
-        const int nlat = (int)c.lats_host.size();
-        if (c.prec == KS_F32) flush(c, 0, s);
-        batch_dslash_ru_kernel<R, false><<<kRuGrid, 256, 0, s>>>(c.lats_dev, nlat, 1, c.x64, c.t64,
-                                                                 nullptr, c.pairs);
-        batch_dslash_ru_kernel<R, true><<<kRuGrid, 256, 0, s>>>(c.lats_dev, nlat, 0, c.t64, c.ax64,
-                                                                c.x64, c.pairs);
-        batch_resid_kernel<R, NT><<<grid, NT, 0, s>>>(c.lats_dev, tl, nt, c.b64, c.ax64, c.r64, c.pairs, c.partials);
-        batch_reliable_kernel<<<(int)c.lats_host.size(), kLat, 0, s>>>(c.lats_dev, R, c.pairs, c.partials,
-                                                                      initial);
-        if (c.prec == KS_F64)
-            batch_load_r_kernel<KS_F64, R, NT><<<grid, NT, 0, s>>>(c.lats_dev, tl, nt, c.r64, c.rs, c.pairs);
-        else
-            batch_load_r_kernel<KS_F32, R, NT><<<grid, NT, 0, s>>>(c.lats_dev, tl, nt, c.r64, c.rs, c.pairs);
-        KS_HIP(hipGetLastError());
-    }
-    static void flush(BatchCtx& c, int all, hipStream_t s)
+    static void flush(BatchCtx& c, hipStream_t s)
     {
         const int nt = c.ntiles[c.tile_idx];
         batch_flush_kernel<R, NT><<<nt, NT, 0, s>>>(c.lats_dev, c.tiles[c.tile_idx], nt, c.x64,
-                                                    c.dx32, c.pairs, all);
+                                                    c.dx32);
         KS_HIP(hipGetLastError());
     }
     static void b2(BatchCtx& c, hipStream_t s)
@@ -813,34 +724,20 @@ struct BatchLaunch {
         batch_b2_kernel<R, NT><<<nt, NT, 0, s>>>(c.lats_dev, c.tiles[c.tile_idx], c.b64, c.partials);
         KS_HIP(hipGetLastError());
     }
-    static void start(BatchCtx& c, hipStream_t s)
-    {
-        const int nt = c.ntiles[c.tile_idx];
-        const int2* tl = c.tiles[c.tile_idx];
-        const int grid = nt;   // streaming vector kernels: one block per tile (the tuned
-                                // persistent schedule is for the hopping terms)
-        reliable(c, 1, s);
-        if (c.prec == KS_F64)
-            batch_xpay_kernel<KS_F64, R, NT><<<grid, NT, 0, s>>>(c.lats_dev, tl, nt, c.rs, c.ps, c.pairs, 1);
-        else
-            batch_xpay_kernel<KS_F32, R, NT><<<grid, NT, 0, s>>>(c.lats_dev, tl, nt, c.rs, c.ps, c.pairs, 1);
-        KS_HIP(hipGetLastError());
-    }
 };
 
 static const int kTileSizes[3] = {64, 128, 256};
 
 template <int R>
-static void dispatch(BatchCtx& c, int what, hipStream_t s, int xpay_or_init = 0)
+static void dispatch(BatchCtx& c, int what, hipStream_t s)
 {
     const int nt = kTileSizes[c.tile_idx];
 #define KS_DISP(NTV)                                                                    \
     if (nt == NTV) {                                                                    \
         if (what == 0) BatchLaunch<R, NTV>::step(c, s);                                 \
-        else if (what == 1) BatchLaunch<R, NTV>::start(c, s);                           \
         else if (what == 3) BatchLaunch<R, NTV>::b2(c, s);                              \
-        else if (what == 4) BatchLaunch<R, NTV>::flush(c, 1, s);                        \
-        else BatchLaunch<R, NTV>::dslash(c, c.prec, xpay_or_init != 0, 1, c.ps, c.ts, nullptr, s); \
+        else if (what == 4) BatchLaunch<R, NTV>::flush(c, s);                           \
+        else BatchLaunch<R, NTV>::hop(c, false, s);                                     \
         return;                                                                         \
     }
     KS_DISP(64)
@@ -876,6 +773,7 @@ void batch_free(BatchCtx* c)
     device_free(c->lats_dev);
     for (int k = 0; k < 3; ++k) device_free(c->tiles[k]);
     device_free(c->partials);
+    device_free(c->partials2);
     device_free(c->pairs);
     device_free(c->clock);
     device_free(c->census);
@@ -934,6 +832,7 @@ static void batch_setup(BatchCtx* c, hipStream_t s)
     c->lats_dev = static_cast<LatDesc*>(device_alloc(sizeof(LatDesc) * nlat));
     c->set_tiles(0, s);
     c->partials = static_cast<double*>(device_alloc(sizeof(double) * max_tiles * nrhs));
+    c->partials2 = static_cast<double*>(device_alloc(sizeof(double) * max_tiles * nrhs));
     c->pairs = static_cast<BatchPair*>(device_alloc(sizeof(BatchPair) * c->npairs));
     KS_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->pairs_host), sizeof(BatchPair) * c->npairs));
     c->clock = static_cast<unsigned long long*>(device_alloc(sizeof(unsigned long long)));
@@ -1132,9 +1031,8 @@ ks_status_t batch_solve_pairs(BatchCtx& c, const double* sigma, const double* to
                                                       c.prec == KS_F64 ? 0.0 : prm.delta,
                                                       prm.max_iter, c.b2);
     KS_HIP(hipGetLastError());
-    run(c, 1, s);
 
-    // the step sequence, captured once per configuration into a graph of `chunk` steps
+    // the step sequence (the first step computes the initial residual in FP64), captured once per configuration into a graph of `chunk` steps
     const int chunk = std::max(1, prm.check_every);
     if (!c.graph_exec || c.graph_chunk != chunk) {
         if (c.graph_exec) (void)hipGraphExecDestroy(c.graph_exec);

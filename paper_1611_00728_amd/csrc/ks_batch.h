@@ -19,14 +19,24 @@ struct LatDesc {
     int pair0;                // first (lattice, RHS) pair index
 };
 
-// CG scalars of one (lattice, RHS) pair.
+// CG scalars of one (lattice, RHS) pair.  One step is four launches (two hopping terms, the
+// update, the direction update); every block of a lattice takes the same decisions from the
+// same sums, and each kernel writes only fields that no block of the same kernel reads: the
+// live fields are committed by the last kernel of the step (its lead block), the shadows s_*
+// carry the third kernel's results to it, and s_mode (first pair of a lattice) the step's mode
+// from the second hopping term to both.
 struct BatchPair {
     double sigma;                // shift of this pair's operator, sigma - D_eo D_oe
     double rho, alpha, beta, maxr, stop2, delta, true_r2;
-    double rn;                   // |r|^2 of the step, applied to rho once the step's updates are known
     unsigned long long t_done;   // device wall clock at convergence
     int iter, max_iter, ru, done, status;
-    int ru_now;                  // 0: none; 1: update due (target met, step cap, or forced); 2: |r| fell by delta
+    int ru_now;                  // reliable update due in the next step (1: target met, step cap,
+                                 // forced by the lattice or initial; 2: |r| fell by delta)
+    int first;                   // the next reliable update is the initial residual (beta = 0)
+    // shadows written by the update kernel for the direction-update kernel
+    double s_alpha, s_beta, s_rho, s_maxr, s_true_r2;
+    int s_done, s_status, s_iter, s_ru, s_finished;
+    int s_mode;                  // first pair of a lattice: 0 idle, 1 CG step, 2 reliable update
 };
 
 struct BatchCtx {
@@ -44,7 +54,8 @@ struct BatchCtx {
     int tile_idx = 0;          // 0: 64, 1: 128, 2: 256 sites per tile
     int persistent = 0;        // >0: grid of this many blocks striding over the tiles
     float tuned_us = 0.f;
-    double* partials = nullptr;
+    double* partials = nullptr;   // per tile and RHS: <p, A p> of a step, or |b - A x|^2
+    double* partials2 = nullptr;  // per tile and RHS: |r|^2 after the update
     BatchPair* pairs = nullptr;
     BatchPair* pairs_host = nullptr;
     unsigned long long* clock = nullptr;
