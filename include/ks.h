@@ -92,7 +92,10 @@ void ks_default_params(ks_solver_params* p);
 /* ------------------------------------------------------------------ gauge field */
 
 /* Loads V (fat) and W (naik), complex128 [4][V][3][3] each, host (on_device = 0) or device
- * (on_device = 1) memory, into a new handle.  The library keeps, for both output parities,
+ * (on_device = 1) memory, into a new handle (the gauge fields the solver of Sec. 3 reads).
+ * Only the FP64 18-real store is built here; the reduced-precision and 12-real stores are
+ * built by ks_gauge_prepare (or on first use), so the Naik storage is chosen per store and per
+ * call rather than once at load.  The library keeps, for both output parities,
  * the 16 matrices of every site {V_mu(x), -V_mu(x-mu)^+, W_mu(x), -W_mu(x-3mu)^+} as FP64
  * site-major planes (the 8-way forward-plus-backward storage of Sec. 3).  Synchronises the
  * stream before returning; the caller may free its arrays afterwards.
@@ -117,8 +120,10 @@ size_t ks_gauge_device_bytes(ks_gauge_t g);
 
 /* ------------------------------------------------------------------ fields */
 
-/* A one-parity colour-vector field of the handle's lattice in the library's layout:
- * FP64 and FP32 as three site-major complex planes, FP16 as one 16-byte record per site
+/* A one-parity colour-vector field of the handle's lattice in the library's layout (the
+ * colour vectors of one checkerboard that the staggered dslash and CG of Sec. 3 act on, laid
+ * out site-major for coalesced loads as Sec. 3's data-layout discussion asks of its vector
+ * unit): FP64 and FP32 as three site-major complex planes, FP16 as one 16-byte record per site
  * (FP32 scale n, then three binary16 complex numbers of v / n, n = max |real| of the site). */
 ks_status_t ks_field_create(ks_field_t* f, ks_gauge_t g, ks_parity_t parity, ks_prec_t prec);
 ks_status_t ks_field_free(ks_field_t f);
@@ -129,8 +134,11 @@ ks_status_t ks_field_export(ks_field_t f, double* dst_dev, hipStream_t stream);
 
 /* ------------------------------------------------------------------ operator */
 
-/* out = D_{p,1-p} in, p = parity of `out`; `in` must have the other parity and both fields
- * the same precision (the link store of that precision and `recon` is built on first use).
+/* The staggered dslash of Sec. 3 restricted to one output parity (its even-odd form, the
+ * kernel whose memory bandwidth Sec. 4 measures): out = D_{p,1-p} in, p = parity of `out`;
+ * `in` must have the other parity and both fields the same precision, and `recon` selects the
+ * Naik storage (the link store of that precision and `recon` is built on first use, as
+ * ks_gauge_prepare would).
  * KS_ERR_ARG if parities or precisions do not match, if out == in, or if the fields belong
  * to another lattice.  Asynchronous. */
 ks_status_t ks_dslash_eo(ks_gauge_t g, ks_field_t out, ks_field_t in, ks_recon_t recon,
@@ -197,7 +205,8 @@ ks_status_t ks_apply_A_noalloc(ks_gauge_t g, double sigma, const double* in_dev,
 
 /* ------------------------------------------------------------------ solvers */
 
-/* Solves (4 m^2 - D_eo D_oe) x = b, b_dev and x_dev complex128 [Vh][3] device arrays.
+/* The single-mass staggered CG of Sec. 3 on the even-odd normal equations:
+ * solves (4 m^2 - D_eo D_oe) x = b, b_dev and x_dev complex128 [Vh][3] device arrays.
  * x_dev holds the initial guess on entry (zero it for x0 = 0) and the solution on return.
  * With p->inner = KS_F64 this is plain FP64 CG; with KS_F32 / KS_F16 the Krylov vectors and
  * the inner operator are FP32 / FP16; x's increments are summed in FP32 and added into the
@@ -274,11 +283,16 @@ ks_status_t ks_force(ks_gauge_t g, int nterm, const double* residues, const doub
  * level1 = NULL: (1/8, 1/16, 1/64, 1/384, 0); level2 = NULL: (1, 1/16, 1/64, 1/384, -1/8)
  * (fat = 9/8 for unit links, so 9/8 - 3/24 = 1 normalises the free derivative); c_naik: -1/24
  * for HISQ.  thin_dev, fat_dev, naik_dev: device complex128 [4][V][3][3] (layout of
- * ks_gauge_load), distinct.  KS_ERR_NONFINITE when a level-1 link is singular.  Allocates
- * about 12 link fields of scratch for the call; synchronises the stream. */
+ * ks_gauge_load), distinct.  KS_ERR_NONFINITE when a level-1 link is singular.  Its scratch
+ * (14 link fields, 2.1 GB at 32^4) is allocated on the first call on a device and kept for
+ * later calls (grown for a larger lattice) until ks_hisq_release; calls that overlap in time
+ * on one device share it and race.  Synchronises the stream. */
 ks_status_t ks_hisq_links(const int dims[4], const double* thin_dev, double* fat_dev,
                           double* naik_dev, const double* level1, const double* level2,
                           double c_naik, hipStream_t stream);
+
+/* Frees the scratch that ks_hisq_links keeps on every device (waits for each device). */
+ks_status_t ks_hisq_release(void);
 
 /* ------------------------------------------------------------------ batched solves */
 

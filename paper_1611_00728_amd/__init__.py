@@ -110,6 +110,7 @@ def lib():
         L.ks_hisq_links.argtypes = [C.POINTER(C.c_int), _vp, _vp, _vp, C.POINTER(C.c_double),
                                     C.POINTER(C.c_double), C.c_double, _vp]
         L.ks_force.argtypes = [_vp, C.c_int, C.POINTER(C.c_double), C.POINTER(_vp), _vp, _vp, _vp]
+        L.ks_hisq_release.argtypes = []
         L.ks_multishift_cg_solve.argtypes = [_vp, C.c_int, C.POINTER(C.c_double), _vp,
                                              C.POINTER(_vp), C.POINTER(C.c_double),
                                              C.POINTER(SolverParams), C.POINTER(SolverStats), _vp]
@@ -350,6 +351,11 @@ def hisq_links(dims, thin, fat, naik, level1=None, level2=None, c_naik=-1.0 / 24
     _check(lib().ks_hisq_links(d, ptrs[0], ptrs[1], ptrs[2], l1, l2, float(c_naik),
                                _stream(stream)))
 
+
+
+def hisq_release():
+    """Frees the scratch the link construction keeps on the device between calls."""
+    _check(lib().ks_hisq_release())
 
 def force(gauge: Gauge, residues, xs, force_fat, force_naik, stream=None):
     """Link derivative of sum_i r_i phi^+ A_i^-1 phi from the solutions xs (ks_force);

@@ -644,6 +644,14 @@ ks_status_t ks_hisq_links(const int dims[4], const double* thin_dev, double* fat
     KS_API_END
 }
 
+ks_status_t ks_hisq_release(void)
+{
+    KS_API_BEGIN
+    hisq_release();
+    return KS_SUCCESS;
+    KS_API_END
+}
+
 ks_status_t ks_stream_copy(void* dst_dev, const void* src_dev, size_t bytes, hipStream_t stream)
 {
     KS_API_BEGIN

@@ -14,6 +14,8 @@
 // x + s_a a in registers (its four five-link staples with their seven-link middles, and the
 // Lepage term, which shares the outer links).
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "ks_device.h"
@@ -449,17 +451,63 @@ const double kHisqLevel1[5] = {1.0 / 8, 1.0 / 16, 1.0 / 64, 1.0 / 384, 0.0};
 const double kHisqLevel2[5] = {1.0, 1.0 / 16, 1.0 / 64, 1.0 / 384, -1.0 / 8};
 const double kHisqNaik = -1.0 / 24;
 
+namespace {
+
+// Scratch of the link construction (six staple fields, the level-1 links and their U(3)
+// projection: 14 link fields), kept per device between calls and grown when a larger lattice
+// comes, so that repeated calls allocate nothing.
+struct HisqScratch {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+std::mutex g_hisq_mu;
+std::map<int, HisqScratch> g_hisq;
+
+char* hisq_scratch(size_t bytes)
+{
+    int dev = 0;
+    KS_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_hisq_mu);
+    HisqScratch& h = g_hisq[dev];
+    if (h.bytes < bytes) {
+        device_free(h.ptr);
+        h.ptr = nullptr;
+        h.bytes = 0;
+        h.ptr = device_alloc(bytes);
+        h.bytes = bytes;
+    }
+    return static_cast<char*>(h.ptr);
+}
+
+}  // namespace
+
+void hisq_release()
+{
+    std::lock_guard<std::mutex> lk(g_hisq_mu);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (auto& kv : g_hisq) {
+        (void)hipSetDevice(kv.first);
+        (void)hipDeviceSynchronize();
+        device_free(kv.second.ptr);
+    }
+    (void)hipSetDevice(cur);
+    g_hisq.clear();
+}
+
 void hisq_links(const Geom& G, const double* thin, double* fat, double* naik,
                 const double* level1, const double* level2, double c_naik, hipStream_t st)
 {
     const long vol = G.V;
     const size_t mat = (size_t)vol * 9 * sizeof(double2);
-    std::vector<void*> bufs;
+    char* base = hisq_scratch(14 * mat + 256);
+    size_t used = 0;
     auto get = [&](size_t bytes) {
-        bufs.push_back(device_alloc(bytes));
-        return static_cast<double2*>(bufs.back());
+        double2* p = reinterpret_cast<double2*>(base + used);
+        used += (bytes + 255) / 256 * 256;
+        return p;
     };
-    try {
+    {
         double2* s1[6];
         for (auto& p : s1) p = get(mat);
         double2* V1 = get(4 * mat);
@@ -482,11 +530,7 @@ void hisq_links(const Geom& G, const double* thin, double* fat, double* naik,
         KS_HIP(hipStreamSynchronize(st));
         KS_REQUIRE(!hbad, KS_ERR_NONFINITE,
                    "link construction: a level-1 smeared link is singular or not finite");
-    } catch (...) {
-        for (void* p : bufs) device_free(p);
-        throw;
     }
-    for (void* p : bufs) device_free(p);
 }
 
 }  // namespace ks

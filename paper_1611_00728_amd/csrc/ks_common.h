@@ -232,6 +232,8 @@ extern const double kHisqLevel2[5];
 extern const double kHisqNaik;
 void hisq_links(const Geom& G, const double* thin, double* fat, double* naik,
                 const double* level1, const double* level2, double c_naik, hipStream_t st);
+// frees the link construction's scratch on every device
+void hisq_release();
 // whether the kernel of this launch form exists for the variant
 bool dslash_form_built(ks_prec_t prec, ks_recon_t recon, int links_per_pass, int link_access,
                        int staged);

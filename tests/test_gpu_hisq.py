@@ -86,3 +86,28 @@ def test_hisq_singular_links_rejected(ks):
     with pytest.raises(ks.KSError) as e:
         ks.hisq_links((4, 4, 5, 4), z5, torch.empty_like(z5), torch.empty_like(z5))
     assert e.value.code == -1
+
+
+def test_scratch_kept_between_calls(ks):
+    """The scratch kept between calls gives the same links on a later call, on a smaller
+    lattice after a larger one, and after it has been released."""
+    import torch
+    announce("hisq scratch reuse")
+    outs = {}
+    for dims in ((8, 8, 8, 8), (4, 6, 4, 8), (8, 8, 8, 8)):
+        U = thin_links(dims, 0.5, 123)
+        thin = dev(U.reshape(-1))
+        fat, naik = torch.empty_like(thin), torch.empty_like(thin)
+        ks.hisq_links(dims, thin, fat, naik)
+        torch.cuda.synchronize()
+        got = (host(fat), host(naik))
+        if dims in outs:
+            assert all(np.array_equal(a, b) for a, b in zip(got, outs[dims]))
+        outs[dims] = got
+    ks.hisq_release()
+    dims = (4, 6, 4, 8)
+    thin = dev(thin_links(dims, 0.5, 123).reshape(-1))
+    fat, naik = torch.empty_like(thin), torch.empty_like(thin)
+    ks.hisq_links(dims, thin, fat, naik)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(fat), outs[dims][0]) and np.array_equal(host(naik), outs[dims][1])
