@@ -113,30 +113,46 @@ def thin_links(dims, scale: float, seed: int) -> np.ndarray:
             g = rng.standard_normal((e - s, 4, 3, 3, 2))
             U[:, s:e] = np.swapaxes(su3_from_gaussian(g, scale), 0, 1)
         return U
-    import multiprocessing as mp
     shape = (4, V, 3, 3)
     _POOL_STATE["out"] = _shared_array(shape)
     try:
-        with mp.get_context("fork").Pool(workers) as pool:
-            tasks = ((s, e, rng.standard_normal((e - s, 4, 3, 3, 2)), scale) for s, e in chunks)
-            for _ in pool.imap_unordered(_pool_su3, tasks, chunksize=1):
-                pass
+        tasks = ((s, e, rng.standard_normal((e - s, 4, 3, 3, 2)), scale) for s, e in chunks)
+        _run_pool(workers, _pool_su3, tasks)
         U = np.array(_POOL_STATE["out"])
     finally:
         _POOL_STATE.clear()
     return U
 
 
+def _run_pool(workers: int, fn, tasks) -> None:
+    """Run fn over tasks in forked workers.  The pool is closed and joined, so every worker
+    returns from its loop and exits by itself (no worker is sent a signal)."""
+    import multiprocessing as mp
+    pool = mp.get_context("fork").Pool(workers)
+    try:
+        for _ in pool.imap_unordered(fn, tasks, chunksize=1):
+            pass
+        pool.close()
+    except BaseException:
+        pool.terminate()
+        raise
+    finally:
+        pool.join()
+
+
 def _workers(nchunks: int) -> int:
     """Worker processes for chunked generation: none for a few chunks, none once this process
-    has initialised a GPU through torch (the workers are forked), else up to 16 (or the
-    KS_INPUT_WORKERS environment variable)."""
+    has initialised a GPU through torch, none under a ROCm profiler (its preloaded library
+    has set up the GPU runtime before the program starts, and the workers are forked), else
+    up to 16 (or the KS_INPUT_WORKERS environment variable)."""
     import os
     import sys
     if nchunks < 4:
         return 1
     torch = sys.modules.get("torch")
     if torch is not None and torch.cuda.is_initialized():
+        return 1
+    if any(k.startswith("ROCPROF") for k in os.environ):
         return 1
     n = int(os.environ.get("KS_INPUT_WORKERS", min(16, os.cpu_count() or 1)))
     return max(1, min(n, nchunks))
@@ -203,17 +219,14 @@ def fat_and_naik(U: np.ndarray, dims, seed: int):
         naik = naik_from_thin(U, dims)
         fold_phases(fat, naik, dims)
         return fat, naik
-    import multiprocessing as mp
     shape = U.shape
     _POOL_STATE["U"] = U                       # read by the forked workers, never written
     _POOL_STATE["fat"] = _shared_array(shape)
     _POOL_STATE["naik"] = _shared_array(shape)
     try:
-        with mp.get_context("fork").Pool(workers) as pool:
-            tasks = ((s, e, rng.standard_normal((e - s, 4, 3, 3, 2)), tuple(dims))
-                     for s, e in chunks)
-            for _ in pool.imap_unordered(_pool_fat_naik, tasks, chunksize=1):
-                pass
+        tasks = ((s, e, rng.standard_normal((e - s, 4, 3, 3, 2)), tuple(dims))
+                 for s, e in chunks)
+        _run_pool(workers, _pool_fat_naik, tasks)
         fat = np.array(_POOL_STATE["fat"])
         naik = np.array(_POOL_STATE["naik"])
     finally:
