@@ -66,13 +66,18 @@ BATCH_DELTA = 0.01
 # and the restart of the inner vectors (r64 read 4 x 48, r and p read and written 4 x 4 x 24)
 BATCH_RU_BYTES = (2 * 4 * 48 + 2 * 4 * 24) + (2304 + 2 * 4 * 48) + (2304 + 4 * 4 * 48) + \
     (4 * 48 + 4 * 4 * 24)
-# network (per site of the full lattice): four layers, each reading its site's 8 stored fat
-# links once (4 forward, 4 backward) and its input channels and writing its output channels
-# (FP32 complex colour vectors, 24 bytes each): 1->8, 8->8, 8->8, 8->1.  The FP32 path reads
-# FP32 links (8 x 72 bytes) in every layer; the matrix-core path reads the binary16 link store
-# (8 x 36 bytes) in its three last layers.
-_NET_CH = (24 + 192) + 2 * (192 + 192) + (192 + 24)
-NET_BYTES_PER_SITE = {"f32": 4 * 576 + _NET_CH, "mfma": 576 + 3 * 288 + _NET_CH}
+# network (per site of the full lattice), applied to the solver's FP32 even-site fields (24 B
+# per even site), as the flexible CG applies it.  FP32 path: four layers 1->8, 8->8, 8->8,
+# 8->1, each reading its site's 8 stored FP32 fat links (8 x 72 B) and its input channels and
+# writing its output channels (FP32 complex colour vectors, 24 B each), plus the input embedded
+# on both parities (even input read, both parities written: 12 + 24 B per site) and the even
+# output read back into the field (12 + 12 B).  Matrix-core path: binary16 links (8 x 36 B) and
+# activations (96 B per site for 8 channels); the first layer reads the even input and the odd
+# sites' links and writes both parities, the middle two read and write every site, the last
+# reads all activations and the even sites' links and writes the even output.
+_NET_F32 = sum(576 + 24 * (ci + co) for ci, co in ((1, 8), (8, 8), (8, 8), (8, 1))) + 36 + 24
+_NET_MFMA = (12 + 144 + 96) + 2 * (96 + 288 + 96) + (96 + 144 + 12)
+NET_BYTES_PER_SITE = {"f32": _NET_F32, "mfma": _NET_MFMA}
 # link construction, per site: the 3x3 complex products of the two smearing levels as nested
 # (per direction 6 three-link staples and 6 outer terms of 4 inner staples, 2 products each:
 # 72; Lepage adds loads, no products), the Naik products (2 per direction), 198 flops each,
@@ -642,7 +647,8 @@ def main():
     last_x = {}
     learned_runs = []
     net_times = {"f32": [], "mfma": []}
-    net_out = torch.zeros_like(bd)
+    net_in = ks.Field(G, 0, ks.F32).load(bd)
+    net_out = ks.Field(G, 0, ks.F32)
 
     def net_burst(record):
         for name in ("f32", "mfma"):
@@ -650,7 +656,7 @@ def main():
                    for _ in range(5)]
             for e0, e1 in evs:
                 e0.record(stream)
-                net.apply(G, bd, net_out, mfma=(name == "mfma"))
+                net.apply_field(net_in, net_out, mfma=(name == "mfma"))
                 e1.record(stream)
             stream.synchronize()
             if record:

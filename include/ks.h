@@ -372,12 +372,20 @@ ks_status_t ks_net_get_weights(ks_net_t n, double* weights);
 ks_status_t ks_net_free(ks_net_t n);
 
 /* out_dev = N(in_dev), complex128 [Vh][3] device arrays of the handle's lattice.  use_mfma = 0:
- * FP32 channel mixing on the vector ALUs, transports with the FP32 fat links; 1: the three
- * last layers (8 -> 8, 8 -> 8, 8 -> 1) mix on the matrix cores (binary16 operands, FP32
- * accumulation) and transport in FP32 arithmetic with the binary16 fat-link store (built on
- * first use).  Asynchronous on `stream`. */
+ * FP32 channel mixing on the vector ALUs, transports with the FP32 fat links; 1: every layer
+ * mixes its channels on the matrix cores (binary16 operands, FP32 accumulation), transports
+ * with the binary16 fat-link store (built on first use) by FP32-accumulated dot products, and
+ * keeps the activations between layers in binary16.  Asynchronous on `stream`. */
 ks_status_t ks_net_apply(ks_net_t n, ks_gauge_t g, const double* in_dev, double* out_dev,
                          int use_mfma, hipStream_t stream);
+
+/* out = N(in) on two even-parity fields of one gauge handle in the solver's storage (KS_F64 or
+ * KS_F32, both the same): the application that ks_fcg_solve makes each step, reading and
+ * writing the fields directly.  use_mfma as in ks_net_apply.  KS_ERR_ARG for null or aliased
+ * fields, fields of other handles or parities, differing or binary16 precisions.
+ * Asynchronous on `stream`. */
+ks_status_t ks_net_apply_field(ks_net_t n, ks_field_t out, ks_field_t in, int use_mfma,
+                               hipStream_t stream);
 
 /* Loss over npairs = B pairs (b_j, x_j), A_j x_j = b_j with A_j = sigma_j - D_eo D_oe on
  * lattice gauges[j] (b_j, x_j complex128 [Vh_j][3] device arrays, sigma host [npairs]): the

@@ -472,6 +472,7 @@ class Net:
         L.ks_net_get_weights.argtypes = [_vp, _vp]
         L.ks_net_free.argtypes = [_vp]
         L.ks_net_apply.argtypes = [_vp, _vp, _vp, _vp, C.c_int, _vp]
+        L.ks_net_apply_field.argtypes = [_vp, _vp, _vp, C.c_int, _vp]
         L.ks_net_loss_grad.argtypes = [_vp, C.c_int, C.POINTER(_vp), C.POINTER(C.c_double),
                                        C.POINTER(_vp), C.POINTER(_vp), C.POINTER(C.c_double),
                                        _vp, _vp]
@@ -501,6 +502,12 @@ class Net:
         _check(lib().ks_net_apply(self.handle, gauge.handle, _dev_vec(x, gauge.vh, "x"),
                                   _dev_vec(out, gauge.vh, "out"), int(bool(mfma)),
                                   _stream(stream)))
+        return out
+
+    def apply_field(self, inp: Field, out: Field, mfma: bool = False, stream=None):
+        """out = N(inp) on even-parity fields in the solver's storage (FP64 or FP32)."""
+        _check(lib().ks_net_apply_field(self.handle, out.handle, inp.handle, int(bool(mfma)),
+                                        _stream(stream)))
         return out
 
     @staticmethod

@@ -529,8 +529,26 @@ ks_status_t ks_net_apply(ks_net_t n, ks_gauge_t g, const double* in_dev, double*
     KS_API_BEGIN
     KS_REQUIRE(n && n->ctx && g && in_dev && out_dev, KS_ERR_ARG, "ks_net_apply: null argument");
     KS_REQUIRE(in_dev != out_dev, KS_ERR_ARG, "ks_net_apply: out aliases in");
-    if (use_mfma) net_apply_mfma(*n->ctx, g, in_dev, out_dev, 1.0, stream);
+    if (use_mfma) net_apply_mfma(*n->ctx, g, in_dev, out_dev, stream);
     else net_apply_f32(*n->ctx, g, in_dev, out_dev, 1.0, stream);
+    return KS_SUCCESS;
+    KS_API_END
+}
+
+ks_status_t ks_net_apply_field(ks_net_t n, ks_field_t out, ks_field_t in, int use_mfma,
+                               hipStream_t stream)
+{
+    KS_API_BEGIN
+    KS_REQUIRE(n && n->ctx && out && in, KS_ERR_ARG, "ks_net_apply_field: null argument");
+    KS_REQUIRE(out != in && out->data != in->data, KS_ERR_ARG,
+               "ks_net_apply_field: out aliases in");
+    KS_REQUIRE(out->g == in->g, KS_ERR_ARG, "ks_net_apply_field: fields of different lattices");
+    KS_REQUIRE(out->parity == KS_EVEN && in->parity == KS_EVEN, KS_ERR_ARG,
+               "ks_net_apply_field: the network maps even-parity fields");
+    KS_REQUIRE(out->prec == in->prec && (in->prec == KS_F64 || in->prec == KS_F32), KS_ERR_ARG,
+               "ks_net_apply_field: both fields KS_F64 or both KS_F32");
+    net_apply_spinor(*n->ctx, in->g, in->prec, in->data, out->data, nullptr, nullptr, use_mfma,
+                     stream);
     return KS_SUCCESS;
     KS_API_END
 }

@@ -513,13 +513,13 @@ ks_status_t fcg_core(ks_gauge_t g, NetCtx& net, double sigma, const double* b, d
     stats.restarts = fb_iters;        // steps taken by the fallback CG
     stats.fallback = reason;
     stats.true_rel_resid = std::sqrt(true_r2 / b2);
-    // per flexible step: the CG step's bytes, the network's layers on the full lattice, its
-    // input and output (r read, the full-lattice input written, z written) and the two dot
-    // products (z, r, q) and the p update (z, r, p read, p written)
+    // per flexible step: the CG step's bytes, one network application (with its input and
+    // output vectors) and the two dot products (z, r, q) and the p update (z, r, p read, p
+    // written)
     const double sb = (double)field_bytes(G, P) / vh;
     stats.model_bytes = (double)it * vh *
-                            (cg_iter_model_bytes(P, RC) + 2.0 * net_model_bytes_per_site(use_mfma) +
-                             sb + 48 + 24 + 3 * sb + 4 * sb) +
+                            (cg_iter_model_bytes(P, RC) + net_model_bytes(use_mfma, sb) + 3 * sb +
+                             4 * sb) +
                         (ru + restarts + 1) * (2 * dslash_model_bytes(KS_F64, KS_RECON_18) + 192) * vh;
     stats.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return rc;

@@ -23,7 +23,8 @@ struct NetBuffers {
     int vh = 0;
     float2* act[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     float2* grad[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-    __half* act16[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // MFMA path
+    // matrix-core path: levels 1..3 as binary16 records [parity][6][Vh] x 16 bytes
+    __half* act16[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     int npart = 0;
     double* part = nullptr;
     double* wpart = nullptr;
@@ -45,6 +46,7 @@ struct NetCtx {
     // MFMA operand cache
     __half* wmma = nullptr;
     unsigned wmma_version = ~0u;
+    float wmma_scale = 0.f;     // binary16 link scale folded into the operands
 };
 
 NetCtx* net_create(const double* w_host);
@@ -55,15 +57,16 @@ NetBuffers& net_buffers(NetCtx& n, const Geom& g);
 void net_forward(NetCtx& n, NetBuffers& B, ks_gauge_t g, hipStream_t s);
 void net_apply_f32(NetCtx& n, ks_gauge_t g, const double* in, double* out, double in_scale,
                    hipStream_t s);
-void net_apply_mfma(NetCtx& n, ks_gauge_t g, const double* in, double* out, double in_scale,
-                    hipStream_t s);
-void net_mfma_prepare(NetCtx& n, hipStream_t s);
-// algorithmic bytes of one network application per site of the full lattice: each layer reads
-// its site's 8 stored fat links once (FP32, or binary16 on the matrix-core path's three last
-// layers) and its input channels, and writes its output channels (FP32 complex colour vectors)
-double net_model_bytes_per_site(int use_mfma);
-void net_layer_mfma(NetCtx& n, ks_gauge_t g, const float2* in, float2* out, int which,
-                    const int* gate, hipStream_t s);
+// complex128 [Vh][3] even-site vectors, on the matrix-core path
+void net_apply_mfma(NetCtx& n, ks_gauge_t g, const double* in, double* out, hipStream_t s);
+// matrix-core operands of the four layers for the current weights and g's binary16 link scale
+void net_mfma_prepare(NetCtx& n, ks_gauge_t g, hipStream_t s);
+void net_apply_mfma_spinor(NetCtx& n, ks_gauge_t g, ks_prec_t prec, const void* r, void* z,
+                           const double* in_scale, const int* gate, hipStream_t s);
+// algorithmic bytes of one application per even site, the solver's vector taking vec_bytes
+// per even site (matrix-core path: per full-lattice site as net_mfma_model_bytes_per_site)
+double net_model_bytes(int use_mfma, double vec_bytes);
+double net_mfma_model_bytes_per_site(int vec_bytes);
 // N applied to an inner-precision field r (Spinor<prec> layout) into z, for the solver: the
 // input is multiplied by *in_scale (device) and the output divided by it; every launch does
 // nothing while *gate != 0.

@@ -401,7 +401,8 @@ __global__ void net_fold_kernel(const double2* __restrict__ g4, double2* __restr
     g[k] = make_double2(a.x + t.x, a.y - t.y);
 }
 
-// network input from an inner-precision field: even sites r * scale, odd sites zero
+// network input from an inner-precision field: even sites r * scale (scale null: 1), odd sites
+// zero
 template <int P>
 __global__ void net_embed_spinor_kernel(int vh, const void* __restrict__ r,
                                         const double* __restrict__ scale, float2* __restrict__ act,
@@ -410,7 +411,7 @@ __global__ void net_embed_spinor_kernel(int vh, const void* __restrict__ r,
     if (gate && *gate) return;
     const int h = blockIdx.x * blockDim.x + threadIdx.x;
     if (h >= vh) return;
-    const float sc = (float)*scale;
+    const float sc = scale ? (float)*scale : 1.f;
     cx<typename St<P>::R> v[3];
     Spinor<P>::load(r, vh, h, v);
 #pragma unroll
@@ -420,7 +421,8 @@ __global__ void net_embed_spinor_kernel(int vh, const void* __restrict__ r,
     }
 }
 
-// network output (even sites of the last layer) divided by scale into an inner-precision field
+// network output (even sites of the last layer) divided by scale (null: 1) into an
+// inner-precision field
 template <int P>
 __global__ void net_extract_spinor_kernel(int vh, const float2* __restrict__ act,
                                           const double* __restrict__ scale, void* __restrict__ z,
@@ -429,7 +431,7 @@ __global__ void net_extract_spinor_kernel(int vh, const float2* __restrict__ act
     if (gate && *gate) return;
     const int h = blockIdx.x * blockDim.x + threadIdx.x;
     if (h >= vh) return;
-    const float inv = (float)(1.0 / *scale);
+    const float inv = (float)(1.0 / (scale ? *scale : 1.0));
     using R = typename St<P>::R;
     cx<R> v[3];
 #pragma unroll
@@ -489,14 +491,15 @@ void wgrad(NetCtx& n, NetBuffers& B, ks_gauge_t g, const float2* in, const float
 
 const int kLayerIn[4] = {1, 8, 8, 8};
 
-double net_model_bytes_per_site(int use_mfma)
+double net_model_bytes(int use_mfma, double vec_bytes)
 {
+    if (use_mfma) return 2.0 * net_mfma_model_bytes_per_site(vec_bytes);
+    // per site of the full lattice each FP32 layer reads its site's eight stored links and
+    // its input channels and writes its output channels (FP32 complex colour vectors); the
+    // input is embedded on both parities and the output read back on the even sites
     double total = 0.0;
-    for (int l = 0; l < 4; ++l) {
-        const double links = (use_mfma && l > 0) ? 8 * 36 : 8 * 72;
-        total += links + 24.0 * (kLayerIn[l] + kLayerOut[l]);
-    }
-    return total;
+    for (int l = 0; l < 4; ++l) total += 8 * 72 + 24.0 * (kLayerIn[l] + kLayerOut[l]);
+    return 2.0 * total + vec_bytes + 2 * 24.0 + 24.0 + vec_bytes;
 }
 const int kLayerOut[4] = {8, 8, 8, 1};
 
@@ -532,6 +535,7 @@ void net_free(NetCtx* n)
         for (int l = 0; l < 5; ++l) {
             device_free(kv.second.act[l]);
             device_free(kv.second.grad[l]);
+            device_free(kv.second.act16[l]);
         }
         device_free(kv.second.part);
         device_free(kv.second.wpart);
@@ -615,38 +619,16 @@ void net_apply_f32(NetCtx& n, ks_gauge_t g, const double* in, double* out, doubl
     KS_HIP(hipGetLastError());
 }
 
-// Same, with the two 8 -> 8 layers' channel mixing on the matrix cores (FP16 operands, FP32
-// accumulation); the 1 -> 8 and 8 -> 1 layers keep the vector-ALU form.
-void net_apply_mfma(NetCtx& n, ks_gauge_t g, const double* in, double* out, double in_scale,
-                    hipStream_t s)
-{
-    gauge_prepare(g, KS_F32, KS_RECON_18, s);
-    gauge_prepare(g, KS_F16, KS_RECON_18, s);
-    net_mfma_prepare(n, s);
-    NetBuffers& B = net_buffers(n, g->geom);
-    const int vh = g->geom.Vh;
-    const float2* w = reinterpret_cast<const float2*>(n.w32);
-    net_embed_kernel<<<blocks_for(vh), kBlock, 0, s>>>(vh, reinterpret_cast<const double2*>(in),
-                                                       in_scale, B.act[0]);
-    layer<1, 8>(g, B.act[0], B.act[1], w + layer_weight_offset(0), s);
-    net_layer_mfma(n, g, B.act[1], B.act[2], 1, nullptr, s);
-    net_layer_mfma(n, g, B.act[2], B.act[3], 2, nullptr, s);
-    net_layer_mfma(n, g, B.act[3], B.act[4], 3, nullptr, s);
-    net_extract_kernel<<<blocks_for(vh), kBlock, 0, s>>>(vh, B.act[4], 1.0 / in_scale,
-                                                         reinterpret_cast<double2*>(out));
-    KS_HIP(hipGetLastError());
-}
-
 void net_apply_spinor(NetCtx& n, ks_gauge_t g, ks_prec_t prec, const void* r, void* z,
                       const double* in_scale, const int* gate, int use_mfma, hipStream_t s)
 {
     KS_REQUIRE(prec == KS_F64 || prec == KS_F32, KS_ERR_ARG,
                "network: the solver's vectors must be FP64 or FP32");
-    gauge_prepare(g, KS_F32, KS_RECON_18, s);
     if (use_mfma) {
-        gauge_prepare(g, KS_F16, KS_RECON_18, s);
-        net_mfma_prepare(n, s);
+        net_apply_mfma_spinor(n, g, prec, r, z, in_scale, gate, s);
+        return;
     }
+    gauge_prepare(g, KS_F32, KS_RECON_18, s);
     NetBuffers& B = net_buffers(n, g->geom);
     const int vh = g->geom.Vh;
     const int nb = blocks_for(vh);
@@ -656,15 +638,9 @@ void net_apply_spinor(NetCtx& n, ks_gauge_t g, ks_prec_t prec, const void* r, vo
     else
         net_embed_spinor_kernel<KS_F32><<<nb, kBlock, 0, s>>>(vh, r, in_scale, B.act[0], gate);
     layer<1, 8>(g, B.act[0], B.act[1], w + layer_weight_offset(0), s, gate);
-    if (use_mfma) {
-        net_layer_mfma(n, g, B.act[1], B.act[2], 1, gate, s);
-        net_layer_mfma(n, g, B.act[2], B.act[3], 2, gate, s);
-        net_layer_mfma(n, g, B.act[3], B.act[4], 3, gate, s);
-    } else {
-        layer<8, 8>(g, B.act[1], B.act[2], w + layer_weight_offset(1), s, gate);
-        layer<8, 8>(g, B.act[2], B.act[3], w + layer_weight_offset(2), s, gate);
-        layer<8, 1>(g, B.act[3], B.act[4], w + layer_weight_offset(3), s, gate);
-    }
+    layer<8, 8>(g, B.act[1], B.act[2], w + layer_weight_offset(1), s, gate);
+    layer<8, 8>(g, B.act[2], B.act[3], w + layer_weight_offset(2), s, gate);
+    layer<8, 1>(g, B.act[3], B.act[4], w + layer_weight_offset(3), s, gate);
     if (prec == KS_F64)
         net_extract_spinor_kernel<KS_F64><<<nb, kBlock, 0, s>>>(vh, B.act[4], in_scale, z, gate);
     else

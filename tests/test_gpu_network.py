@@ -6,9 +6,10 @@ Tolerances:
   output component within 2^-13 S of the oracle's, S the component's sum of product moduli
   (the oracle network run on |w|, |V| and |b|): four layers of FP32 sums of a few hundred
   terms each stay far inside it;
-* forward, matrix-core path (the three last layers' mixing operands rounded to binary16, unit
-  roundoff 2^-11 per operand, 72 terms per output adding in quadrature: a few 1e-4 per
-  layer): 3e-3 relative L2 and 2^-6 S per component;
+* forward, matrix-core path (every layer's input activations, stored links, transported
+  values and weights rounded to binary16, unit roundoff 2^-11 per operand, some 200 terms
+  per output adding in quadrature: about 5e-4 per layer): 3e-3 relative L2 and 2^-6 S per
+  component;
 * loss 1e-5 relative (the GPU takes x^+ A x as Re<x, b> and A (y - x) as A y - b, exact up to
   the pairs' FP64 solve tolerance); gradient 1e-4 relative L2 and every component within
   1e-4 of the largest (FP32 forward and backward passes, FP64 sums);
@@ -57,7 +58,10 @@ def modulus_sums(g, ws, b):
     return out.real
 
 
-@pytest.mark.parametrize("dims", [(4, 6, 4, 8), (8, 8, 8, 8), (6, 4, 4, 4), (16, 16, 16, 16)])
+# (6, 6, 6, 6): Vh = 648 is not a multiple of the 16 sites of a wave, so one wave holds sites
+# of both parities and the last block has lanes past the end
+@pytest.mark.parametrize("dims", [(4, 6, 4, 8), (8, 8, 8, 8), (6, 4, 4, 4), (6, 6, 6, 6),
+                                  (16, 16, 16, 16)])
 def test_forward_f32_and_mfma(ks, dims):
     announce("net forward", dims)
     import torch
@@ -76,6 +80,46 @@ def test_forward_f32_and_mfma(ks, dims):
         assert rel_l2(got, ref) <= l2, mfma
         assert np.all(np.abs(got.real - ref.real) <= rel * S), mfma
         assert np.all(np.abs(got.imag - ref.imag) <= rel * S), mfma
+    net.free()
+    G.free()
+
+
+@pytest.mark.parametrize("dims,prec", [((6, 6, 6, 6), "f64"), ((6, 6, 6, 6), "f32"),
+                                       ((16, 16, 16, 16), "f32")])
+def test_apply_field(ks, dims, prec):
+    """N applied to the solver's own FP64 / FP32 even-site fields (what the flexible CG calls
+    each step), both paths, every component against the oracle."""
+    announce("net apply field", dims, prec)
+    import torch
+    g = make_gauge(dims, 0.5, 79)
+    G = ks.Gauge(dims, g.fat, g.naik)
+    ws = random_net(5004)
+    net = ks.Net(flatten_weights(ws))
+    b = gaussian_source(g.volume // 2, 7)
+    if prec == "f32":
+        b = b.astype(np.complex64).astype(np.complex128)   # the field stores FP32
+    ref, _ = N.network_forward(N.Network(ws), g, b, keep_cache=False)
+    S = modulus_sums(g, ws, b)
+    fin = ks.Field(G, 0, ks.PREC[prec]).load(dev(b))
+    fout = ks.Field(G, 0, ks.PREC[prec])
+    out = zeros_dev(b.shape)
+    for mfma, rel in ((False, 2.0 ** -13), (True, 2.0 ** -6)):
+        net.apply_field(fin, fout, mfma=mfma)
+        fout.store(out)
+        torch.cuda.synchronize()
+        got = host(out)
+        assert np.all(np.abs(got.real - ref.real) <= rel * S), mfma
+        assert np.all(np.abs(got.imag - ref.imag) <= rel * S), mfma
+    with pytest.raises(ks.KSError):
+        net.apply_field(fin, fin)
+    odd = ks.Field(G, 1, ks.PREC[prec])
+    with pytest.raises(ks.KSError):
+        net.apply_field(fin, odd)
+    f16 = ks.Field(G, 0, ks.F16)
+    with pytest.raises(ks.KSError):
+        net.apply_field(f16, fout)
+    for f in (fin, fout, odd, f16):
+        f.free()
     net.free()
     G.free()
 
@@ -239,16 +283,18 @@ def test_fcg_identity_matches_cg(ks, lat, inner):
     assert abs(res.stats["iters"] - info.iters) <= 3
 
 
-@pytest.mark.parametrize("mfma", [False, True])
-def test_fcg_network_preconditioner(ks, lat, mfma):
-    """An untrained N = L^+ L is still positive: flexible CG never falls back."""
-    announce("fcg network", mfma)
+@pytest.mark.parametrize("mfma,inner", [(False, "f32"), (True, "f32"), (True, "f64")])
+def test_fcg_network_preconditioner(ks, lat, mfma, inner):
+    """An untrained N = L^+ L is still positive: flexible CG never falls back (the network
+    reads and writes the solver's FP32 or FP64 vectors)."""
+    announce("fcg network", mfma, inner)
     import torch
     G = ks.Gauge(lat.dims, lat.fat, lat.naik)
     net = ks.Net(flatten_weights(random_net(5000)))
     b = gaussian_source(lat.volume // 2, 56)
     x = zeros_dev(b.shape)
-    res = ks.fcg_solve(G, net, 0.05, dev(b), x, ks.default_params(tol=1e-10, inner=ks.F32),
+    res = ks.fcg_solve(G, net, 0.05, dev(b), x,
+                       ks.default_params(tol=1e-10, inner=ks.PREC[inner]),
                        mfma=mfma, raise_on_error=False)
     torch.cuda.synchronize()
     tr = float(np.linalg.norm(b - oracle.apply_A(lat, 0.01, host(x))) / np.linalg.norm(b))
