@@ -407,6 +407,73 @@ def sweep(args):
           flush=True)
 
 
+def counters_pass(N, ks, G, g, bd, fields, variants, gm, mb_h):
+    """One short pass over every hot kernel, for rocprofv3 counter runs (the calibration copy
+    first).  Prints the launch sizes the per-kernel byte models need."""
+    import numpy as np
+    import torch
+    from ksinputs import make_gauge, gaussian_source, flatten_weights, net_init_weights, SEEDS
+    vh = g.volume // 2
+    # a plain copy of known size (1 GiB read + 1 GiB written) calibrates the byte counters
+    src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    ks.stream_copy(dst, src)
+    torch.cuda.synchronize()
+    del src, dst
+    for v in variants:
+        ein, eout = fields[v[0]]
+        for _ in range(N):
+            ks.dslash_eo(G, eout, ein, v[1])
+    # FP32-inner CG on the 32^4 system: N fused steps (and the reliable updates among them)
+    x = torch.zeros_like(bd)
+    ks.cg_solve(G, MASS, bd, x, ks.default_params(tol=TOL, inner=ks.F32, max_iter=N),
+                raise_on_error=False)
+    # the network on the solver's FP32 fields, both paths
+    net = ks.Net(flatten_weights(net_init_weights(SEEDS["net_init"])))
+    nin, nout = ks.Field(G, ks.EVEN, ks.F32).load(bd), ks.Field(G, ks.EVEN, ks.F32)
+    for _ in range(N):
+        net.apply_field(nin, nout, mfma=True)
+        net.apply_field(nin, nout, mfma=False)
+    torch.cuda.synchronize()
+    del nin, nout, net
+    # link construction from the 32^4 thin links
+    thin_d = torch.from_numpy(np.ascontiguousarray(g.thin).reshape(-1)).cuda()
+    hf, hn = torch.empty_like(thin_d), torch.empty_like(thin_d)
+    ks.hisq_links(g.dims, thin_d, hf, hn)
+    torch.cuda.synchronize()
+    del thin_d, hf, hn
+    ks.hisq_release()
+    # 32^3 x 48: FP32-inner multi-shift, N shared steps, then the force from its iterates
+    GM = ks.Gauge(gm.dims, gm.fat, gm.naik)
+    GM.prepare(ks.F32, 18)
+    mb = torch.from_numpy(mb_h).cuda()
+    sig = 4 * np.geomspace(0.002, 0.5, 9) ** 2
+    xs = [torch.zeros_like(mb) for _ in sig]
+    ks.multishift_cg_solve(GM, sig, mb, xs, 1e-9, ks.default_params(inner=ks.F32, max_iter=N),
+                           raise_on_error=False)
+    fv = torch.empty(36 * gm.volume, dtype=torch.complex128, device="cuda")
+    fw = torch.empty_like(fv)
+    ks.force(GM, [1.0 / (i + 1) for i in range(len(sig))], xs, fv, fw)
+    torch.cuda.synchronize()
+    del GM, xs, fv, fw
+    # batch: 8 lattices of 16^4 x 4 right-hand sides, N steps
+    bdims = [(16, 16, 16, 16)] * 8
+    bg = [make_gauge(d, 0.4, SEEDS["batch_gauge"](j)) for j, d in enumerate(bdims)]
+    B = ks.Batch(bdims, [x_.fat for x_ in bg], [x_.naik for x_ in bg], 4, ks.F32)
+    bb = [torch.from_numpy(gaussian_source(x_.volume // 2, SEEDS["batch_rhs"](j, r))).cuda()
+          for j, x_ in enumerate(bg) for r in range(4)]
+    bx = [torch.zeros_like(v) for v in bb]
+    B.solve([0.05] * len(bdims), bb, bx, ks.default_params(tol=TOL, max_iter=N, check_every=8,
+                                                           delta=BATCH_DELTA),
+            raise_on_error=False)
+    torch.cuda.synchronize()
+    print(json.dumps({"counters": N, "sites_32x32x32x32": g.volume,
+                      "sites_32x32x32x48": gm.volume, "batch": "8 x 16^4 x 4 RHS",
+                      "copy_bytes": 2 * (1 << 27) * 8,
+                      "dslash_model_bytes": {"%s_r%d" % v: model_bytes_per_site(*v) * vh
+                                             for v in variants}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -419,9 +486,11 @@ def main():
                     help="learned48: the 48^3 x 64, m = 0.002 learned-preconditioner workload "
                          "(training pairs, training, flexible CG vs mixed CG); sweep: Dslash_eo "
                          "over lattice sizes and the oracle's host timings; each its own JSON line")
-    ap.add_argument("--dslash-only", type=int, default=0, metavar="N",
-                    help="counter runs: N launches of each Dslash_eo variant and one plain "
-                         "1 GiB device copy, then exit")
+    ap.add_argument("--counters", type=int, default=0, metavar="N",
+                    help="counter runs: one plain 1 GiB device copy (calibration), N launches "
+                         "of each tuned Dslash_eo variant, then N steps or launches of each "
+                         "other hot kernel (FP32 CG, network layers, 32^3x48 multi-shift and "
+                         "force, a 16^4 batch, link construction), then exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the solver has no multi-GPU path (the lattice is "
@@ -450,11 +519,11 @@ def main():
     mb_h = gaussian_source(gm.volume // 2, SEEDS["source"](3))
     log("32^4 and 32^3x48 inputs generated in %.1f s" % (time.time() - t0))
     g5 = blocks5 = None
-    if not args.dslash_only and not args.no_learned48:
+    if not args.counters and not args.no_learned48:
         g5, blocks5 = learned_inputs()
     # the oracle's own FP64 CG solution of the 32^4 system, on host threads meanwhile
     oracle_ref = None
-    if not args.dslash_only:
+    if not args.counters:
         import oracle
         ncpu = oracle.max_threads()
         oracle_ref = OracleSolve(g, 4 * MASS * MASS, b, 1e-12, max(1, ncpu - 4))
@@ -501,7 +570,7 @@ def main():
     # gathers through the caches vs staged in LDS: the best launch shape of each combination
     # per variant; the tuned configuration is restored afterwards
     link_study = {}
-    if not args.dslash_only:
+    if not args.counters:
         for v in variants:
             key = "%s_r%d" % v
             cfg = tuned[key]
@@ -529,20 +598,8 @@ def main():
             link_study[key] = row
         log("link access study: %s" % json.dumps(link_study))
 
-    if args.dslash_only:
-        # a plain copy of known size (1 GiB read + 1 GiB written) calibrates the byte counters
-        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
-        dst = torch.empty_like(src)
-        ks.stream_copy(dst, src)
-        for v in variants:
-            ein, eout = fields[v[0]]
-            for _ in range(args.dslash_only):
-                ks.dslash_eo(G, eout, ein, v[1])
-        torch.cuda.synchronize()
-        print(json.dumps({"dslash_only": args.dslash_only, "sites": vh,
-                          "copy_bytes": 2 * src.numel() * 8,
-                          "model_bytes": {"%s_r%d" % v: model_bytes_per_site(*v) * vh
-                                          for v in variants}}), flush=True)
+    if args.counters:
+        counters_pass(args.counters, ks, G, g, bd, fields, variants, gm, mb_h)
         return
 
     def burst(v, record):

@@ -158,13 +158,16 @@ __device__ __forceinline__ void link_pairs(const void* fat, int s, int vh, int h
     unsigned u[9];
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-        const uvec4 q = reinterpret_cast<const uvec4*>(sb + (size_t)j * 16 * vh)[h];
+        // streamed once per layer: non-temporal, so that they do not evict the activations,
+        // which the neighbours read again
+        const uvec4 q =
+            __builtin_nontemporal_load(reinterpret_cast<const uvec4*>(sb + (size_t)j * 16 * vh) + h);
         u[4 * j] = q.x;
         u[4 * j + 1] = q.y;
         u[4 * j + 2] = q.z;
         u[4 * j + 3] = q.w;
     }
-    u[8] = reinterpret_cast<const unsigned*>(sb + (size_t)2 * 16 * vh)[h];
+    u[8] = __builtin_nontemporal_load(reinterpret_cast<const unsigned*>(sb + (size_t)2 * 16 * vh) + h);
 #pragma unroll
     for (int e = 0; e < 9; ++e) {
         lr[e] = as_h2(u[e] ^ 0x80000000u);
