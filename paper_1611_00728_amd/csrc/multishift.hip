@@ -474,7 +474,13 @@ ks_status_t multishift_core(ks_gauge_t g, int nshift, const double* sigma, const
             const int n = (int)std::min<size_t>(4, need.size() - g0);
             const int R = n <= 2 ? 2 : 4;
             const int ri = R == 2 ? 1 : 2;
-            if (!w.ms_batch[ri]) w.ms_batch[ri] = batch_create_on(g, R, KS_F32, s);
+            if (!w.ms_batch[ri]) {
+                w.ms_batch[ri] = batch_create_on(g, R, KS_F32, s);
+                // 256-site tiles: one large lattice fills the device with them, and the
+                // update kernels' capped grid covers 4x the sites per wave (measured at
+                // 32^3x48, FP32: 0.441 -> 0.423 s for the whole solve)
+                w.ms_batch[ri]->set_tiles(2, s);
+            }
             KS_HIP(hipMemsetAsync(zero, 0, fb, s));
             std::vector<const double*> bp(R);
             std::vector<double*> xp(R);
