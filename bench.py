@@ -227,7 +227,9 @@ def config5(g5, blocks):
     the full lattice (FP64 CG solutions), 1000 Adam steps on the A-norm loss, then flexible CG
     with the network (matrix-core mixing) against FP32-inner CG with reliable updates and plain
     FP64 CG, all to FP64 true relative residual 1e-10, each solution's residual recomputed by
-    the FP64 oracle.  Returns the JSON row."""
+    the FP64 oracle; mixed and learned again on three more held-out sources.  Returns the JSON
+    row."""
+    import numpy as np
     import torch
     import paper_1611_00728_amd as ks
     from paper_1611_00728_amd import learn
@@ -291,6 +293,37 @@ def config5(g5, blocks):
         log("%s: %s" % (name, json.dumps(rows[name])))
     for name, x in xs.items():
         rows[name]["true_rel_resid_oracle"] = oracle_resid(g5, 4 * mass * mass, bh, x)
+    # three more held-out sources, mixed and learned, each judged by the oracle
+    held = {"sources": 4, "mixed_iters": [rows["mixed_f32_cg"]["iters"]],
+            "learned_iters": [rows["learned_fcg"]["iters"]],
+            "mixed_s": [rows["mixed_f32_cg"]["seconds"]],
+            "learned_s": [rows["learned_fcg"]["seconds"]], "learned_fallbacks": 0,
+            "max_true_rel_resid_oracle": max(rows[k]["true_rel_resid_oracle"]
+                                             for k in ("mixed_f32_cg", "learned_fcg"))}
+    for r in range(3):
+        hb = gaussian_source(vh, SEEDS["source"](5) + 100 + r)
+        hd = torch.from_numpy(hb).cuda()
+        for key, fn in (("mixed", lambda x: ks.cg_solve(
+                            G, mass, hd, x, ks.default_params(tol=tol, inner=ks.F32))),
+                        ("learned", lambda x: ks.fcg_solve(
+                            G, net, mass, hd, x, ks.default_params(tol=tol, inner=ks.F32),
+                            mfma=True))):
+            x = torch.zeros_like(hd)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            res = fn(x)
+            torch.cuda.synchronize()
+            held[key + "_s"].append(time.perf_counter() - t)
+            held[key + "_iters"].append(res.stats["iters"])
+            if key == "learned" and res.stats["fallback"]:
+                held["learned_fallbacks"] += 1
+            held["max_true_rel_resid_oracle"] = max(held["max_true_rel_resid_oracle"],
+                                                    oracle_resid(g5, 4 * mass * mass, hb, x))
+    held["iteration_ratio_mean"] = float(np.mean(np.array(held["learned_iters"]) /
+                                                 np.array(held["mixed_iters"])))
+    held["time_ratio_mean"] = float(np.mean(np.array(held["learned_s"]) /
+                                            np.array(held["mixed_s"])))
+    log("held-out sources: %s" % json.dumps(held))
     tm, tl = rows["mixed_f32_cg"]["seconds"], rows["learned_fcg"]["seconds"]
     im, il = rows["mixed_f32_cg"]["iters"], rows["learned_fcg"]["iters"]
     net.free()
@@ -304,6 +337,7 @@ def config5(g5, blocks):
                      "adam_steps": steps, "batch": batch, "lr": lr, "training_s": t_train,
                      "loss": "A-norm error relative to the solution's",
                      "loss_first": float(hist[0]), "loss_last": float(hist[-1])},
+        "held_out_sources": held,
         "learned_vs_mixed_iterations": il / im,
         "learned_vs_mixed_speedup": tm / tl,
         "break_even_solves": ((t_gen + t_train) / (tm - tl)) if tl < tm else None,
