@@ -55,6 +55,13 @@ def model_bytes_per_site(prec: str, recon: int) -> int:
 # 4 x 24 of p), the x/r update (p, q, r read, r written: 4 x 4 x 24; x's FP32 increments read
 # and written: 2 x 4 x 24) and p = r + beta p (3 x 4 x 24)
 BATCH_STEP_BYTES = 1344 + 1440 + 576 + 288
+# the same with binary16 links and vectors (16-byte records per site and right-hand side; x's
+# increments stay FP32): hopping terms 576 + 4 x 16 in + 4 x 16 out (+ 4 x 16 p), the update
+# 3 x 4 x 16 read, 4 x 16 written, 2 x 4 x 24 increments, p = r + beta p 3 x 4 x 16
+BATCH_STEP_BYTES_F16 = 704 + 768 + 448 + 192
+# binary16 inner iterations take reliable updates at a 33-fold drop (at 0.01 the binary16
+# recursion needs more steps, at 0.1 more updates)
+BATCH_DELTA_F16 = 0.03
 # reliable-update threshold of the batch: its updates are lattice-synchronous FP64 multi-RHS
 # A-applies (the fastest of a lattice's four residuals sets their rate), so it takes them at a
 # 100-fold drop; the FP32 recursion keeps the same step counts there (single-mass CG keeps 0.1)
@@ -88,13 +95,13 @@ HISQ_BYTES_PER_SITE = 3 * 576
 FP64_PEAK_TFLOPS = 78.6
 
 
-def batch_model_bytes(stats, vhs, nrhs=4):
+def batch_model_bytes(stats, vhs, nrhs=4, step_bytes=BATCH_STEP_BYTES):
     """Algorithmic bytes of one batched solve: a lattice takes CG steps while any of its
     right-hand sides iterates, and reliable updates while any is due."""
     total = 0.0
     for l, vh in enumerate(vhs):
         st = stats[l * nrhs:(l + 1) * nrhs]
-        total += vh * (max(x["iters"] for x in st) * BATCH_STEP_BYTES +
+        total += vh * (max(x["iters"] for x in st) * step_bytes +
                        max(x["reliable_updates"] for x in st) * BATCH_RU_BYTES)
     return total
 
@@ -661,20 +668,26 @@ def main():
     bx = [torch.zeros_like(v) for v in bb]
     bvh = [x.volume // 2 for x in bg]
     batch_cfg = B.tune()
-    log("batch of %d lattices x 4 RHS ready in %.1f s, schedule %s"
-        % (len(bdims), time.time() - t1, json.dumps(batch_cfg)))
-    batch_runs = []
+    # the same batch with binary16 inner iterations
+    B16 = ks.Batch(bdims, [x.fat for x in bg], [x.naik for x in bg], 4, ks.F16)
+    batch16_cfg = B16.tune()
+    bx16 = [torch.zeros_like(v) for v in bb]
+    log("batch of %d lattices x 4 RHS ready in %.1f s, schedule %s, binary16 %s"
+        % (len(bdims), time.time() - t1, json.dumps(batch_cfg), json.dumps(batch16_cfg)))
+    batch_runs, batch16_runs = [], []
 
     def batch_solve(record):
-        for v in bx:
-            v.zero_()
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        rc, st = B.solve(bmass, bb, bx, ks.default_params(tol=TOL, check_every=8,
-                                                          delta=BATCH_DELTA))
-        torch.cuda.synchronize()
-        if record:
-            batch_runs.append((time.perf_counter() - t, st))
+        for B_, xs_, delta_, runs_ in ((B, bx, BATCH_DELTA, batch_runs),
+                                       (B16, bx16, BATCH_DELTA_F16, batch16_runs)):
+            for v in xs_:
+                v.zero_()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            rc, st = B_.solve(bmass, bb, xs_, ks.default_params(tol=TOL, check_every=8,
+                                                                delta=delta_))
+            torch.cuda.synchronize()
+            if record:
+                runs_.append((time.perf_counter() - t, st))
 
     # multi-shift workload: 32^3 x 48, nine shifts sigma_i = 4 m_i^2, m_i log-spaced 0.002..0.5
     t1 = time.time()
@@ -855,6 +868,8 @@ def main():
               for name, xs in ms_last.items()}
     batch_orc = [oracle_resid(bg[p_ // 4], 4 * bmass[p_ // 4] ** 2, bb_h[p_], bx[p_])
                  for p_ in range(len(bb))]
+    batch16_orc = [oracle_resid(bg[p_ // 4], 4 * bmass[p_ // 4] ** 2, bb_h[p_], bx16[p_])
+                   for p_ in range(len(bb))]
     log("oracle residuals of every solution in %.1f s (32^4 oracle CG: %d steps, %.1f s on %d "
         "threads)" % (time.time() - t_or, info_or.iters, oracle_ref.seconds, oracle_ref.threads))
 
@@ -916,6 +931,23 @@ def main():
              "iters_range": [min(x["iters"] for _, st in batch_runs for x in st),
                              max(x["iters"] for _, st in batch_runs for x in st)],
              "schedule": batch_cfg}
+    walls16 = [w for w, _ in batch16_runs]
+    per16 = [x["seconds"] for _, st in batch16_runs for x in st]
+    batch["binary16_inner"] = {
+        "inner": "binary16 links and vectors (FP32 arithmetic) + FP64 reliable updates",
+        "reliable_update_delta": BATCH_DELTA_F16,
+        "wall_seconds": float(np.median(walls16)),
+        "solves_per_second": len(bb) / float(np.median(walls16)),
+        "p50_seconds_per_solve": float(np.percentile(per16, 50)),
+        "p99_seconds_per_solve": float(np.percentile(per16, 99)),
+        "max_true_rel_resid_gpu": max(x["true_rel_resid"] for _, st in batch16_runs for x in st),
+        "max_true_rel_resid_oracle": max(batch16_orc),
+        "model_GBps": batch_model_bytes(batch16_runs[-1][1], bvh,
+                                        step_bytes=BATCH_STEP_BYTES_F16) /
+                      float(np.median(walls16)) / 1e9,
+        "iters_range": [min(x["iters"] for _, st in batch16_runs for x in st),
+                        max(x["iters"] for _, st in batch16_runs for x in st)],
+        "schedule": batch16_cfg}
 
     msr = {}
     for name, rs in ms_runs.items():

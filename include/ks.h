@@ -312,9 +312,11 @@ typedef struct {
 /* nlat lattices; dims: nlat x 4 extents (each even, >= 4); fat[l], naik[l]: the links of
  * lattice l in the layout of ks_gauge_load, host (on_device = 0) or device memory; nrhs: 1, 2
  * or 4 right-hand sides per lattice; inner: KS_F32 (FP32 inner iterations, FP64 reliable
- * updates) or KS_F64.  Links are held in the library's per-lattice stores; vectors in arenas
- * that keep the nrhs values of a site and colour adjacent, so one link load serves all of
- * them.  Synchronises the stream. */
+ * updates), KS_F16 (binary16 links and vectors with an FP32 scale per site and right-hand
+ * side, FP32 arithmetic, the solution's increments in FP32, FP64 reliable updates) or KS_F64.
+ * Links are held in the library's per-lattice stores; vectors in arenas that keep the nrhs
+ * values of a site adjacent, so one link load serves all of them.  Synchronises the
+ * stream. */
 ks_status_t ks_batch_create(ks_batch_t* out, int nlat, const int* dims, const double* const* fat,
                             const double* const* naik, int on_device, int nrhs, ks_prec_t inner,
                             hipStream_t stream);

@@ -1,9 +1,9 @@
 // Batched CG: many independent lattices of uneven sizes, each with R right-hand sides, solved
 // together.  One launch of each step covers every (lattice, site tile) of the batch through a
 // tile table; the multi-RHS Dslash loads each link once and applies it to all R vectors of
-// the site.  Every (lattice, RHS) pair keeps its own CG scalars on the device, with FP32 (or
-// FP64) inner iterations, FP64 solution accumulation (through FP32 increments added in at
-// each reliable update when the inner iterations are FP32) and per-pair FP64 reliable updates
+// the site.  Every (lattice, RHS) pair keeps its own CG scalars on the device, with FP32,
+// binary16 or FP64 inner iterations, FP64 solution accumulation (through FP32 increments added
+// in at each reliable update in reduced precision) and per-pair FP64 reliable updates
 // decided on the device, so a fixed sequence of kernels makes up one step and a run of steps
 // is captured once into a HIP graph and replayed until every pair has converged.
 #include <algorithm>
@@ -61,6 +61,8 @@ struct MVec {
             }
         }
     }
+    // v as it reads back after a store (no rounding at FP32 and FP64)
+    __device__ static __forceinline__ void round(cx<T>[3][R]) {}
     __device__ static __forceinline__ void store(char* base, size_t vec_off, int vh, int h,
                                                  const cx<T> v[3][R])
     {
@@ -81,6 +83,64 @@ struct MVec {
                         reinterpret_cast<float2*>(p)[r] = make_float2(v[k][r].r, v[k][r].i);
                 }
             }
+        }
+    }
+};
+
+// binary16 inner vectors: one 16-byte record per (site, RHS), {FP32 scale n, 3 x half2}, value
+// = n * half (n = the largest real of the record, as a single-RHS binary16 field stores a site),
+// the R records of a site adjacent: [Vh_l][R] from record offset vec_off_l * R.
+template <int R>
+struct MVec<KS_F16, R> {
+    using T = float;
+    __device__ static __forceinline__ const uint4* rec(const char* base, size_t vec_off, int h)
+    {
+        return reinterpret_cast<const uint4*>(base) + (vec_off + (size_t)h) * R;
+    }
+    __device__ static __forceinline__ void load(const char* base, size_t vec_off, int vh, int h,
+                                                cx<T> v[3][R])
+    {
+        const uint4* p = rec(base, vec_off, h);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint4 q = p[r];
+            const float n = __uint_as_float(q.x);
+            const float2 a = unpack_half2(q.y), b = unpack_half2(q.z), c = unpack_half2(q.w);
+            v[0][r] = {n * a.x, n * a.y};
+            v[1][r] = {n * b.x, n * b.y};
+            v[2][r] = {n * c.x, n * c.y};
+        }
+    }
+    __device__ static __forceinline__ void store(char* base, size_t vec_off, int vh, int h,
+                                                 const cx<T> v[3][R])
+    {
+        uint4* p = const_cast<uint4*>(rec(base, vec_off, h));
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            float n = 0.f;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) n = fmaxf(n, fmaxf(fabsf(v[k][r].r), fabsf(v[k][r].i)));
+            uint4 q;
+            q.x = __float_as_uint(n);
+            if (n > 0.f) {
+                q.y = pack_half2(v[0][r].r / n, v[0][r].i / n);
+                q.z = pack_half2(v[1][r].r / n, v[1][r].i / n);
+                q.w = pack_half2(v[2][r].r / n, v[2][r].i / n);
+            } else {
+                q.y = q.z = q.w = 0u;
+            }
+            p[r] = q;
+        }
+    }
+    // v replaced by the values its records decode to
+    __device__ static __forceinline__ void round(cx<T> v[3][R])
+    {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            cx<T> s[3] = {v[0][r], v[1][r], v[2][r]};
+            Spinor<KS_F16>::round(s);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) v[k][r] = s[k];
         }
     }
 };
@@ -136,6 +196,11 @@ __device__ __forceinline__ void hop_site(const LatDesc& L, int par, int h, const
         cx<T> m[9];
         if (s < 8) load_link<PP, 9>(fat, s, vh, h, m);
         else load_link<PP, 9>(naik, s - 8, vh, h, m);
+        if constexpr (PP == KS_F16) {   // binary16 stores hold link / scale
+            const float sc = s < 8 ? L.fat_scale : L.naik_scale;
+#pragma unroll
+            for (int e = 0; e < 9; ++e) m[e] = {sc * m[e].r, sc * m[e].i};
+        }
         cx<T> v[3][R];
         V::load(in, L.vec_off, vh, nb[s], v);
 #pragma unroll
@@ -274,6 +339,8 @@ __global__ __launch_bounds__(NT) void batch_update_kernel(
 {
     using T = typename St<P>::R;
     using MV = MVec<P, R>;
+    // x itself (FP64), or its FP32 increments in reduced precision
+    using XV = MVec<P == KS_F64 ? KS_F64 : KS_F32, R>;
     int cached = -1;           // the lattice whose totals tot holds (the grid strides over the
     double tot[4];             // tiles, so a block's tiles mostly share a lattice)
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
@@ -319,7 +386,7 @@ __global__ __launch_bounds__(NT) void batch_update_kernel(
                 MV::load(p, L.vec_off, vh, h, pv);
                 MV::load(q, L.vec_off, vh, h, qv);
                 MV::load(r, L.vec_off, vh, h, rv);
-                MV::load(x, L.vec_off, vh, h, xv);
+                XV::load(x, L.vec_off, vh, h, xv);
 #pragma unroll
                 for (int k = 0; k < R; ++k) {
                     // a finished pair keeps x and r: its direction is no longer maintained
@@ -331,11 +398,18 @@ __global__ __launch_bounds__(NT) void batch_update_kernel(
                         xv[c][k].i = fma(af, pv[c][k].i, xv[c][k].i);
                         rv[c][k].r = fma(-af, qv[c][k].r, rv[c][k].r);
                         rv[c][k].i = fma(-af, qv[c][k].i, rv[c][k].i);
-                        nrm[k] += (double)rv[c][k].r * rv[c][k].r + (double)rv[c][k].i * rv[c][k].i;
                     }
                 }
-                MV::store(x, L.vec_off, vh, h, xv);
+                XV::store(x, L.vec_off, vh, h, xv);
                 MV::store(r, L.vec_off, vh, h, rv);
+                MV::round(rv);   // |r|^2 of r as stored
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    if (!go[k]) continue;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+                        nrm[k] += (double)rv[c][k].r * rv[c][k].r + (double)rv[c][k].i * rv[c][k].i;
+                }
             }
 #pragma unroll
             for (int k = 0; k < R; ++k) {
@@ -465,7 +539,7 @@ __global__ __launch_bounds__(NT) void batch_direction_kernel(
         const int h = tl.y + threadIdx.x;
         if (h < vh) {
             if (any_due) {
-                if (P == KS_F32 && dx) {
+                if (P != KS_F64 && dx) {
                     cx<double> xv[3][R];
                     cx<float> dv[3][R], zero[3][R];
                     MVec<KS_F64, R>::load(x64, L.vec_off, vh, h, xv);
@@ -677,6 +751,9 @@ struct BatchLaunch {
         if (c.prec == KS_F64) {
             if (xpay) KS_BH(KS_F64, true);
             else KS_BH(KS_F64, false);
+        } else if (c.prec == KS_F16) {
+            if (xpay) KS_BH(KS_F16, true);
+            else KS_BH(KS_F16, false);
         } else {
             if (xpay) KS_BH(KS_F32, true);
             else KS_BH(KS_F32, false);
@@ -700,6 +777,13 @@ struct BatchLaunch {
                                                                  c.partials, c.partials2);
             batch_direction_kernel<KS_F64, R, NT><<<ug, NT, 0, s>>>(c.lats_dev, tl, nt, c.rs,
                                                                     c.ps, c.x64, nullptr, c.pairs,
+                                                                    c.partials2);
+        } else if (c.prec == KS_F16) {
+            batch_update_kernel<KS_F16, R, NT><<<ug, NT, 0, s>>>(c.lats_dev, tl, nt, c.dx32, c.ps,
+                                                                 c.qs, c.rs, c.r64, c.pairs,
+                                                                 c.partials, c.partials2);
+            batch_direction_kernel<KS_F16, R, NT><<<ug, NT, 0, s>>>(c.lats_dev, tl, nt, c.rs,
+                                                                    c.ps, c.x64, c.dx32, c.pairs,
                                                                     c.partials2);
         } else {
             batch_update_kernel<KS_F32, R, NT><<<ug, NT, 0, s>>>(c.lats_dev, tl, nt, c.dx32, c.ps,
@@ -808,6 +892,8 @@ static void batch_setup(BatchCtx* c, hipStream_t s)
             L.fat32[par] = g->store[inner][0].fat[par];
             L.naik32[par] = g->store[inner][0].naik[par];
         }
+        L.fat_scale = g->store[inner][0].fat_scale;
+        L.naik_scale = g->store[inner][0].naik_scale;
         L.vec_off = vec_off;
         L.pair0 = l * nrhs;
         vec_off += (size_t)g->geom.Vh;
@@ -852,7 +938,7 @@ static void batch_setup(BatchCtx* c, hipStream_t s)
     c->r64 = static_cast<char*>(device_alloc(nrec * 16));
     c->t64 = static_cast<char*>(device_alloc(nrec * 16));
     c->ax64 = static_cast<char*>(device_alloc(nrec * 16));
-    if (inner == KS_F32) {
+    if (inner != KS_F64) {
         c->dx32_bytes = nrec * 8;
         c->dx32 = static_cast<char*>(device_alloc(c->dx32_bytes));
     }
@@ -867,7 +953,8 @@ static void batch_setup(BatchCtx* c, hipStream_t s)
 static BatchCtx* batch_new(int nrhs, ks_prec_t inner)
 {
     KS_REQUIRE(nrhs == 1 || nrhs == 2 || nrhs == 4, KS_ERR_ARG, "batch: nrhs must be 1, 2 or 4");
-    KS_REQUIRE(inner == KS_F64 || inner == KS_F32, KS_ERR_ARG, "batch: inner precision F64 or F32");
+    KS_REQUIRE(inner == KS_F64 || inner == KS_F32 || inner == KS_F16, KS_ERR_ARG,
+               "batch: inner precision F64, F32 or F16");
     BatchCtx* c = new BatchCtx();
     c->nrhs = nrhs;
     c->prec = inner;

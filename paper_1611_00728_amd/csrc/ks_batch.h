@@ -12,6 +12,7 @@ struct LatDesc {
     Geom g;
     const void* fat32[2];     // inner-precision link planes per output parity
     const void* naik32[2];
+    float fat_scale, naik_scale;   // value = stored * scale (binary16 stores; 1 otherwise)
     const void* fat64[2];     // FP64 link planes (reliable updates)
     const void* naik64[2];
     size_t vec_off;           // site offset of this lattice in every vector arena

@@ -48,7 +48,8 @@ def run_batch(ks, B, gs, masses, nrhs, tol=1e-10, **kw):
     return rc, st, bh, [host(x) for x in xs]
 
 
-@pytest.mark.parametrize("nrhs,inner", [(4, "f32"), (2, "f32"), (1, "f32"), (1, "f64"), (4, "f64")])
+@pytest.mark.parametrize("nrhs,inner", [(4, "f32"), (2, "f32"), (1, "f32"), (1, "f64"), (4, "f64"),
+                                        (4, "f16"), (2, "f16"), (1, "f16")])
 def test_batch_pairs_converge(ks, fields, nrhs, inner):
     announce("batch", nrhs, inner)
     gs, masses = fields
@@ -63,7 +64,7 @@ def test_batch_pairs_converge(ks, fields, nrhs, inner):
         assert tr <= 1e-10, (p, tr)
         assert st[p]["status"] == 0 and st[p]["seconds"] > 0
         assert abs(st[p]["true_rel_resid"] - tr) <= 1e-3 * tr + 1e-15
-        if inner == "f32":
+        if inner in ("f32", "f16"):
             assert st[p]["reliable_updates"] >= 1
     # each pair agrees with an independent oracle solve
     for p in (0, len(bh) - 1):
@@ -112,13 +113,15 @@ def test_batch_matches_single_solves(ks, fields):
     B.free()
 
 
-def test_batch_runs_are_bit_identical(ks, fields):
-    """Two solves of the same batch (FP32 inner, per-lattice reliable updates) return the same
-    x bit for bit and the same step counts: the reductions have a fixed order and the
-    reliable-update kernel's spread of work over the grid does not change any sum."""
-    announce("batch repeatability")
+@pytest.mark.parametrize("inner", ["f32", "f16"])
+def test_batch_runs_are_bit_identical(ks, fields, inner):
+    """Two solves of the same batch (reduced-precision inner, per-lattice reliable updates)
+    return the same x bit for bit and the same step counts: the reductions have a fixed order
+    and the reliable-update kernel's spread of work over the grid does not change any sum."""
+    announce("batch repeatability", inner)
     gs, masses = fields
-    B = ks.Batch([g.dims for g in gs], [g.fat for g in gs], [g.naik for g in gs], 4, ks.F32)
+    B = ks.Batch([g.dims for g in gs], [g.fat for g in gs], [g.naik for g in gs], 4,
+                 ks.PREC[inner])
     rc1, st1, _, x1 = run_batch(ks, B, gs, masses, 4, check_every=4)
     rc2, st2, _, x2 = run_batch(ks, B, gs, masses, 4, check_every=4)
     assert rc1 == 0 and rc2 == 0
