@@ -24,7 +24,6 @@ namespace ks {
 namespace {
 
 constexpr int kMaxShift = 32;
-constexpr int kFinish = 1024;
 
 struct MSState {
     double rho, alpha, alpha_prev, beta, beta_prev, pAp;
@@ -32,8 +31,14 @@ struct MSState {
     int iter, max_iter, gate, stop_next, status, nactive, nshift, ru_pending, base;
     double delta[kMaxShift], stop2[kMaxShift];
     double zeta[kMaxShift], zeta_prev[kMaxShift];
-    double alpha_i[kMaxShift], beta_i[kMaxShift];
+    double alpha_i[kMaxShift];
     int active[kMaxShift], upd[kMaxShift];
+    // taken by the residual kernel's lead for the update kernel, whose own lead rewrites the
+    // live fields while its other blocks still read these: rho, the step's gate and count,
+    // zeta_i before and after the step
+    double s_rho;
+    int s_gate, s_iter;
+    double s_zeta[kMaxShift], s_zn[kMaxShift];
 };
 
 struct ShiftPtrs {
@@ -43,57 +48,75 @@ struct ShiftPtrs {
     int base;              // index of the smallest shift, whose system is the base system
 };
 
-__device__ __forceinline__ double finish_sum(const double* in, int n)
+// Every block adds up the previous kernel's partial sums itself (thread t adds t, t + NT, ...,
+// then the fixed block tree), so all blocks hold the same total bit for bit.
+template <int NT>
+__device__ __forceinline__ double block_total(const double* __restrict__ in, int n)
 {
-    double s = 0.0;
-    for (int k = threadIdx.x; k < n; k += kFinish) s += in[k];
-    return block_sum<kFinish>(s);
+    __shared__ double total;
+    double t = 0.0;
+    for (int k = threadIdx.x; k < n; k += NT) t += in[k];
+    t = block_sum<NT>(t);
+    if (threadIdx.x == 0) total = t;
+    __syncthreads();
+    return total;
 }
 
-__global__ __launch_bounds__(kFinish) void ms_alpha_kernel(const double* __restrict__ part, int n,
-                                                           MSState* __restrict__ st)
-{
-    if (st->gate) return;
-    if (st->stop_next || st->ru_pending) {
-        // finished, or the host recomputes the base residual before the next step
-        if (threadIdx.x == 0) st->gate = 1;
-        return;
-    }
-    const double pap = finish_sum(part, n);
-    if (threadIdx.x != 0) return;
-    st->pAp = pap;
-    if (!isfinite(pap) || !(pap > 0.0)) {
-        st->status = isfinite(pap) ? KS_ERR_BREAKDOWN : KS_ERR_NONFINITE;
-        st->gate = 1;
-        return;
-    }
-    const double a = st->rho / pap;
-    st->alpha = a;
-    for (int i = 0; i < st->nshift; ++i) {
-        // the base shift's solution keeps being updated while any shift iterates: the base
-        // reliable update recomputes r from it, and every shifted residual is zeta_i r
-        st->upd[i] = st->active[i] || i == st->base;
-        if (!st->upd[i]) continue;
-        const double z = st->zeta[i], zp = st->zeta_prev[i];
-        const double zn = z * zp * st->alpha_prev /
-                          (a * st->beta_prev * (zp - z) + zp * st->alpha_prev * (1.0 + st->delta[i] * a));
-        st->alpha_i[i] = a * zn / z;
-        st->beta_i[i] = zn;   // holds zeta' until the beta step
-    }
-}
-
-// r -= alpha q; partial sums of |r|^2 as stored
+// alpha = rho / <p, A p> from the hopping term's partials, r -= alpha q, partials of |r|^2 as
+// stored.  The lead thread alone writes the state: per shift the step's zeta', alpha_i and
+// whether the shift is updated, and the copies that the update kernel decides from.
 template <int P>
-__global__ __launch_bounds__(kBlock) void ms_r_kernel(int vh, const void* __restrict__ q,
-                                                      void* __restrict__ r,
-                                                      const MSState* __restrict__ st,
-                                                      double* __restrict__ partials)
+__global__ __launch_bounds__(kCgFuse) void ms_r_kernel(int vh, const void* __restrict__ q,
+                                                       void* __restrict__ r,
+                                                       MSState* __restrict__ st,
+                                                       const double* __restrict__ pap_part,
+                                                       int npap, double* __restrict__ rr_part)
 {
     using R = typename St<P>::R;
-    if (st->gate) return;
-    const R a = (R)st->alpha;
-    const int h = blockIdx.x * blockDim.x + threadIdx.x;
-    double s = 0.0;
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    // one read of the gate per block: only this kernel's lead can set it (on breakdown), and
+    // a block that sees that skips the step as the breakdown test would
+    __shared__ int gated;
+    if (threadIdx.x == 0) gated = st->gate;
+    __syncthreads();
+    if (gated) {
+        if (lead) st->s_gate = 1;
+        return;
+    }
+    const double pap = block_total<kCgFuse>(pap_part, npap);
+    const double rho = st->rho;
+    const bool ok = isfinite(pap) && pap > 0.0;
+    if (lead) {
+        st->pAp = pap;
+        st->s_gate = ok ? 0 : 1;
+        if (!ok) {
+            st->status = isfinite(pap) ? KS_ERR_BREAKDOWN : KS_ERR_NONFINITE;
+            st->gate = 1;
+        } else {
+            const double a = rho / pap;
+            st->alpha = a;
+            st->s_rho = rho;
+            st->s_iter = st->iter;
+            for (int i = 0; i < st->nshift; ++i) {
+                // the base shift's solution keeps being updated while any shift iterates: the
+                // base reliable update recomputes r from it, and every shifted residual is
+                // zeta_i r
+                st->upd[i] = st->active[i] || i == st->base;
+                if (!st->upd[i]) continue;
+                const double z = st->zeta[i], zp = st->zeta_prev[i];
+                const double zn =
+                    z * zp * st->alpha_prev /
+                    (a * st->beta_prev * (zp - z) + zp * st->alpha_prev * (1.0 + st->delta[i] * a));
+                st->alpha_i[i] = a * zn / z;
+                st->s_zeta[i] = z;
+                st->s_zn[i] = zn;
+            }
+        }
+    }
+    if (!ok) return;
+    const R a = (R)(rho / pap);
+    const int h = blockIdx.x * kCgFuse + threadIdx.x;
+    double sum = 0.0;
     if (h < vh) {
         cx<R> qv[3], rv[3];
         Spinor<P>::load(q, vh, h, qv);
@@ -107,46 +130,10 @@ __global__ __launch_bounds__(kBlock) void ms_r_kernel(int vh, const void* __rest
         Spinor<P>::round(rv);
 #pragma unroll
         for (int k = 0; k < 3; ++k)
-            s += (double)rv[k].r * (double)rv[k].r + (double)rv[k].i * (double)rv[k].i;
+            sum += (double)rv[k].r * (double)rv[k].r + (double)rv[k].i * (double)rv[k].i;
     }
-    s = block_sum<kBlock>(s);
-    if (threadIdx.x == 0) partials[blockIdx.x] = s;
-}
-
-__global__ __launch_bounds__(kFinish) void ms_beta_kernel(const double* __restrict__ part, int n,
-                                                          MSState* __restrict__ st)
-{
-    if (st->gate) return;
-    const double rn = finish_sum(part, n);
-    if (threadIdx.x != 0) return;
-    if (!isfinite(rn)) {
-        st->status = KS_ERR_NONFINITE;
-        st->gate = 1;
-        return;
-    }
-    const double b = rn / st->rho;
-    st->beta = b;
-    st->iter += 1;
-    for (int i = 0; i < st->nshift; ++i) {
-        if (!st->upd[i]) continue;
-        const double zn = st->beta_i[i];
-        const double ratio = zn / st->zeta[i];
-        st->beta_i[i] = b * ratio * ratio;
-        st->zeta_prev[i] = st->zeta[i];
-        st->zeta[i] = zn;
-        if (st->active[i] && zn * zn * rn <= st->stop2[i]) {
-            st->active[i] = 0;
-            st->nactive -= 1;
-        }
-    }
-    st->alpha_prev = st->alpha;
-    st->beta_prev = b;
-    st->rho = rn;
-    if (st->nactive == 0 || st->iter >= st->max_iter) st->stop_next = 1;
-    // reliable update of the base residual when it fell by ru_delta since the last one
-    const double s = sqrt(rn);
-    if (st->ru_delta > 0.0 && s < st->ru_delta * st->maxr) st->ru_pending = 1;
-    st->maxr = fmax(st->maxr, s);
+    sum = block_sum<kCgFuse>(sum);
+    if (threadIdx.x == 0) rr_part[blockIdx.x] = sum;
 }
 
 // x_i += alpha_i p_i; p_i = zeta_i r + beta_i p_i for every shift updated this step, and the
@@ -159,30 +146,86 @@ __global__ __launch_bounds__(kFinish) void ms_beta_kernel(const double* __restri
 // read-modify-write).  The shifts' own vectors (x_i or its increments, p_i) are touched once
 // per step: read and written streamed, they do not push the base direction p, which the next
 // hopping term gathers from its 16 neighbours, out of the caches.
+// The step's scalars come first: every block sums the residual kernel's |r|^2 partials
+// itself and forms beta = |r|^2 / rho and per shift beta_i = beta (zeta_i' / zeta_i)^2 from
+// the copies that kernel's lead took; the lead thread alone commits the live state (zeta_i,
+// frozen shifts, the step count, the base's reliable-update and stop decisions, the gate).
 template <int P>
 __global__ __launch_bounds__(kBlock) void ms_update_kernel(int vh, const void* __restrict__ r,
                                                            void* __restrict__ pb, ShiftPtrs sp,
-                                                           const MSState* __restrict__ st)
+                                                           MSState* __restrict__ st,
+                                                           const double* __restrict__ rr_part,
+                                                           int nrr)
 {
     using R = typename St<P>::R;
     constexpr bool kSloppy = P != KS_F64;
     constexpr int kX = kSloppy ? KS_F32 : KS_F64;
     using XR = typename St<kX>::R;
     constexpr int G = kSloppy ? 4 : 3;
-    if (st->gate) return;
+    if (st->s_gate) return;
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    const double rn = block_total<kBlock>(rr_part, nrr);
+    if (!isfinite(rn)) {
+        if (lead) {
+            st->status = KS_ERR_NONFINITE;
+            st->gate = 1;
+        }
+        return;
+    }
+    const int ns = st->nshift;
+    const double beta = rn / st->s_rho;
+    __shared__ XR sh_ai[kMaxShift];
+    __shared__ R sh_bi[kMaxShift], sh_zi[kMaxShift];
+    __shared__ int sh_upd[kMaxShift];
+    if (threadIdx.x < ns) {
+        const int i = threadIdx.x;
+        const int u = st->upd[i];
+        sh_upd[i] = u;
+        if (u) {
+            const double zn = st->s_zn[i];
+            const double ratio = zn / st->s_zeta[i];
+            sh_ai[i] = (XR)st->alpha_i[i];
+            sh_bi[i] = (R)(beta * ratio * ratio);
+            sh_zi[i] = (R)zn;
+        }
+    }
+    if (lead) {
+        const int iter = st->s_iter + 1;
+        st->beta = beta;
+        st->iter = iter;
+        for (int i = 0; i < ns; ++i) {
+            if (!st->upd[i]) continue;
+            const double zn = st->s_zn[i];
+            st->zeta_prev[i] = st->s_zeta[i];
+            st->zeta[i] = zn;
+            if (st->active[i] && zn * zn * rn <= st->stop2[i]) {
+                st->active[i] = 0;
+                st->nactive -= 1;
+            }
+        }
+        st->alpha_prev = st->alpha;
+        st->beta_prev = beta;
+        st->rho = rn;
+        if (st->nactive == 0 || iter >= st->max_iter) st->stop_next = 1;
+        // reliable update of the base residual when it fell by ru_delta since the last one
+        const double sr = sqrt(rn);
+        if (st->ru_delta > 0.0 && sr < st->ru_delta * st->maxr) st->ru_pending = 1;
+        st->maxr = fmax(st->maxr, sr);
+        if (st->stop_next || st->ru_pending) st->gate = 1;
+    }
+    __syncthreads();
     const int h = blockIdx.x * blockDim.x + threadIdx.x;
     if (h >= vh) return;
     cx<R> rv[3], bv[3];
     Spinor<P>::load(r, vh, h, rv);
     Spinor<P>::load(pb, vh, h, bv);
-    const int ns = st->nshift;
     for (int i0 = 0; i0 < ns; i0 += G) {
         cx<R> pv[G][3];
         cx<XR> xv[G][3];
 #pragma unroll
         for (int j = 0; j < G; ++j) {
             const int i = i0 + j;
-            if (i >= ns || !st->upd[i]) continue;
+            if (i >= ns || !sh_upd[i]) continue;
             if (i == sp.base) {
 #pragma unroll
                 for (int k = 0; k < 3; ++k) pv[j][k] = bv[k];
@@ -194,8 +237,8 @@ __global__ __launch_bounds__(kBlock) void ms_update_kernel(int vh, const void* _
 #pragma unroll
         for (int j = 0; j < G; ++j) {
             const int i = i0 + j;
-            if (i >= ns || !st->upd[i]) continue;
-            const XR ai = (XR)st->alpha_i[i];
+            if (i >= ns || !sh_upd[i]) continue;
+            const XR ai = sh_ai[i];
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 xv[j][k].r = fma(ai, (XR)pv[j][k].r, xv[j][k].r);
@@ -203,7 +246,7 @@ __global__ __launch_bounds__(kBlock) void ms_update_kernel(int vh, const void* _
             }
             Streamed<kX>::store(kSloppy ? sp.dx[i] : sp.x[i], vh, h, xv[j]);
             if (i == sp.base) continue;
-            const R bi = (R)st->beta_i[i], zi = (R)st->zeta[i];
+            const R bi = sh_bi[i], zi = sh_zi[i];
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 pv[j][k].r = fma(bi, pv[j][k].r, zi * rv[k].r);
@@ -212,7 +255,7 @@ __global__ __launch_bounds__(kBlock) void ms_update_kernel(int vh, const void* _
             Streamed<P>::store(sp.p[i], vh, h, pv[j]);
         }
     }
-    const R b = (R)st->beta;
+    const R b = (R)beta;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         bv[k].r = fma(b, bv[k].r, rv[k].r);
@@ -243,16 +286,19 @@ __global__ __launch_bounds__(kBlock) void ms_flush_kernel(int vh, int nshift, Sh
 }
 
 template <int P>
-void launch_r(int vh, const void* q, void* r, const MSState* st, double* part, hipStream_t s)
+void launch_r(int vh, const void* q, void* r, MSState* st, const double* pap_part, int npap,
+              double* rr_part, hipStream_t s)
 {
-    ms_r_kernel<P><<<blocks_for(vh), kBlock, 0, s>>>(vh, q, r, st, part);
+    ms_r_kernel<P><<<blocks_for(vh, kCgFuse), kCgFuse, 0, s>>>(vh, q, r, st, pap_part, npap,
+                                                                rr_part);
 }
 
 template <int P>
-void launch_upd(int vh, const void* r, void* pb, const ShiftPtrs& sp, const MSState* st,
-                hipStream_t s)
+void launch_upd(int vh, const void* r, void* pb, const ShiftPtrs& sp, MSState* st,
+                const double* rr_part, hipStream_t s)
 {
-    ms_update_kernel<P><<<blocks_for(vh), kBlock, 0, s>>>(vh, r, pb, sp, st);
+    ms_update_kernel<P><<<blocks_for(vh), kBlock, 0, s>>>(vh, r, pb, sp, st, rr_part,
+                                                          blocks_for(vh, kCgFuse));
 }
 
 }  // namespace
@@ -383,14 +429,13 @@ ks_status_t multishift_core(ks_gauge_t g, int nshift, const double* sigma, const
         a2.dot_partials = w.partials;
         a2.gate = &st->gate;
         dslash(g, P, RC, a2, s);
-        ms_alpha_kernel<<<1, kFinish, 0, s>>>(w.partials, dslash_blocks(g, P, RC), st);
-        if (P == KS_F64) launch_r<KS_F64>(vh, w.ms_q, w.ms_r, st, w.partials, s);
-        else if (P == KS_F32) launch_r<KS_F32>(vh, w.ms_q, w.ms_r, st, w.partials, s);
-        else launch_r<KS_F16>(vh, w.ms_q, w.ms_r, st, w.partials, s);
-        ms_beta_kernel<<<1, kFinish, 0, s>>>(w.partials, w.npart, st);
-        if (P == KS_F64) launch_upd<KS_F64>(vh, w.ms_r, w.ms_pb, sp, st, s);
-        else if (P == KS_F32) launch_upd<KS_F32>(vh, w.ms_r, w.ms_pb, sp, st, s);
-        else launch_upd<KS_F16>(vh, w.ms_r, w.ms_pb, sp, st, s);
+        const int npap = dslash_blocks(g, P, RC);
+        if (P == KS_F64) launch_r<KS_F64>(vh, w.ms_q, w.ms_r, st, w.partials, npap, w.rr_part, s);
+        else if (P == KS_F32) launch_r<KS_F32>(vh, w.ms_q, w.ms_r, st, w.partials, npap, w.rr_part, s);
+        else launch_r<KS_F16>(vh, w.ms_q, w.ms_r, st, w.partials, npap, w.rr_part, s);
+        if (P == KS_F64) launch_upd<KS_F64>(vh, w.ms_r, w.ms_pb, sp, st, w.rr_part, s);
+        else if (P == KS_F32) launch_upd<KS_F32>(vh, w.ms_r, w.ms_pb, sp, st, w.rr_part, s);
+        else launch_upd<KS_F16>(vh, w.ms_r, w.ms_pb, sp, st, w.rr_part, s);
         KS_HIP(hipGetLastError());
     };
     double model_bytes = 0.0;
