@@ -224,11 +224,13 @@ __device__ __forceinline__ float2_t transport(const half2_t lr[9], const half2_t
 // IN: the first layer reads an inner-precision vector IN (even sites, times *scale); otherwise
 // (IN = void) the binary16 activations.  OUT: the last layer writes OUT (even sites, divided by
 // *scale); otherwise binary16 activations of both parities.
+// At least five waves per SIMD (the 8 -> 8 layer from 99 to 88 registers, no spills): more
+// gathers in flight per CU (32^4 application 408 -> 397 us).
 template <int CIN, int COUT, class IN, class OUT>
-__global__ __launch_bounds__(256) void net_mfma_layer_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void net_mfma_layer_kernel(
     Geom geo, const void* __restrict__ in, void* __restrict__ out, const void* __restrict__ fat_e,
     const void* __restrict__ fat_o, const half4_t* __restrict__ frag,
-    const double* __restrict__ scale, const int* __restrict__ gate)
+    const double* __restrict__ scale, const int* __restrict__ gate, int slab)
 {
     constexpr bool kFirst = CIN == 1;
     constexpr bool kLast = COUT == 1;
@@ -239,10 +241,34 @@ __global__ __launch_bounds__(256) void net_mfma_layer_kernel(
     const int nsites = kLast ? vh : 2 * vh;
     const int lane = threadIdx.x & 63;
     const int n = lane & 15, grp = lane >> 4;
-    const int t = xcd_tile(blockIdx.x, gridDim.x) * kBlockSites + (threadIdx.x >> 6) * kWaveSites + n;
-    const bool live = t < nsites;
-    const int par = (live && t >= vh) ? 1 : 0;
-    const int h = live ? t - par * vh : 0;
+    bool live;
+    int par, h;
+    if (slab) {
+        // workgroups are dealt to the 8 XCDs in turn; XCD k takes the z-planes
+        // [k Nz / 8, (k + 1) Nz / 8) of every t, t after t, both parities of a (z, t) plane
+        // together.  A block's x, y, z and t neighbours are then loaded by its own XCD's
+        // blocks shortly before or after it, while they are still in that XCD's L2; only
+        // the two z-planes next to the slab come from another XCD's share (32^4 application
+        // 428 -> 408 us against contiguous site ranges per XCD).
+        constexpr int npar = kLast ? 1 : 2;
+        const int plane = geo.n[0] * geo.n[1] / 2;          // rows of one (z, t) plane
+        const int tpp = plane / kBlockSites;
+        const int zs = geo.n[2] >> 3;
+        int q = blockIdx.x >> 3;
+        const int yb = q % tpp;
+        q /= tpp;
+        par = npar == 1 ? 0 : q & 1;
+        q /= npar;
+        const int z = (blockIdx.x & 7) * zs + q % zs;
+        const int tt = q / zs;
+        h = (tt * geo.n[2] + z) * plane + yb * kBlockSites + (threadIdx.x >> 6) * kWaveSites + n;
+        live = true;
+    } else {
+        const int t = xcd_tile(blockIdx.x, gridDim.x) * kBlockSites + (threadIdx.x >> 6) * kWaveSites + n;
+        live = t < nsites;
+        par = (live && t >= vh) ? 1 : 0;
+        h = live ? t - par * vh : 0;
+    }
     const void* fat = par ? fat_o : fat_e;
     float sc = 1.f;
     if (kFirst || kLast) sc = scale ? (float)*scale : 1.f;
@@ -372,9 +398,13 @@ void launch_layer(ks_gauge_t g, const void* in, void* out, const half4_t* frag,
                   const double* scale, const int* gate, hipStream_t s)
 {
     const LinkStore& st = g->store[KS_F16][0];
-    const long nsites = COUT == 1 ? g->geom.Vh : 2L * g->geom.Vh;
+    const Geom& G = g->geom;
+    const long nsites = COUT == 1 ? G.Vh : 2L * G.Vh;
+    // the z-slab order needs 8 | Nz and whole blocks per (z, t) plane; it then tiles the
+    // sites exactly
+    const int slab = (G.n[2] % 8 == 0 && (G.n[0] * G.n[1] / 2) % kBlockSites == 0) ? 1 : 0;
     net_mfma_layer_kernel<CIN, COUT, IN, OUT><<<blocks_for(nsites, kBlockSites), 256, 0, s>>>(
-        g->geom, in, out, st.fat[0], st.fat[1], frag, scale, gate);
+        G, in, out, st.fat[0], st.fat[1], frag, scale, gate, slab);
     KS_HIP(hipGetLastError());
 }
 
