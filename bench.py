@@ -4,7 +4,8 @@ Workload: the 32^4 lattice (thin-link scale 0.5, gauge seed 1002, source seed 20
 One step is one pass of the hot path:
   1. timed bursts of Dslash_eo launches of all six variants (FP64 / FP32 / FP16, 18- and
      12-real Naik; HIP events around every launch, on the stream the library launches on);
-  2. the batched solve (64 lattices of 8^4, 12^4, 16^4 x 4 right-hand sides, FP32 + RU);
+  2. the batched solve (64 lattices of 8^4, 12^4, 16^4 x 4 right-hand sides, FP32 + RU, then
+     binary16 + RU);
   3. the multi-shift solve on 32^3 x 48 (9 shifts; FP64, FP32 + RU and FP16 + RU, 18-real
      Naik, and FP64 and FP32 with 12-real Naik) and the force from its solutions;
   4. network bursts and the learned flexible CG;
@@ -508,8 +509,15 @@ def counters_pass(N, ks, G, g, bd, fields, variants, gm, mb_h):
                                                            delta=BATCH_DELTA),
             raise_on_error=False)
     torch.cuda.synchronize()
+    # the same batch with binary16 inner iterations
+    B16 = ks.Batch(bdims, [x_.fat for x_ in bg], [x_.naik for x_ in bg], 4, ks.F16)
+    bx = [torch.zeros_like(v) for v in bb]
+    B16.solve([0.05] * len(bdims), bb, bx, ks.default_params(tol=TOL, max_iter=N, check_every=8,
+                                                             delta=BATCH_DELTA_F16),
+              raise_on_error=False)
+    torch.cuda.synchronize()
     print(json.dumps({"counters": N, "sites_32x32x32x32": g.volume,
-                      "sites_32x32x32x48": gm.volume, "batch": "8 x 16^4 x 4 RHS",
+                      "sites_32x32x32x48": gm.volume, "batch": "8 x 16^4 x 4 RHS, FP32 and binary16",
                       "copy_bytes": 2 * (1 << 27) * 8,
                       "dslash_model_bytes": {"%s_r%d" % v: model_bytes_per_site(*v) * vh
                                              for v in variants}}), flush=True)
