@@ -8,10 +8,11 @@
   5e-6, FP16 5e-3);
 * the benchmark's CG solves at 32^4, m = 0.01 (FP64, FP32 with 18- and 12-real Naik, FP16 with
   12-real Naik), each x judged by the oracle's FP64 residual |b - A x| / |b| <= 1e-10;
-* the benchmark's multi-shift solve at 32^3 x 48 (nine shifts, FP32 inner and FP64, per-shift
-  target 1e-9), each x_i judged by the oracle's residual of its own shifted system;
-* the benchmark's batch (64 lattices x 4 right-hand sides, tuned, reliable updates at a
-  100-fold drop), every pair judged likewise.
+* the benchmark's multi-shift solves at 32^3 x 48 (nine shifts, FP64, FP32 and FP16 inner with
+  18-real Naik, FP64 and FP32 with 12-real Naik, per-shift target 1e-9), each x_i judged by the
+  oracle's residual of its own shifted system;
+* the benchmark's batches (64 lattices x 4 right-hand sides, tuned; FP32 inner with reliable
+  updates at a 100-fold drop, binary16 inner at a 33-fold drop), every pair judged likewise.
 """
 import numpy as np
 import pytest
@@ -86,20 +87,28 @@ def test_bench_cg_32(ks, lat32, inner, recon):
     assert abs(res.stats["true_rel_resid"] - tr) <= 1e-3 * tr
 
 
-@pytest.mark.parametrize("inner", ["f32", "f64"])
-def test_bench_multishift_32x48(ks, inner):
-    import torch
+@pytest.fixture(scope="module")
+def lat48(ks):
     dims = (32, 32, 32, 48)
-    announce("bench multishift 32^3x48", inner)
     g = make_gauge(dims, 0.5, SEEDS["gauge"](3))
     G = ks.Gauge(dims, g.fat, g.naik)
-    G.prepare(ks.PREC[inner], 18)
-    G.tune(ks.PREC[inner], 18)
-    b = gaussian_source(g.volume // 2, SEEDS["source"](3))
+    yield g, G, gaussian_source(g.volume // 2, SEEDS["source"](3))
+    G.free()
+
+
+@pytest.mark.parametrize("inner,recon", [("f32", 18), ("f64", 18), ("f16", 18), ("f32", 12),
+                                         ("f64", 12)])
+def test_bench_multishift_32x48(ks, lat48, inner, recon):
+    import torch
+    announce("bench multishift 32^3x48", inner, recon)
+    g, G, b = lat48
+    G.prepare(ks.PREC[inner], recon)
+    G.tune(ks.PREC[inner], recon)
     sig = 4 * np.geomspace(0.002, 0.5, 9) ** 2
     xs = [zeros_dev(b.shape) for _ in sig]
     rc, stats = ks.multishift_cg_solve(G, sig, dev(b), xs, 1e-9,
-                                       ks.default_params(inner=ks.PREC[inner], check_every=16),
+                                       ks.default_params(inner=ks.PREC[inner], recon=recon,
+                                                         check_every=16),
                                        raise_on_error=False)
     torch.cuda.synchronize()
     assert rc == 0
@@ -109,23 +118,25 @@ def test_bench_multishift_32x48(ks, inner):
         assert abs(stats[i]["true_rel_resid"] - tr) <= 1e-3 * tr
 
 
-def test_bench_batch(ks):
+@pytest.mark.parametrize("inner,delta", [("f32", 0.01), ("f16", 0.03)])
+def test_bench_batch(ks, inner, delta):
     """The benchmark's batch: 24 x 8^4 + 24 x 12^4 + 16 x 16^4 lattices x 4 right-hand sides,
-    FP32 inner iterations with per-lattice reliable updates at a 100-fold drop, tuned schedule;
-    every pair's x judged by the oracle's residual (<= 1e-10)."""
+    FP32 inner iterations with per-lattice reliable updates at a 100-fold drop, or binary16
+    ones at a 33-fold drop, tuned schedule; every pair's x judged by the oracle's residual
+    (<= 1e-10)."""
     import torch
     from ksinputs import batch_masses
-    announce("bench batch 64 lattices x 4")
+    announce("bench batch 64 lattices x 4", inner)
     bdims = [(8, 8, 8, 8)] * 24 + [(12, 12, 12, 12)] * 24 + [(16, 16, 16, 16)] * 16
     gs = [make_gauge(d, 0.4, SEEDS["batch_gauge"](j)) for j, d in enumerate(bdims)]
     masses = batch_masses(len(bdims), 0.01, 0.2, SEEDS["batch_mass"])
-    B = ks.Batch(bdims, [x.fat for x in gs], [x.naik for x in gs], 4, ks.F32)
+    B = ks.Batch(bdims, [x.fat for x in gs], [x.naik for x in gs], 4, ks.PREC[inner])
     B.tune()
     bh = [gaussian_source(x.volume // 2, SEEDS["batch_rhs"](j, r)) for j, x in enumerate(gs)
           for r in range(4)]
     bs = [dev(b) for b in bh]
     xs = [zeros_dev(b.shape) for b in bh]
-    rc, st = B.solve(masses, bs, xs, ks.default_params(tol=1e-10, check_every=8, delta=0.01),
+    rc, st = B.solve(masses, bs, xs, ks.default_params(tol=1e-10, check_every=8, delta=delta),
                      raise_on_error=False)
     torch.cuda.synchronize()
     assert rc == 0
