@@ -40,6 +40,18 @@ void* device_alloc(size_t bytes)
     return p;
 }
 
+void* device_alloc_zero(size_t bytes, hipStream_t s)
+{
+    void* p = device_alloc(bytes);
+    const hipError_t e = hipMemsetAsync(p, 0, bytes ? bytes : 1, s);
+    if (e != hipSuccess) {
+        (void)hipFree(p);
+        set_error("hipMemsetAsync of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+        throw Failure{KS_ERR_HIP};
+    }
+    return p;
+}
+
 void device_free(void* p)
 {
     if (p) (void)hipFree(p);
@@ -56,6 +68,7 @@ Geom make_geom(const int dims[4])
     }
     g.V = (int)v;
     g.Vh = (int)(v / 2);
+    g.lp = link_pitch(g.Vh);
     return g;
 }
 

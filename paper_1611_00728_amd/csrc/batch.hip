@@ -194,8 +194,8 @@ __device__ __forceinline__ void hop_site(const LatDesc& L, int par, int h, const
 #pragma unroll kHopUnroll
     for (int s = 0; s < 16; ++s) {
         cx<T> m[9];
-        if (s < 8) load_link<PP, 9>(fat, s, vh, h, m);
-        else load_link<PP, 9>(naik, s - 8, vh, h, m);
+        if (s < 8) load_link<PP, 9>(fat, s, g.lp, h, m);
+        else load_link<PP, 9>(naik, s - 8, g.lp, h, m);
         if constexpr (PP == KS_F16) {   // binary16 stores hold link / scale
             const float sc = s < 8 ? L.fat_scale : L.naik_scale;
 #pragma unroll

@@ -150,13 +150,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void ds
             for (int u = 0; u < U; ++u) {
                 const int s = s0 + u;
                 if (bwd4) {
-                    if (s0 < 8) load_link<P, 9>(fat_o, s - 4, vh, nb[s], m[u]);
-                    else if (RECON == 12) load_link<P, 6>(naik_o, s - 12, vh, nb[s], m[u]);
-                    else load_link<P, 9>(naik_o, s - 12, vh, nb[s], m[u]);
+                    if (s0 < 8) load_link<P, 9>(fat_o, s - 4, g.lp, nb[s], m[u]);
+                    else if (RECON == 12) load_link<P, 6>(naik_o, s - 12, g.lp, nb[s], m[u]);
+                    else load_link<P, 9>(naik_o, s - 12, g.lp, nb[s], m[u]);
                 } else {
-                    if (s0 < 8) load_link<P, 9>(fat, s, vh, h, m[u]);
-                    else if (RECON == 12) load_link<P, 6>(naik, s - 8, vh, h, m[u]);
-                    else load_link<P, 9>(naik, s - 8, vh, h, m[u]);
+                    if (s0 < 8) load_link<P, 9>(fat, s, g.lp, h, m[u]);
+                    else if (RECON == 12) load_link<P, 6>(naik, s - 8, g.lp, h, m[u]);
+                    else load_link<P, 9>(naik, s - 8, g.lp, h, m[u]);
                 }
                 const int j = nb[s] - lo;
                 if (LG && (s & 3) < 2 && j >= 0 && j < len) Spinor<P>::load(staged, len, j, v[u]);

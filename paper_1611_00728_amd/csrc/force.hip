@@ -79,7 +79,7 @@ __global__ __launch_bounds__(kBlock) void dslash_multi_kernel(Geom g, int par,
         const int dist = (s & 4) ? (kind ? -3 : -1) : (kind ? 3 : 1);
         const int nb = hop_cb(g, i, c, s & 3, dist);
         cx<double> m[9];
-        load_link<KS_F64, 9>(links, s, vh, hs, m);
+        load_link<KS_F64, 9>(links, s, g.lp, hs, m);
 #pragma unroll
         for (int q = 0; q < K; ++q) {
             cx<double> v[3];

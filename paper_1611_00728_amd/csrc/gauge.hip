@@ -48,16 +48,16 @@ __global__ __launch_bounds__(kBlock) void layout_f64_kernel(Geom g, int par,
                         const double2 t = L[b * 3 + a];
                         v = make_double2(-t.x, t.y);   // -(conj of the transpose)
                     }
-                    dst[(size_t)(s * 9 + a * 3 + b) * g.Vh + h] = v;
+                    dst[(size_t)(s * 9 + a * 3 + b) * g.lp + h] = v;
                 }
         }
     }
 }
 
-// FP64 planes [8 slots][N][Vh] -> packed planes of precision P (value * scale).
+// FP64 planes [8 slots][N][lp] -> packed planes of precision P (value * scale), pitch lp.
 template <int P, int N>
 __global__ __launch_bounds__(kBlock) void pack_kernel(const double2* __restrict__ src,
-                                                      char* __restrict__ dst, int vh,
+                                                      char* __restrict__ dst, int vh, int lp,
                                                       double scale)
 {
     const int h = blockIdx.x * blockDim.x + threadIdx.x;
@@ -65,8 +65,8 @@ __global__ __launch_bounds__(kBlock) void pack_kernel(const double2* __restrict_
     using LP = LinkPack<P, N>;
     for (int slot = 0; slot < 8; ++slot)
         for (int e = 0; e < N; ++e) {
-            const double2 v = src[(size_t)(slot * N + e) * vh + h];
-            char* d = dst + LP::offset(slot, e, vh, h);
+            const double2 v = src[(size_t)(slot * N + e) * lp + h];
+            char* d = dst + LP::offset(slot, e, lp, h);
             if constexpr (P == KS_F64)
                 *reinterpret_cast<double2*>(d) = make_double2(v.x * scale, v.y * scale);
             else if constexpr (P == KS_F32)
@@ -77,13 +77,13 @@ __global__ __launch_bounds__(kBlock) void pack_kernel(const double2* __restrict_
 }
 
 template <int N>
-void pack(ks_prec_t p, const double2* src, void* dst, int vh, double scale, hipStream_t s)
+void pack(ks_prec_t p, const double2* src, void* dst, const Geom& g, double scale, hipStream_t s)
 {
-    const int nb = blocks_for(vh);
+    const int nb = blocks_for(g.Vh);
     char* d = static_cast<char*>(dst);
-    if (p == KS_F64) pack_kernel<KS_F64, N><<<nb, kBlock, 0, s>>>(src, d, vh, scale);
-    else if (p == KS_F32) pack_kernel<KS_F32, N><<<nb, kBlock, 0, s>>>(src, d, vh, scale);
-    else pack_kernel<KS_F16, N><<<nb, kBlock, 0, s>>>(src, d, vh, scale);
+    if (p == KS_F64) pack_kernel<KS_F64, N><<<nb, kBlock, 0, s>>>(src, d, g.Vh, g.lp, scale);
+    else if (p == KS_F32) pack_kernel<KS_F32, N><<<nb, kBlock, 0, s>>>(src, d, g.Vh, g.lp, scale);
+    else pack_kernel<KS_F16, N><<<nb, kBlock, 0, s>>>(src, d, g.Vh, g.lp, scale);
     KS_HIP(hipGetLastError());
 }
 
@@ -125,7 +125,7 @@ __global__ __launch_bounds__(kBlock) void recon12_kernel(Geom g, int par,
             zd u[3][3];
             for (int a = 0; a < 3; ++a)
                 for (int b = 0; b < 3; ++b) {
-                    const double2 v = naik[(size_t)(s * 9 + a * 3 + b) * g.Vh + h];
+                    const double2 v = naik[(size_t)(s * 9 + a * 3 + b) * g.lp + h];
                     u[a][b] = {v.x / sc, v.y / sc};
                 }
             for (int a = 0; a < 3; ++a)
@@ -140,7 +140,7 @@ __global__ __launch_bounds__(kBlock) void recon12_kernel(Geom g, int par,
             defect = fmax(defect, zabs(zsub(det, zd{1.0, 0.0})));
             for (int e = 0; e < 6; ++e) {
                 const zd v = u[e / 3][e % 3];
-                out[(size_t)(s * 6 + e) * g.Vh + h] = make_double2(v.r, v.i);
+                out[(size_t)(s * 6 + e) * g.lp + h] = make_double2(v.r, v.i);
             }
         }
     }
@@ -179,10 +179,10 @@ int recon_index(ks_recon_t r) { return r == KS_RECON_12 ? 1 : 0; }
 void gauge_build_f64(ks_gauge_t g, const double* fat_dev, const double* naik_dev, hipStream_t s)
 {
     LinkStore& st = g->store[KS_F64][0];
-    const size_t plane = (size_t)72 * g->geom.Vh * 16;   // 8 slots x 9 entries x Vh x 16 B
+    const size_t plane = (size_t)72 * g->geom.lp * 16;   // 8 slots x 9 entries x lp x 16 B
     for (int par = 0; par < 2; ++par) {
-        st.fat[par] = device_alloc(plane);
-        st.naik[par] = device_alloc(plane);
+        st.fat[par] = device_alloc_zero(plane, s);
+        st.naik[par] = device_alloc_zero(plane, s);
         st.bytes += 2 * plane;
     }
     for (int par = 0; par < 2; ++par) {
@@ -215,7 +215,7 @@ void gauge_prepare(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, hipStream_t s
     if (st.ready) return;
     const LinkStore& m = g->store[KS_F64][0];
     const Geom& G = g->geom;
-    const size_t n18 = (size_t)72 * G.Vh;   // complex entries per parity and class
+    const size_t n18 = (size_t)72 * G.lp;   // complex entries per parity and class
 
     // fat planes: shared between the 18- and 12-real stores of one precision
     LinkStore& base = g->store[prec][0];
@@ -228,9 +228,9 @@ void gauge_prepare(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, hipStream_t s
             fs = frexp_scale(mx);
         }
         for (int par = 0; par < 2; ++par) {
-            base.fat[par] = device_alloc(n18 * entry_bytes(prec));
+            base.fat[par] = device_alloc_zero(n18 * entry_bytes(prec), s);
             base.bytes += n18 * entry_bytes(prec);
-            pack<9>(prec, static_cast<const double2*>(m.fat[par]), base.fat[par], G.Vh, fs, s);
+            pack<9>(prec, static_cast<const double2*>(m.fat[par]), base.fat[par], G, fs, s);
         }
         base.fat_scale = (float)(1.0 / fs);
     }
@@ -253,9 +253,9 @@ void gauge_prepare(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, hipStream_t s
                 st.naik[par] = m.naik[par];
                 continue;
             }
-            st.naik[par] = device_alloc(n18 * entry_bytes(prec));
+            st.naik[par] = device_alloc_zero(n18 * entry_bytes(prec), s);
             st.bytes += n18 * entry_bytes(prec);
-            pack<9>(prec, static_cast<const double2*>(m.naik[par]), st.naik[par], G.Vh, ns, s);
+            pack<9>(prec, static_cast<const double2*>(m.naik[par]), st.naik[par], G, ns, s);
         }
         st.naik_scale = (float)(1.0 / ns);
     } else {
@@ -263,7 +263,7 @@ void gauge_prepare(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, hipStream_t s
         if (g->naik_c0 == 0.0) {
             double2 w[9];
             for (int k = 0; k < 9; ++k)
-                KS_HIP(hipMemcpyAsync(&w[k], static_cast<const double2*>(m.naik[0]) + (size_t)k * G.Vh,
+                KS_HIP(hipMemcpyAsync(&w[k], static_cast<const double2*>(m.naik[0]) + (size_t)k * G.lp,
                                       sizeof(double2), hipMemcpyDeviceToHost, s));
             KS_HIP(hipStreamSynchronize(s));
             std::complex<double> u[3][3];
@@ -276,21 +276,21 @@ void gauge_prepare(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, hipStream_t s
                        KS_ERR_NOT_SU3, "12-real Naik storage: det W at the origin is not real");
             g->naik_c0 = std::cbrt(det.real());
         }
-        const size_t n12 = (size_t)48 * G.Vh;
+        const size_t n12 = (size_t)48 * G.lp;
         const int nb = blocks_for(G.Vh);
         double* part = static_cast<double*>(device_alloc(sizeof(double) * (nb + 1)));
         double defect[2] = {0, 0};
         void* outs[2] = {nullptr, nullptr};
         double2* tmp = nullptr;
         try {
-            if (prec != KS_F64) tmp = static_cast<double2*>(device_alloc(n12 * 16));
+            if (prec != KS_F64) tmp = static_cast<double2*>(device_alloc_zero(n12 * 16, s));
             for (int par = 0; par < 2; ++par) {
-                outs[par] = device_alloc(n12 * entry_bytes(prec));
+                outs[par] = device_alloc_zero(n12 * entry_bytes(prec), s);
                 const double2* src = static_cast<const double2*>(m.naik[par]);
                 double2* u = (prec == KS_F64) ? static_cast<double2*>(outs[par]) : tmp;
                 recon12_kernel<<<nb, kBlock, 0, s>>>(G, par, src, u, g->naik_c0, part);
                 KS_HIP(hipGetLastError());
-                if (prec != KS_F64) pack<6>(prec, tmp, outs[par], G.Vh, 1.0, s);
+                if (prec != KS_F64) pack<6>(prec, tmp, outs[par], G, 1.0, s);
                 reduce_max(part, nb, part + nb, s);
                 KS_HIP(hipMemcpyAsync(&defect[par], part + nb, sizeof(double),
                                       hipMemcpyDeviceToHost, s));

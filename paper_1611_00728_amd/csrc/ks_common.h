@@ -39,6 +39,8 @@ struct Failure {
     } while (0)
 
 void* device_alloc(size_t bytes);
+// device_alloc, then the memory cleared on stream s (link stores: their padding rows are zero)
+void* device_alloc_zero(size_t bytes, hipStream_t s);
 void device_free(void* p);
 
 // ------------------------------------------------------------------ geometry
@@ -47,14 +49,23 @@ struct Geom {
     int n[4];
     int stride[4];     // lexicographic strides 1, Nx, Nx Ny, Nx Ny Nz
     int V, Vh;
+    int lp;            // sites per link plane (link_pitch(Vh) >= Vh)
 };
+
+// Sites per plane of a link store: Vh rounded up to a multiple of 512, plus 256.  A hopping
+// term streams 144 link planes at the same site offset; with a power-of-two pitch (Vh = 2^19
+// at 32^4) those streams meet the same HBM channels, and a pitch of 256 (mod 512) sites
+// spreads them (144 planes of 16-byte entries read at 32^4: 5.5 TB/s at pitch Vh, 6.8 TB/s at
+// Vh + 256; 1024 and 4096 extra sites are as slow as none).
+inline int link_pitch(int vh) { return ((vh + 511) / 512) * 512 + 256; }
 
 Geom make_geom(const int dims[4]);
 
 // ------------------------------------------------------------------ link stores
 
-// Per precision, per output parity: fat planes [8 slots][9 entries][Vh] and Naik planes
-// [8 slots][9 or 6 entries][Vh] of complex numbers (double2 / float2 / __half2).
+// Per precision, per output parity: fat planes [8 slots][9 entries][lp] and Naik planes
+// [8 slots][9 or 6 entries][lp] of complex numbers (double2 / float2 / __half2), lp the link
+// pitch of the geometry (rows Vh .. lp - 1 of a plane are zero and never read).
 // Slot s < 4: forward link of direction s at the site; s >= 4: minus the adjoint of the
 // backward link of direction s - 4 (one hop for fat, three hops for Naik).
 struct LinkStore {

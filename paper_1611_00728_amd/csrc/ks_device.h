@@ -88,9 +88,9 @@ __device__ __forceinline__ cx<float> half2_to_cx(unsigned u)
     return {f.x, f.y};
 }
 
-// Packed link planes.  Per slot, the N complex entries of a link occupy N * ES * Vh bytes:
-// N / W "vector planes" of 16 bytes per site (W = 16 / ES entries each, site-major), then one
-// plane holding the remaining N % W entries per site.  Every lane of a wave reads 16 bytes (or
+// Packed link planes.  Per slot, the N complex entries of a link occupy N * ES * lp bytes (lp
+// the link pitch of the geometry, >= Vh): N / W "vector planes" of 16 bytes per site (W = 16 / ES
+// entries each, site-major), then one plane holding the remaining N % W entries per site.  Every lane of a wave reads 16 bytes (or
 // the remainder) of consecutive sites, so each load is one contiguous, fully used segment.
 template <int P, int N>
 struct LinkPack {
@@ -98,25 +98,26 @@ struct LinkPack {
     static constexpr int W = 16 / ES;
     static constexpr int NF = N / W;
     static constexpr int NR = N % W;
-    // byte offset of entry e of `slot` at site h
-    __host__ __device__ static size_t offset(int slot, int e, int vh, int h)
+    // byte offset of entry e of `slot` at site h, planes of lp sites
+    __host__ __device__ static size_t offset(int slot, int e, int lp, int h)
     {
-        const size_t sb = (size_t)slot * N * ES * vh;
+        const size_t sb = (size_t)slot * N * ES * lp;
         const int j = e / W, t = e % W;
-        if (j < NF) return sb + (size_t)j * 16 * vh + (size_t)h * 16 + t * ES;
-        return sb + (size_t)NF * 16 * vh + (size_t)h * NR * ES + t * ES;
+        if (j < NF) return sb + (size_t)j * 16 * lp + (size_t)h * 16 + t * ES;
+        return sb + (size_t)NF * 16 * lp + (size_t)h * NR * ES + t * ES;
     }
 };
 
+// the N entries of link `slot` at site h from planes of lp sites
 template <int P, int N>
-__device__ __forceinline__ void load_link(const void* base, int slot, int vh, int h,
+__device__ __forceinline__ void load_link(const void* base, int slot, int lp, int h,
                                           cx<typename St<P>::R> m[9])
 {
     using LP = LinkPack<P, N>;
-    const char* sb = static_cast<const char*>(base) + (size_t)slot * N * LP::ES * vh;
+    const char* sb = static_cast<const char*>(base) + (size_t)slot * N * LP::ES * lp;
 #pragma unroll
     for (int j = 0; j < LP::NF; ++j) {
-        const char* pl = sb + (size_t)j * 16 * vh;
+        const char* pl = sb + (size_t)j * 16 * lp;
         if constexpr (P == KS_F64) {
             const dvec2 v = __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(pl) + h);
             m[j] = {v.x, v.y};
@@ -133,7 +134,7 @@ __device__ __forceinline__ void load_link(const void* base, int slot, int vh, in
         }
     }
     if constexpr (LP::NR > 0) {
-        const char* pl = sb + (size_t)LP::NF * 16 * vh;
+        const char* pl = sb + (size_t)LP::NF * 16 * lp;
         constexpr int o = LP::NF * LP::W;
         if constexpr (P == KS_F32) {
             const fvec2 v = __builtin_nontemporal_load(reinterpret_cast<const fvec2*>(pl) + h);

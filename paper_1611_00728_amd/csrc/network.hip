@@ -82,7 +82,7 @@ __global__ __launch_bounds__(kNT) void net_layer_kernel(Geom g, const float2* __
         const int nbh = hop_cb(g, i, c, mu, bwd ? -1 : +1);
         const int p = bwd ? 5 + mu : 1 + mu;
         cx<float> m[9];
-        load_link<KS_F32, 9>(fat, s, vh, h, m);
+        load_link<KS_F32, 9>(fat, s, g.lp, h, m);
         if (bwd) {   // stored -V_mu(x-mu)^+
 #pragma unroll
             for (int e = 0; e < 9; ++e) m[e] = {-m[e].r, -m[e].i};
@@ -178,7 +178,7 @@ __global__ __launch_bounds__(kNT) void net_wgrad_kernel(Geom g, const float2* __
                 const int s = p - 1;
                 nbh = hop_cb(g, i, c, s & 3, s >= 4 ? -1 : +1);
                 spar = 1 - par;
-                load_link<KS_F32, 9>(fat, s, vh, h, m);
+                load_link<KS_F32, 9>(fat, s, g.lp, h, m);
                 if (s >= 4)   // the store holds -V(x-mu)^+
 #pragma unroll
                     for (int e = 0; e < 9; ++e) m[e] = {-m[e].r, -m[e].i};

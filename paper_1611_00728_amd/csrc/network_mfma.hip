@@ -146,28 +146,28 @@ __device__ __forceinline__ int lane_hop(const Geom& geo, int i, const int c[4], 
     return j >> 1;
 }
 
-// The nine entries of stored link slot s at checkerboard row h (binary16 (re, im) pairs),
-// returned as the two operand forms of a complex product by dot2:
+// The nine entries of stored link slot s at checkerboard row h (binary16 (re, im) pairs, planes
+// of lp sites), returned as the two operand forms of a complex product by dot2:
 // lr = (re, -im) gives Re(m v) = dot2(lr, v), li = (im, re) gives Im(m v) = dot2(li, v).
-__device__ __forceinline__ void link_pairs(const void* fat, int s, int vh, int h, half2_t lr[9],
+__device__ __forceinline__ void link_pairs(const void* fat, int s, int lp, int h, half2_t lr[9],
                                            half2_t li[9])
 {
     using LP = LinkPack<KS_F16, 9>;
     static_assert(LP::NF == 2 && LP::NR == 1, "binary16 link packing");
-    const char* sb = static_cast<const char*>(fat) + (size_t)s * 9 * LP::ES * vh;
+    const char* sb = static_cast<const char*>(fat) + (size_t)s * 9 * LP::ES * lp;
     unsigned u[9];
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
         // streamed once per layer: non-temporal, so that they do not evict the activations,
         // which the neighbours read again
         const uvec4 q =
-            __builtin_nontemporal_load(reinterpret_cast<const uvec4*>(sb + (size_t)j * 16 * vh) + h);
+            __builtin_nontemporal_load(reinterpret_cast<const uvec4*>(sb + (size_t)j * 16 * lp) + h);
         u[4 * j] = q.x;
         u[4 * j + 1] = q.y;
         u[4 * j + 2] = q.z;
         u[4 * j + 3] = q.w;
     }
-    u[8] = __builtin_nontemporal_load(reinterpret_cast<const unsigned*>(sb + (size_t)2 * 16 * vh) + h);
+    u[8] = __builtin_nontemporal_load(reinterpret_cast<const unsigned*>(sb + (size_t)2 * 16 * lp) + h);
 #pragma unroll
     for (int e = 0; e < 9; ++e) {
         lr[e] = as_h2(u[e] ^ 0x80000000u);
@@ -323,7 +323,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void n
         Gathered<CIN> x;
         if (!kFirst || par == 1) {
             const int nbh = lane_hop(geo, i, c, grp, j ? -1 : +1);
-            link_pairs(fat, j * 4 + grp, vh, h, lr, li);
+            link_pairs(fat, j * 4 + grp, geo.lp, h, lr, li);
             if constexpr (kFirst) {
                 cx<typename IN::R> v[3];
                 IN::load(in, vh, nbh, v);
