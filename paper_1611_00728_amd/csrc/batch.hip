@@ -929,10 +929,14 @@ static void batch_setup(BatchCtx* c, hipStream_t s)
     KS_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->census_host), sizeof(int)));
     const size_t cs = inner == KS_F64 ? 16 : 8;
     const size_t nrec = vec_off * 3 * nrhs;
-    c->ps = static_cast<char*>(device_alloc(nrec * cs));
-    c->qs = static_cast<char*>(device_alloc(nrec * cs));
-    c->ts = static_cast<char*>(device_alloc(nrec * cs));
-    c->rs = static_cast<char*>(device_alloc(nrec * cs));
+    // inner-precision arenas: complex numbers of cs bytes, or one 16-byte binary16 record per
+    // site and right-hand side
+    const size_t ib = inner == KS_F16 ? vec_off * nrhs * 16 : nrec * cs;
+    c->inner_bytes = ib;
+    c->ps = static_cast<char*>(device_alloc(ib));
+    c->qs = static_cast<char*>(device_alloc(ib));
+    c->ts = static_cast<char*>(device_alloc(ib));
+    c->rs = static_cast<char*>(device_alloc(ib));
     c->x64 = static_cast<char*>(device_alloc(nrec * 16));
     c->b64 = static_cast<char*>(device_alloc(nrec * 16));
     c->r64 = static_cast<char*>(device_alloc(nrec * 16));
@@ -944,7 +948,7 @@ static void batch_setup(BatchCtx* c, hipStream_t s)
     }
     // finished pairs leave their slots of p, q, t untouched: start every arena finite
     for (char* a : {c->ps, c->qs, c->ts, c->rs})
-        KS_HIP(hipMemsetAsync(a, 0, nrec * cs, s));
+        KS_HIP(hipMemsetAsync(a, 0, ib, s));
     for (char* a : {c->x64, c->b64, c->r64, c->t64, c->ax64})
         KS_HIP(hipMemsetAsync(a, 0, nrec * 16, s));
     KS_HIP(hipStreamSynchronize(s));
@@ -1190,8 +1194,7 @@ void batch_tune(BatchCtx& c, hipStream_t caller)
         c.pairs_host[p] = q;
     }
     KS_HIP(hipMemcpyAsync(c.pairs, c.pairs_host, sizeof(BatchPair) * c.npairs, hipMemcpyHostToDevice, s));
-    const size_t cs = c.prec == KS_F64 ? 16 : 8;
-    KS_HIP(hipMemsetAsync(c.ps, 0x3f, c.total_vh * 3 * c.nrhs * cs, s));
+    KS_HIP(hipMemsetAsync(c.ps, 0x3f, c.inner_bytes, s));
     hipEvent_t e0, e1;
     KS_HIP(hipEventCreate(&e0));
     KS_HIP(hipEventCreate(&e1));

@@ -68,6 +68,7 @@ struct BatchCtx {
     // FP32 inner: x's FP32 increments since the pair's last reliable update (zero otherwise)
     char* dx32 = nullptr;
     size_t dx32_bytes = 0;
+    size_t inner_bytes = 0;   // bytes of each inner-precision arena (p, q, t, r)
     void** io_ptrs = nullptr;  // device table of the caller's per-pair vectors
     double* b2 = nullptr;      // |b|^2 per pair
     double* pair_param = nullptr;     // device [2][npairs]: shift and tolerance of each pair
