@@ -488,7 +488,11 @@ ks_status_t multishift_core(ks_gauge_t g, int nshift, const double* sigma, const
     const int ms_iters = hs->iter;
     if (!rolled_back) flush();
 
-    // FP64 verdict per shift; refine the ones above target from x_i
+    // FP64 verdict per shift; refine the ones above target from x_i.  In reduced precision with
+    // at least two shifts besides the base, those go to the batched refinement unchecked: its
+    // first step computes every pair's FP64 residual anyway and finishes the pairs already at
+    // target, so a separate FP64 A-apply per shift here would only repeat it.
+    const bool batch_all = P != KS_F64 && nshift >= 3 && b2 > 0;
     std::vector<int> need;
     for (int i = 0; i < nshift; ++i) {
         ks_solver_stats& o = stats[i];
@@ -497,6 +501,10 @@ ks_status_t multishift_core(ks_gauge_t g, int nshift, const double* sigma, const
         o.reliable_updates = ms_ru;
         o.model_bytes = model_bytes / nshift;
         if (result != KS_SUCCESS) continue;
+        if (batch_all && i != i0) {
+            need.push_back(i);
+            continue;
+        }
         const double tr2 = true_resid2(g, sigma[i], b, x[i], s);
         o.true_rel_resid = b2 > 0 ? std::sqrt(tr2 / b2) : 0.0;
         if (b2 > 0 && tr2 > tol[i] * tol[i] * b2) need.push_back(i);
