@@ -32,6 +32,10 @@
  * workspace.  Different handles are independent.
  * Errors: every call returns a ks_status_t and never aborts; ks_last_error() gives a message
  * for the calling thread's last failure.
+ * Diagnostics: with the environment variable KS_LOG at 1 or more, each solve prints a summary
+ * line (status, steps, reliable updates, FP64 residual, seconds, model GB/s), each tuning its
+ * result and each failing call its error on stderr, prefixed "[ks]"; unset or 0, the library
+ * prints nothing.
  */
 #ifndef KS_H
 #define KS_H
@@ -149,7 +153,13 @@ ks_status_t ks_dslash_eo(ks_gauge_t g, ks_field_t out, ks_field_t in, ks_recon_t
  * capped through the LDS request) and keeps the fastest for every later launch through this
  * handle (ks_dslash_eo and the solvers).  Untuned variants use 256 threads, no cap.  Allocates
  * two scratch fields for the duration of the call; synchronises the stream.  Must not be
- * called while the stream is being captured into a graph. */
+ * called while the stream is being captured into a graph.
+ * With the environment variable KS_TUNE_CACHE naming a file, the configuration is taken from
+ * that file when it holds a usable entry for this device (architecture, compute units),
+ * lattice extents, precision and Naik storage, without any timing; otherwise the tuned result
+ * is recorded there (one JSON object per line, the file replaced atomically; lines of other
+ * keys, readable or not, are kept).  KS_LOG >= 1 prints each tuning result on stderr, >= 2
+ * also the cache's hit or miss. */
 ks_status_t ks_tune_dslash(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, hipStream_t stream);
 
 /* Launch configuration of one Dslash variant:
@@ -372,6 +382,17 @@ ks_status_t ks_net_create(ks_net_t* out, const double* weights);
 ks_status_t ks_net_set_weights(ks_net_t n, const double* weights);   /* also resets Adam */
 ks_status_t ks_net_get_weights(ks_net_t n, double* weights);
 ks_status_t ks_net_free(ks_net_t n);
+
+/* Training state, for checkpoints: the free weights (complex128 [KS_NET_WEIGHTS]), Adam's first
+ * and second moments (double [2 * KS_NET_WEIGHTS] each, one per real and imaginary part, in the
+ * order of the weights' reals) and the number of Adam steps taken, all on the host.
+ * ks_net_set_state restores a state that ks_net_get_state returned, after which ks_net_train
+ * continues exactly as the saved network would have (bias correction included).  Synchronous.
+ * KS_ERR_ARG for null pointers, a negative step count or non-finite values. */
+ks_status_t ks_net_get_state(ks_net_t n, double* weights, double* adam_m, double* adam_v,
+                             int* step);
+ks_status_t ks_net_set_state(ks_net_t n, const double* weights, const double* adam_m,
+                             const double* adam_v, int step);
 
 /* out_dev = N(in_dev), complex128 [Vh][3] device arrays of the handle's lattice.  use_mfma = 0:
  * FP32 channel mixing on the vector ALUs, transports with the FP32 fat links; 1: every layer

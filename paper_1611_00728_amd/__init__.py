@@ -455,6 +455,41 @@ class Batch:
 
 
 NET_WEIGHTS = 648
+CHECKPOINT_MAGIC = b"KSNETCK1"
+
+
+def write_checkpoint(path, weights, adam_m, adam_v, step: int):
+    """Network checkpoint, little-endian: the 8-byte magic, uint32 number of complex weights,
+    uint32 Adam step count, then float64 arrays: the weights as (re, im) pairs, Adam's first
+    moments, Adam's second moments (2 * the number of weights each)."""
+    import numpy as np
+    w = np.asarray(weights, dtype=np.complex128).ravel()
+    m = np.asarray(adam_m, dtype=np.float64).ravel()
+    v = np.asarray(adam_v, dtype=np.float64).ravel()
+    if m.size != 2 * w.size or v.size != 2 * w.size or step < 0:
+        raise ValueError("inconsistent checkpoint state")
+    head = CHECKPOINT_MAGIC + np.array([w.size, step], dtype="<u4").tobytes()
+    body = b"".join(a.astype("<f8").tobytes() for a in (w.view(np.float64), m, v))
+    tmp = str(path) + ".tmp"
+    with open(tmp, "wb") as f:
+        f.write(head + body)
+    os.replace(tmp, path)
+
+
+def read_checkpoint(path):
+    """(weights, adam_m, adam_v, step) from a file written by write_checkpoint; ValueError for
+    another format or a truncated file."""
+    import numpy as np
+    with open(path, "rb") as f:
+        data = f.read()
+    if len(data) < 16 or data[:8] != CHECKPOINT_MAGIC:
+        raise ValueError("%s: not a network checkpoint" % path)
+    n, step = (int(x) for x in np.frombuffer(data[8:16], dtype="<u4"))
+    if len(data) != 16 + 3 * 2 * n * 8:
+        raise ValueError("%s: %d bytes, expected %d" % (path, len(data), 16 + 48 * n))
+    a = np.frombuffer(data[16:], dtype="<f8").astype(np.float64)
+    w = a[:2 * n].copy().view(np.complex128)
+    return w, a[2 * n:4 * n].copy(), a[4 * n:].copy(), step
 
 
 class Net:
@@ -471,6 +506,8 @@ class Net:
         L.ks_net_set_weights.argtypes = [_vp, _vp]
         L.ks_net_get_weights.argtypes = [_vp, _vp]
         L.ks_net_free.argtypes = [_vp]
+        L.ks_net_get_state.argtypes = [_vp, _vp, _vp, _vp, C.POINTER(C.c_int)]
+        L.ks_net_set_state.argtypes = [_vp, _vp, _vp, _vp, C.c_int]
         L.ks_net_apply.argtypes = [_vp, _vp, _vp, _vp, C.c_int, _vp]
         L.ks_net_apply_field.argtypes = [_vp, _vp, _vp, C.c_int, _vp]
         L.ks_net_loss_grad.argtypes = [_vp, C.c_int, C.POINTER(_vp), C.POINTER(C.c_double),
@@ -497,6 +534,38 @@ class Net:
         w = np.zeros(NET_WEIGHTS, dtype=np.complex128)
         _check(lib().ks_net_get_weights(self.handle, _vp(w.ctypes.data)))
         return w
+
+    def get_state(self):
+        """(weights complex128 [NET_WEIGHTS], Adam first and second moments float64
+        [2 NET_WEIGHTS] each, Adam step count)."""
+        import numpy as np
+        w = np.zeros(NET_WEIGHTS, dtype=np.complex128)
+        m = np.zeros(2 * NET_WEIGHTS)
+        v = np.zeros(2 * NET_WEIGHTS)
+        step = C.c_int()
+        _check(lib().ks_net_get_state(self.handle, _vp(w.ctypes.data), _vp(m.ctypes.data),
+                                      _vp(v.ctypes.data), C.byref(step)))
+        return w, m, v, step.value
+
+    def set_state(self, weights, adam_m, adam_v, step: int):
+        import numpy as np
+        w = np.ascontiguousarray(np.asarray(weights, dtype=np.complex128).ravel())
+        m = np.ascontiguousarray(np.asarray(adam_m, dtype=np.float64).ravel())
+        v = np.ascontiguousarray(np.asarray(adam_v, dtype=np.float64).ravel())
+        if w.size != NET_WEIGHTS or m.size != 2 * NET_WEIGHTS or v.size != 2 * NET_WEIGHTS:
+            raise ValueError("state sizes: %d complex weights, %d reals per moment"
+                             % (NET_WEIGHTS, 2 * NET_WEIGHTS))
+        _check(lib().ks_net_set_state(self.handle, _vp(w.ctypes.data), _vp(m.ctypes.data),
+                                      _vp(v.ctypes.data), int(step)))
+
+    def save(self, path):
+        """Checkpoint of the weights and the Adam state (format of write_checkpoint)."""
+        write_checkpoint(path, *self.get_state())
+
+    def load(self, path):
+        """Restores a checkpoint written by save; training continues where it stopped."""
+        self.set_state(*read_checkpoint(path))
+        return self
 
     def apply(self, gauge: Gauge, x, out, mfma: bool = False, stream=None):
         _check(lib().ks_net_apply(self.handle, gauge.handle, _dev_vec(x, gauge.vh, "x"),

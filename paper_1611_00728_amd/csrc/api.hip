@@ -1,8 +1,11 @@
 // C ABI of libks (declared in include/ks.h): argument checks, handle management, error
 // reporting.  Every entry point catches the library's internal failures and returns a code.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdint>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -19,6 +22,26 @@ thread_local char g_err[512] = "";
 }
 
 const char* error_text() { return g_err; }
+
+int log_level()
+{
+    static const int level = [] {
+        const char* e = std::getenv("KS_LOG");
+        return e ? std::atoi(e) : 0;
+    }();
+    return level;
+}
+
+void log_msg(int level, const char* fmt, ...)
+{
+    if (log_level() < level) return;
+    char line[640];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(line, sizeof(line), fmt, ap);
+    va_end(ap);
+    std::fprintf(stderr, "[ks] %s\n", line);
+}
 
 void set_error(const char* fmt, ...)
 {
@@ -85,6 +108,7 @@ using namespace ks;
 #define KS_API_END                                                                      \
     }                                                                                   \
     catch (const Failure& f) {                                                          \
+        log_msg(1, "%s: error %d: %s", __func__, (int)f.code, error_text());             \
         return f.code;                                                                  \
     }                                                                                   \
     catch (const std::bad_alloc&) {                                                     \
@@ -97,6 +121,13 @@ using namespace ks;
     }
 
 static_assert(kNetWeights == KS_NET_WEIGHTS, "network weight count of the ABI");
+
+static void log_solve(const char* what, ks_status_t rc, const ks_solver_stats& s)
+{
+    log_msg(1, "%s: status %d, %d steps, %d reliable updates, true residual %.3g, %.4f s, "
+               "%.1f GB/s model", what, (int)rc, s.iters, s.reliable_updates, s.true_rel_resid,
+            s.seconds, s.seconds > 0 ? s.model_bytes / s.seconds / 1e9 : 0.0);
+}
 
 static bool prec_ok(int p) { return p == KS_F64 || p == KS_F32 || p == KS_F16; }
 static bool recon_ok(int r) { return r == KS_RECON_18 || r == KS_RECON_12; }
@@ -363,6 +394,7 @@ ks_status_t ks_cg_solve(ks_gauge_t g, double mass, const double* b_dev, double* 
                                    static_cast<double*>(w.x64), *p, local, stream);
     export_field(g->geom, KS_F64, w.x64, x_dev, stream);
     KS_HIP(hipStreamSynchronize(stream));
+    log_solve("cg", rc, local);
     if (st) *st = local;
     return rc;
     KS_API_END
@@ -398,6 +430,7 @@ ks_status_t ks_full_solve(ks_gauge_t g, double mass, const double* b_even, const
     export_field(g->geom, KS_F64, w.x64, x_even, stream);
     export_field(g->geom, KS_F64, w.full[4], x_odd, stream);
     KS_HIP(hipStreamSynchronize(stream));
+    log_solve("full solve", rc, local);
     if (st) *st = local;
     return rc;
     KS_API_END
@@ -444,6 +477,7 @@ ks_status_t ks_multishift_cg_solve(ks_gauge_t g, int nshift, const double* sigma
                                            xs.data(), tol, *p, st, stream);
     for (int i = 0; i < nshift; ++i) export_field(g->geom, KS_F64, xs[i], x_dev[i], stream);
     KS_HIP(hipStreamSynchronize(stream));
+    for (int i = 0; i < nshift; ++i) log_solve("multishift shift", rc, st[i]);
     return rc;
     KS_API_END
 }
@@ -469,7 +503,20 @@ ks_status_t ks_batch_solve(ks_batch_t b, const double* masses, const double* con
     KS_REQUIRE(b && b->ctx && masses && b_dev && x_dev && st, KS_ERR_ARG,
                "ks_batch_solve: null argument");
     check_params(p);
-    return batch_solve(*b->ctx, masses, b_dev, x_dev, *p, st, stream);
+    const ks_status_t rc = batch_solve(*b->ctx, masses, b_dev, x_dev, *p, st, stream);
+    if (log_level() >= 1) {
+        int it = 0, worst = 0;
+        double res = 0.0, sec = 0.0;
+        for (int k = 0; k < b->ctx->npairs; ++k) {
+            it = std::max(it, st[k].iters);
+            res = std::max(res, st[k].true_rel_resid);
+            sec = std::max(sec, st[k].seconds);
+            if (st[k].status != 0 && worst == 0) worst = st[k].status;
+        }
+        log_msg(1, "batch: status %d, %d pairs, at most %d steps, largest residual %.3g, %.4f s",
+                worst ? worst : (int)rc, b->ctx->npairs, it, res, sec);
+    }
+    return rc;
     KS_API_END
 }
 
@@ -521,6 +568,33 @@ ks_status_t ks_net_get_weights(ks_net_t n, double* weights)
     KS_API_BEGIN
     KS_REQUIRE(n && n->ctx && weights, KS_ERR_ARG, "ks_net_get_weights: null argument");
     net_get_weights(*n->ctx, weights, nullptr);
+    return KS_SUCCESS;
+    KS_API_END
+}
+
+ks_status_t ks_net_get_state(ks_net_t n, double* weights, double* adam_m, double* adam_v,
+                             int* step)
+{
+    KS_API_BEGIN
+    KS_REQUIRE(n && n->ctx && weights && adam_m && adam_v && step, KS_ERR_ARG,
+               "ks_net_get_state: null argument");
+    net_get_state(*n->ctx, weights, adam_m, adam_v, step, nullptr);
+    return KS_SUCCESS;
+    KS_API_END
+}
+
+ks_status_t ks_net_set_state(ks_net_t n, const double* weights, const double* adam_m,
+                             const double* adam_v, int step)
+{
+    KS_API_BEGIN
+    KS_REQUIRE(n && n->ctx && weights && adam_m && adam_v, KS_ERR_ARG,
+               "ks_net_set_state: null argument");
+    KS_REQUIRE(step >= 0, KS_ERR_ARG, "ks_net_set_state: negative step count %d", step);
+    for (int k = 0; k < 2 * KS_NET_WEIGHTS; ++k)
+        KS_REQUIRE(std::isfinite(weights[k]) && std::isfinite(adam_m[k]) &&
+                       std::isfinite(adam_v[k]) && adam_v[k] >= 0.0,
+                   KS_ERR_ARG, "ks_net_set_state: entry %d is not finite (or a negative second moment)", k);
+    net_set_state(*n->ctx, weights, adam_m, adam_v, step, nullptr);
     return KS_SUCCESS;
     KS_API_END
 }
@@ -643,6 +717,7 @@ ks_status_t ks_fcg_solve(ks_gauge_t g, ks_net_t n, double mass, const double* b_
                                     local, stream);
     export_field(g->geom, KS_F64, w.x64, x_dev, stream);
     KS_HIP(hipStreamSynchronize(stream));
+    log_solve("fcg", rc, local);
     if (st) *st = local;
     return rc;
     KS_API_END

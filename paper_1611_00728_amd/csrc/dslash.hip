@@ -8,6 +8,12 @@
 // bytes); the 16 neighbour vectors are gathers that the XCD-aware tile order keeps inside
 // one XCD's L2 for most hops.
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <fstream>
+#include <mutex>
+#include <string>
+#include <unistd.h>
 #include <utility>
 #include <vector>
 
@@ -340,6 +346,113 @@ static float time_launches(ks_gauge_t g, ks_prec_t prec, int ri, const DslashArg
 // launches with HIP events on this lattice; the four fastest are then timed again over 20
 // launches each, twice in alternation, and the one with the best mean is kept for the handle
 // (a single short timing picks a lucky candidate too often).
+// ---------------------------------------------------------------- tuning cache
+// With the environment variable KS_TUNE_CACHE naming a file, a variant's configuration is
+// looked up there before any timing and recorded there after tuning.  One JSON object per
+// line, keyed by the device (architecture name, compute units), the lattice extents, the
+// precision and the Naik storage; lines the library cannot read are kept as they are.
+namespace {
+
+std::mutex g_cache_mu;
+
+struct CacheKey {
+    std::string arch;
+    int cus;
+    int dims[4];
+    int prec;
+    int naik;
+};
+
+std::string cache_line(const CacheKey& k, const TuneEntry& t)
+{
+    char b[512];
+    std::snprintf(b, sizeof(b),
+                  "{\"arch\": \"%s\", \"cus\": %d, \"dims\": [%d, %d, %d, %d], \"prec\": %d, "
+                  "\"naik\": %d, \"threads\": %d, \"lds_bytes\": %d, \"links_per_pass\": %d, "
+                  "\"link_access\": %d, \"staged\": %d, \"us\": %.2f}",
+                  k.arch.c_str(), k.cus, k.dims[0], k.dims[1], k.dims[2], k.dims[3], k.prec, k.naik,
+                  t.nt, t.lds, t.group, t.way, t.staged, (double)t.us);
+    return b;
+}
+
+bool parse_line(const std::string& line, CacheKey& k, TuneEntry& t)
+{
+    char arch[64];
+    float us = 0.f;
+    const int n = std::sscanf(
+        line.c_str(),
+        "{\"arch\": \"%63[^\"]\", \"cus\": %d, \"dims\": [%d, %d, %d, %d], \"prec\": %d, "
+        "\"naik\": %d, \"threads\": %d, \"lds_bytes\": %d, \"links_per_pass\": %d, "
+        "\"link_access\": %d, \"staged\": %d, \"us\": %f}",
+        arch, &k.cus, &k.dims[0], &k.dims[1], &k.dims[2], &k.dims[3], &k.prec, &k.naik, &t.nt,
+        &t.lds, &t.group, &t.way, &t.staged, &us);
+    if (n != 14) return false;
+    k.arch = arch;
+    t.us = us;
+    return true;
+}
+
+bool same_key(const CacheKey& a, const CacheKey& b)
+{
+    return a.arch == b.arch && a.cus == b.cus && a.dims[0] == b.dims[0] && a.dims[1] == b.dims[1] &&
+           a.dims[2] == b.dims[2] && a.dims[3] == b.dims[3] && a.prec == b.prec &&
+           a.naik == b.naik;
+}
+
+std::vector<std::string> cache_lines(const char* path)
+{
+    std::vector<std::string> out;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line))
+        if (!line.empty()) out.push_back(line);
+    return out;
+}
+
+bool cache_lookup(const char* path, const CacheKey& key, TuneEntry& t)
+{
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    bool found = false;
+    for (const std::string& line : cache_lines(path)) {
+        CacheKey k;
+        TuneEntry e;
+        if (parse_line(line, k, e) && same_key(k, key)) {
+            t = e;
+            found = true;   // the last entry of a key wins
+        }
+    }
+    return found;
+}
+
+// Replaces the key's entry (or appends it) through a temporary file renamed over the cache,
+// so that a reader never sees a half-written file.  Failures are reported, not fatal.
+void cache_store(const char* path, const CacheKey& key, const TuneEntry& t)
+{
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    std::vector<std::string> keep;
+    for (const std::string& line : cache_lines(path)) {
+        CacheKey k;
+        TuneEntry e;
+        if (!(parse_line(line, k, e) && same_key(k, key))) keep.push_back(line);
+    }
+    keep.push_back(cache_line(key, t));
+    const std::string tmp = std::string(path) + ".tmp" + std::to_string((long)getpid());
+    {
+        std::ofstream f(tmp, std::ios::trunc);
+        for (const std::string& line : keep) f << line << '\n';
+        if (!f) {
+            log_msg(1, "tuning cache %s: cannot write %s", path, tmp.c_str());
+            return;
+        }
+    }
+    if (std::rename(tmp.c_str(), path) != 0) {
+        log_msg(1, "tuning cache %s: cannot replace it", path);
+        std::remove(tmp.c_str());
+    }
+}
+
+}  // namespace
+
 void dslash_tune(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, hipStream_t s)
 {
     const int ri = recon_index(recon);
@@ -353,6 +466,27 @@ void dslash_tune(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, hipStream_t s)
                             : 65536L;
     const long lds_blk = (long)prop.sharedMemPerBlock;
     const Geom& G = g->geom;
+    const int naik = ri ? 12 : 18;
+    const char* cache = std::getenv("KS_TUNE_CACHE");
+    const CacheKey key{prop.gcnArchName, prop.multiProcessorCount,
+                       {G.n[0], G.n[1], G.n[2], G.n[3]}, (int)prec, naik};
+    if (cache && *cache) {
+        TuneEntry t;
+        const bool hit = cache_lookup(cache, key, t);
+        const bool usable = hit && (t.nt == 64 || t.nt == 128 || t.nt == 256) &&
+                            (t.way == 4 || t.way == 8) && (t.staged == 0 || t.staged == 1) &&
+                            t.lds >= 0 && t.lds <= lds_blk &&
+                            form_built((int)prec, naik, t.group, t.way == 4, t.staged != 0);
+        log_msg(2, "tuning cache %s: %s for %s %d-real %dx%dx%dx%d", cache,
+                usable ? "hit" : hit ? "unusable entry" : "miss",
+                prec == KS_F64 ? "FP64" : prec == KS_F32 ? "FP32" : "FP16", naik, G.n[0], G.n[1],
+                G.n[2], G.n[3]);
+        if (usable) {
+            t.tuned = true;
+            g->tune[prec][ri] = t;
+            return;
+        }
+    }
     const size_t fb = field_bytes(G, prec);
     void* in = device_alloc(fb);
     void* out = nullptr;
@@ -372,8 +506,7 @@ void dslash_tune(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, hipStream_t s)
         for (int staged : {0, 1}) {
         for (int way : {8, 4}) {
         for (int group : {1, 2, 4}) {
-        const int rc = ri ? 12 : 18;
-        if (!form_built((int)prec, rc, group, way == 4, staged != 0)) continue;
+        if (!form_built((int)prec, naik, group, way == 4, staged != 0)) continue;
         for (int nt : {64, 128, 256}) {
             for (int blocks_cu : {0, 2, 3, 4, 5, 6, 8, 10, 12, 16, 20, 24, 32}) {
                 TuneEntry t;
@@ -423,6 +556,12 @@ void dslash_tune(ks_gauge_t g, ks_prec_t prec, ks_recon_t recon, hipStream_t s)
     best.us = best_us;
     best.tuned = true;
     g->tune[prec][ri] = best;
+    log_msg(1, "tuned %s %d-real Dslash at %dx%dx%dx%d: %d threads, %d links per pass, %d-way, "
+               "%s gathers, %d B LDS, %.1f us",
+            prec == KS_F64 ? "FP64" : prec == KS_F32 ? "FP32" : "FP16", naik, G.n[0], G.n[1],
+            G.n[2], G.n[3], best.nt, best.group, best.way, best.staged ? "staged" : "cached",
+            best.lds, (double)best_us);
+    if (cache && *cache) cache_store(cache, key, best);
 }
 
 }  // namespace ks

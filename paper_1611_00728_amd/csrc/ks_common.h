@@ -16,6 +16,12 @@ namespace ks {
 
 void set_error(const char* fmt, ...);
 
+// Diagnostics on stderr, one line each prefixed "[ks]", when the environment variable KS_LOG
+// holds a level >= `level` (read once per process; unset or 0: silent).  1: every solve's
+// summary, tuning results and returned errors; 2: also the tuner's cache decisions.
+int log_level();
+void log_msg(int level, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+
 struct Failure {
     ks_status_t code;
 };

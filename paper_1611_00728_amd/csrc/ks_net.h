@@ -53,6 +53,10 @@ NetCtx* net_create(const double* w_host);
 void net_free(NetCtx* n);
 void net_set_weights(NetCtx& n, const double* w_host, hipStream_t s);
 void net_get_weights(NetCtx& n, double* w_host, hipStream_t s);
+// the free weights, Adam's moments and step count (host arrays of 2 * kNetWeights reals each)
+void net_get_state(NetCtx& n, double* w, double* m, double* v, int* step, hipStream_t s);
+void net_set_state(NetCtx& n, const double* w, const double* m, const double* v, int step,
+                   hipStream_t s);
 NetBuffers& net_buffers(NetCtx& n, const Geom& g);
 void net_forward(NetCtx& n, NetBuffers& B, ks_gauge_t g, hipStream_t s);
 void net_apply_f32(NetCtx& n, ks_gauge_t g, const double* in, double* out, double in_scale,

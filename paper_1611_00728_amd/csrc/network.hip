@@ -594,6 +594,29 @@ void net_get_weights(NetCtx& n, double* w_host, hipStream_t s)
     KS_HIP(hipStreamSynchronize(s));
 }
 
+void net_get_state(NetCtx& n, double* w, double* m, double* v, int* step, hipStream_t s)
+{
+    const size_t nb = sizeof(double) * 2 * kNetWeights;
+    KS_HIP(hipMemcpyAsync(w, n.w64, nb, hipMemcpyDeviceToHost, s));
+    KS_HIP(hipMemcpyAsync(m, n.adam_m, nb, hipMemcpyDeviceToHost, s));
+    KS_HIP(hipMemcpyAsync(v, n.adam_v, nb, hipMemcpyDeviceToHost, s));
+    KS_HIP(hipStreamSynchronize(s));
+    *step = n.step;
+}
+
+void net_set_state(NetCtx& n, const double* w, const double* m, const double* v, int step,
+                   hipStream_t s)
+{
+    const size_t nb = sizeof(double) * 2 * kNetWeights;
+    KS_HIP(hipMemcpyAsync(n.w64, w, nb, hipMemcpyHostToDevice, s));
+    KS_HIP(hipMemcpyAsync(n.adam_m, m, nb, hipMemcpyHostToDevice, s));
+    KS_HIP(hipMemcpyAsync(n.adam_v, v, nb, hipMemcpyHostToDevice, s));
+    expand_weights(n, s);
+    KS_HIP(hipStreamSynchronize(s));
+    n.step = step;
+    n.version += 1;
+}
+
 // Forward through the four layers, input already in act[0]; activations of every layer kept.
 void net_forward(NetCtx& n, NetBuffers& B, ks_gauge_t g, hipStream_t s)
 {

@@ -88,3 +88,31 @@ def test_cg_coefficients_argument_checks(libks):
     assert libks.ks_cg_coefficients(None, 0, None, None, ctypes.byref(n)) == -1
     assert libks.ks_cg_coefficients(ctypes.c_void_p(16), -1, None, None, ctypes.byref(n)) == -1
     assert libks.ks_cg_coefficients(ctypes.c_void_p(16), 4, None, None, ctypes.byref(n)) == -1
+
+
+def _run_with_log(level):
+    import subprocess
+    import sys
+    code = ("import ctypes as C, sys; sys.path.insert(0, %r)\n"
+            "import paper_1611_00728_amd as ks\n"
+            "L = ks.lib()\n"
+            "p = ks.default_params()\n"
+            "rc = L.ks_cg_solve(None, C.c_double(0.1), None, None, C.byref(p), None, None)\n"
+            "print('rc', rc)\n") % ROOT
+    env = dict(os.environ)
+    env.pop("KS_LOG", None)
+    if level is not None:
+        env["KS_LOG"] = str(level)
+    return subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                          timeout=120)
+
+
+def test_ks_log_reports_errors(libks):
+    """KS_LOG = 1: a failing call prints its entry point, code and message on stderr, prefixed
+    "[ks]"; without KS_LOG (or at 0) the library prints nothing."""
+    on = _run_with_log(1)
+    assert on.returncode == 0 and "rc -1" in on.stdout
+    assert "[ks] ks_cg_solve: error -1: ks_cg_solve: null argument" in on.stderr
+    for level in (None, 0):
+        off = _run_with_log(level)
+        assert off.returncode == 0 and "rc -1" in off.stdout and "[ks]" not in off.stderr

@@ -257,3 +257,51 @@ def test_dslash_full_size_32(ks, lat32, prec, recon):
                 del r, S
     finally:
         G.set_config(P, recon, 256, 0, 1, 8, 0)
+
+
+def test_tune_cache(ks, tmp_path, monkeypatch):
+    """KS_TUNE_CACHE: tuning records the variant's configuration in the file; a new handle on
+    the same lattice takes an entry from there as written (an edited one included) and its
+    Dslash still equals the oracle's; an unusable entry is tuned again and replaced; entries of
+    other variants and lines the library cannot read are kept."""
+    import json
+    announce("tune cache")
+    path = tmp_path / "tune.jsonl"
+    path.write_text("not an entry\n")
+    monkeypatch.setenv("KS_TUNE_CACHE", str(path))
+    dims = (8, 8, 8, 8)
+    g = make_gauge(dims, 0.5, 3)
+    vh = g.volume // 2
+    G1 = ks.Gauge(dims, g.fat, g.naik)
+    c1 = G1.tune(ks.F64, 18)
+    lines = path.read_text().splitlines()
+    assert len(lines) == 2 and lines[0] == "not an entry"
+    e = json.loads(lines[1])
+    assert e["dims"] == list(dims) and e["prec"] == 0 and e["naik"] == 18
+    assert [e[k] for k in ("threads", "lds_bytes", "links_per_pass", "link_access", "staged")] == \
+        [c1[k] for k in ("threads", "lds_bytes", "links_per_pass", "link_access", "staged")]
+    # an entry edited to another built form is taken as written, without timing
+    e.update(threads=128, lds_bytes=0, links_per_pass=1, link_access=4, staged=0, us=12.5)
+    path.write_text(lines[0] + "\n" + json.dumps(e) + "\n")
+    G2 = ks.Gauge(dims, g.fat, g.naik)
+    c2 = G2.tune(ks.F64, 18)
+    assert (c2["threads"], c2["link_access"], c2["links_per_pass"], c2["staged"]) == (128, 4, 1, 0)
+    assert c2["tuned_us"] == pytest.approx(12.5)
+    psi = gaussian_source(vh, 808)
+    got = run_dslash(ks, G2, vh, 0, psi, ks.F64, 18)
+    assert rel_l2(got, oracle.dslash_eo(g, 0, psi)) <= 1e-12
+    # an unusable entry (96 threads) is tuned again and replaced
+    e.update(threads=96)
+    path.write_text(lines[0] + "\n" + json.dumps(e) + "\n")
+    G3 = ks.Gauge(dims, g.fat, g.naik)
+    c3 = G3.tune(ks.F64, 18)
+    assert c3["threads"] in (64, 128, 256)
+    lines = path.read_text().splitlines()
+    assert len(lines) == 2 and lines[0] == "not an entry"
+    assert json.loads(lines[1])["threads"] == c3["threads"]
+    # another variant is added beside it
+    G3.tune(ks.F32, 18)
+    lines = path.read_text().splitlines()
+    assert len(lines) == 3 and sorted(json.loads(x)["prec"] for x in lines[1:]) == [0, 1]
+    for G in (G1, G2, G3):
+        G.free()

@@ -241,6 +241,41 @@ def test_training_reduces_loss(ks, lat):
     net.free()
 
 
+def test_checkpoint_resumes_training(ks, lat, tmp_path):
+    """A checkpoint (weights, Adam moments, step count) taken after 10 Adam steps and restored
+    into a fresh network continues training exactly as the original does: 10 more steps give
+    the same loss history and the same weights bit for bit; a malformed state is refused."""
+    announce("net checkpoint")
+    G = ks.Gauge(lat.dims, lat.fat, lat.naik)
+    sigma = 4 * 0.05 ** 2
+    bs, xs = [], []
+    for j in range(4):
+        b = gaussian_source(lat.volume // 2, 700 + j)
+        x, _ = oracle.cg(lat, sigma, b, 1e-12)
+        bs.append(dev(b))
+        xs.append(dev(x))
+    args = ([G] * 4, [sigma] * 4, bs, xs)
+    a = ks.Net(flatten_weights(net_init_weights(5000)))
+    a.train(*args, steps=10, batch=2, lr=3e-3)
+    path = tmp_path / "net.ckpt"
+    a.save(path)
+    w, m, v, step = ks.read_checkpoint(path)
+    assert step == 10 and np.any(m != 0) and np.all(v >= 0)
+    ha = a.train(*args, steps=10, batch=2, lr=3e-3)
+    b2 = ks.Net(flatten_weights(net_init_weights(6000))).load(path)
+    hb = b2.train(*args, steps=10, batch=2, lr=3e-3)
+    assert np.array_equal(ha, hb)
+    assert np.array_equal(a.get_weights(), b2.get_weights())
+    assert a.get_state()[3] == b2.get_state()[3] == 20
+    with pytest.raises(ks.KSError):
+        b2.set_state(w, m, -np.abs(v) - 1.0, 3)
+    with pytest.raises(ks.KSError):
+        b2.set_state(w, m, v, -1)
+    a.free()
+    b2.free()
+    G.free()
+
+
 def test_batched_training_pairs(ks):
     """Training pairs from blocks cut out of a larger lattice, solved together by the batched
     FP64 CG: every x solves its own block's system to the oracle's FP64 residual, and the pair

@@ -363,3 +363,31 @@ def test_full_solve_special_cases(ks, cfg1):
     with pytest.raises(ks.KSError) as e:
         ks.full_solve(G, 0.0, dev(b), dev(z), xe, xod)
     assert e.value.code == -1
+
+
+def test_ks_log_solve_summary(ks):
+    """KS_LOG = 1: a tuning prints its result and a solve one summary line with its status,
+    steps and FP64 residual (in a child process, whose environment sets the level)."""
+    import os
+    import subprocess
+    import sys
+    announce("KS_LOG solve summary")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "import torch, paper_1611_00728_amd as ks\n"
+            "from ksinputs import make_gauge, gaussian_source\n"
+            "g = make_gauge((4, 4, 4, 8), 0.5, 5)\n"
+            "G = ks.Gauge(g.dims, g.fat, g.naik)\n"
+            "G.tune(ks.F32, 18)\n"
+            "b = torch.from_numpy(gaussian_source(g.volume // 2, 6)).cuda()\n"
+            "x = torch.zeros_like(b)\n"
+            "r = ks.cg_solve(G, 0.1, b, x, ks.default_params(tol=1e-10, inner=ks.F32))\n"
+            "print('iters', r.stats['iters'])\n") % root
+    env = dict(os.environ, KS_LOG="1")
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                         timeout=110)
+    assert out.returncode == 0, out.stderr[-2000:]
+    iters = int(out.stdout.split("iters")[1])
+    assert "[ks] tuned FP32 18-real Dslash at 4x4x4x8:" in out.stderr
+    line = [l for l in out.stderr.splitlines() if l.startswith("[ks] cg: ")]
+    assert len(line) == 1 and line[0].startswith("[ks] cg: status 0, %d steps," % iters)
