@@ -360,6 +360,51 @@ def learned48(args):
     print(json.dumps(config5(g5, blocks)), flush=True)
 
 
+def multishift_workload(args):
+    """The multi-shift workload alone: 32^3 x 48 (thin-link scale 0.5), nine shifts
+    sigma_i = 4 m_i^2 with m_i log-spaced over [0.002, 0.5], per-shift target 1e-9; FP64, FP32 and
+    FP16 inner with 18-real Naik, each variant tuned first, `--warmup` untimed and `--steps`
+    timed solves.  One JSON line (seconds per solve, steps per shift, largest GPU residual)."""
+    import numpy as np
+    import torch
+    import paper_1611_00728_amd as ks
+    from ksinputs import make_gauge, gaussian_source, SEEDS
+    dims = (32, 32, 32, 48)
+    g = make_gauge(dims, 0.5, SEEDS["gauge"](3))
+    b_h = gaussian_source(g.volume // 2, SEEDS["source"](3))
+    torch.cuda.set_device(0)
+    G = ks.Gauge(dims, g.fat, g.naik)
+    del g
+    b = torch.from_numpy(b_h).cuda()
+    sig = 4 * np.geomspace(0.002, 0.5, 9) ** 2
+    xs = [torch.zeros_like(b) for _ in sig]
+    rows = {}
+    for name, p_ in (("f64", ks.F64), ("f32", ks.F32), ("f16", ks.F16)):
+        G.prepare(p_, 18)
+        G.tune(p_, 18)
+        times = []
+        for k in range(args.warmup + args.steps):
+            torch.cuda.synchronize()
+            time.sleep(0.05)   # an idle gap that marks the solve's start in a kernel trace
+            t = time.perf_counter()
+            rc, st = ks.multishift_cg_solve(G, sig, b, xs, 1e-9,
+                                            ks.default_params(inner=p_, check_every=16))
+            torch.cuda.synchronize()
+            if k >= args.warmup:
+                times.append(time.perf_counter() - t)
+        torch.cuda.synchronize()
+        time.sleep(0.05)   # and its end, before the next variant's set-up
+        rows[name] = {"seconds": float(np.median(times)), "solves": len(times),
+                      "iters_per_shift": [x["iters"] for x in st],
+                      "reliable_updates_per_shift": [x["reliable_updates"] for x in st],
+                      "max_true_rel_resid_gpu": max(x["true_rel_resid"] for x in st)}
+        log("multishift %s: %.4f s" % (name, rows[name]["seconds"]))
+    print(json.dumps({"workload": "multi-shift CG, 32^3x48, 9 shifts, tol 1e-9",
+                      "lattice": list(dims), "shifts": [float(x) for x in sig],
+                      "variants": rows}), flush=True)
+    G.free()
+
+
 def sweep(args):
     """Dslash_eo bandwidth over lattice sizes (L^4 for L = 8 ... 48 and the paper's 20^3 x 64 and
     24^3 x 60), every precision and Naik storage, each variant autotuned per lattice; and the
@@ -531,10 +576,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned48", action="store_true",
                     help="skip the 48^3 x 64 learned-preconditioner workload after the steps")
-    ap.add_argument("--workload", default="default", choices=["default", "learned48", "sweep"],
+    ap.add_argument("--workload", default="default",
+                    choices=["default", "learned48", "sweep", "multishift"],
                     help="learned48: the 48^3 x 64, m = 0.002 learned-preconditioner workload "
                          "(training pairs, training, flexible CG vs mixed CG); sweep: Dslash_eo "
-                         "over lattice sizes and the oracle's host timings; each its own JSON line")
+                         "over lattice sizes and the oracle's host timings; multishift: the "
+                         "32^3 x 48 multi-shift solves alone (FP64, FP32, FP16 inner, --steps "
+                         "timed solves each); each its own JSON line")
     ap.add_argument("--counters", type=int, default=0, metavar="N",
                     help="counter runs: one plain 1 GiB device copy (calibration), N launches "
                          "of each tuned Dslash_eo variant, then N steps or launches of each "
@@ -556,6 +604,9 @@ def main():
         import torch
         torch.cuda.set_device(0)
         sweep(args)
+        return
+    if args.workload == "multishift":
+        multishift_workload(args)
         return
     # every input is generated before the GPU is touched: large fields are computed by forked
     # worker processes
