@@ -116,3 +116,12 @@ def test_ks_log_reports_errors(libks):
     for level in (None, 0):
         off = _run_with_log(level)
         assert off.returncode == 0 and "rc -1" in off.stdout and "[ks]" not in off.stderr
+
+
+def test_net_state_argument_checks(libks):
+    """The training-state entry points refuse null handles and buffers before any device work."""
+    w = (C.c_double * 4)()
+    step = C.c_int()
+    assert libks.ks_net_get_state(None, w, w, w, C.byref(step)) == -1
+    assert libks.ks_net_set_state(None, w, w, w, 0) == -1
+    assert b"null" in libks.ks_last_error()
