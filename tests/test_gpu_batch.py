@@ -132,10 +132,14 @@ def test_batch_runs_are_bit_identical(ks, fields, inner):
     B.free()
 
 
-def test_batch_zero_rhs_and_max_iter(ks, fields):
-    announce("batch edge cases")
+@pytest.mark.parametrize("inner", ["f32", "f16"])
+def test_batch_zero_rhs_and_max_iter(ks, fields, inner):
+    """A zero right-hand side finishes at once with x = 0 (binary16: all-zero records); a pair
+    started from its own solution finishes in its first (FP64) check; a step cap returns
+    KS_ERR_NOT_CONVERGED with the residual of the returned x."""
+    announce("batch edge cases", inner)
     gs, masses = fields
-    B = ks.Batch([gs[0].dims], [gs[0].fat], [gs[0].naik], 2, ks.F32)
+    B = ks.Batch([gs[0].dims], [gs[0].fat], [gs[0].naik], 2, ks.PREC[inner])
     import torch
     b = gaussian_source(gs[0].volume // 2, 7)
     bs = [dev(np.zeros_like(b)), dev(b)]
@@ -143,6 +147,12 @@ def test_batch_zero_rhs_and_max_iter(ks, fields):
     rc, st = B.solve(masses[:1], bs, xs, ks.default_params(tol=1e-10), raise_on_error=False)
     torch.cuda.synchronize()
     assert rc == 0 and np.all(host(xs[0]) == 0) and st[0]["iters"] == 0
+    assert true_rel(gs[0], 4 * masses[0] ** 2, b, host(xs[1])) <= 1e-10
+    # restarted from its solution: no step, and x unchanged up to the FP64 check
+    x1 = host(xs[1])
+    rc, st = B.solve(masses[:1], bs, xs, ks.default_params(tol=1e-10), raise_on_error=False)
+    torch.cuda.synchronize()
+    assert rc == 0 and st[1]["iters"] == 0 and np.array_equal(host(xs[1]), x1)
     xs = [zeros_dev(b.shape), zeros_dev(b.shape)]
     rc, st = B.solve(masses[:1], [dev(b), dev(b)], xs, ks.default_params(tol=1e-10, max_iter=3),
                      raise_on_error=False)
